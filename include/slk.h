@@ -1,0 +1,251 @@
+/*
+ * slk.h -- C ABI of libslk, an MI355X (gfx950) implementation of the bound-optimizer
+ * iteration of Scalable Laplacian K-modes (SLK-BO; Ziko, Granger, Ben Ayed, NeurIPS 2018).
+ *
+ * The calls follow the paper's problem statement: points X = {x_p in R^D} and a number
+ * of clusters L (Section 1, Eq. (1)); a Laplacian weight lambda (Eq. (1)); the Gaussian
+ * kernel k(x, y) = exp(-||x - y||^2 / (2 sigma^2)) and the binary kNN affinity with its
+ * sigma^2 estimator (Section 4.2); initial modes (Algorithm 1, input); outputs Z and the
+ * modes {m_l} (Algorithm 1, output).
+ *
+ * Conventions shared by every call:
+ *  - Pointers are DEVICE pointers unless the parameter name ends in `_host`.
+ *  - Arrays are dense, row-major, contiguous: X is n x d float32, Z is n x L float32,
+ *    labels are n int32, kNN lists are n x k.
+ *  - Point indices (modes, labels' rows, kNN lists, CSR columns) are 0-based and always
+ *    in the caller's original point order; an internal locality permutation is hidden.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Work is stream-ordered.  A call
+ *    with a `_host` output synchronises `stream` before it returns; device outputs are
+ *    complete when the stream reaches the call's end.
+ *  - The caller owns every array it passes in; the library never frees caller memory.
+ *    Graph handles are owned by the library until slk_graph_destroy.  Temporary device
+ *    memory is taken from the stream-ordered allocator and returned before the call ends.
+ *  - Errors are returned as slk_status; no exception or abort crosses the ABI.  Arguments
+ *    are validated before any launch; on a non-OK status the outputs are unspecified and
+ *    slk_last_error() describes the failure (thread-local text, valid until the next call
+ *    on the same thread).
+ *  - Results are deterministic: the same inputs and parameters give bit-identical
+ *    outputs (all reductions run in a fixed order).
+ *  - Limits: 2 <= n < 2^31, d >= 1, 1 <= k <= 64, 1 <= L <= 256, total CSR entries < 2^31.
+ */
+#ifndef SLK_H_
+#define SLK_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SLK_OK = 0,
+  SLK_ERR_INVALID_ARG = 1,   /* a size, pointer or parameter is out of range          */
+  SLK_ERR_OUT_OF_MEMORY = 2, /* a device or pinned host allocation failed             */
+  SLK_ERR_DEVICE = 3,        /* a HIP runtime call or kernel launch failed            */
+  SLK_ERR_NUMERIC = 4,       /* the relaxed bound became NaN or infinite              */
+  SLK_ERR_UNSUPPORTED = 5    /* a valid request this build does not implement          */
+} slk_status;
+
+/* Precision of the points used by the distance computations. */
+typedef enum {
+  SLK_PREC_FP32 = 0, /* X as given (float32)                                            */
+  SLK_PREC_BF16 = 1  /* X rounded to bfloat16 once; all distances use the rounded points */
+} slk_precision;
+
+/* Candidate search used by slk_build_knn. */
+typedef enum {
+  SLK_KNN_AUTO = 0,  /* exact FP64 brute force for small n*n*d, else MFMA candidates     */
+  SLK_KNN_EXACT = 1, /* every distance in FP64                                           */
+  SLK_KNN_MFMA = 2   /* bf16 MFMA Gram candidates + FP64 re-rank + certificate           */
+} slk_knn_method;
+
+typedef struct slk_graph slk_graph; /* opaque: device-resident kNN lists, CSR, sigma^2 */
+
+typedef struct {
+  int32_t k;          /* k_n, neighbours per point (Section 4.2); 1 <= k <= 64, k < n      */
+  int32_t reorder;    /* 1: relabel points internally for neighbour locality (BFS order)   */
+  int32_t candidates; /* MFMA path: candidates kept per row before the exact re-rank
+                         (0 = automatic; clamped to [k, 256])                               */
+  slk_knn_method method;
+  slk_precision prec;
+} slk_knn_opts;
+
+typedef struct {
+  int64_t n;
+  int32_t k;            /* 0 for a graph imported from CSR                                 */
+  int32_t reordered;    /* 1 if an internal locality permutation is in use                 */
+  int64_t nnz;          /* stored CSR entries (ordered pairs)                               */
+  int32_t max_degree;
+  int32_t min_degree;
+  double sigma2;        /* kNN bandwidth estimate (<= 0 if unknown, e.g. CSR import)       */
+  int64_t rows_certified;  /* MFMA path: rows whose top-k the error bound certified        */
+  int64_t rows_fallback;   /* MFMA path: rows recomputed by the exact FP64 search          */
+} slk_graph_info_t;
+
+/* Fill *opts with defaults: k = 10, reorder = 0, candidates = 0, AUTO, FP32. */
+slk_status slk_knn_opts_default(slk_knn_opts* opts);
+
+/*
+ * Build the kNN affinity of Section 4.2 from the points.
+ *  x      : n x d float32 points (device).
+ *  For every p the k nearest q != p under the Euclidean distance are found, ordered by
+ *  (squared distance, index) -- ties go to the smaller index.  The reported squared
+ *  distances are the FP64 sum over j = 0..d-1, in order, of (x_pj - x_qj)^2 with every
+ *  subtraction, square and addition rounded separately.  The binary affinity
+ *  w_pq = 1 iff q in N_p or p in N_q (no self-loops) is stored as CSR, and
+ *  sigma^2 = (1 / (n k)) sum_p sum_{q in N_p} ||x_p - x_q||^2  (Section 4.2).
+ *  On success *g_out receives a new handle (release with slk_graph_destroy).
+ *  Synchronises `stream`.
+ */
+slk_status slk_build_knn(const float* x, int64_t n, int32_t d, const slk_knn_opts* opts,
+                         void* stream, slk_graph** g_out);
+
+/*
+ * Build the graph from given kNN lists (device): knn_idx n x k int32 (original indices,
+ * each row free of p itself), knn_d2 n x k float64 (their squared distances, used only
+ * for sigma^2; may be NULL, then sigma^2 is unknown).  Same symmetrisation as above.
+ * Synchronises `stream`.
+ */
+slk_status slk_graph_from_knn(int64_t n, int32_t k, const int32_t* knn_idx, const double* knn_d2,
+                              int32_t reorder, void* stream, slk_graph** g_out);
+
+/*
+ * Import a binary affinity given as CSR (device arrays): row_ptr n+1 int32 (row_ptr[0] = 0,
+ * non-decreasing, row_ptr[n] = nnz), col_idx nnz int32 in [0, n).  The matrix should be
+ * symmetric for the bound of Proposition 1 to hold; it is used as given (duplicates count
+ * twice, self-loops act as a diagonal shift).  sigma2_hint is stored as the graph's sigma^2
+ * (<= 0 = unknown).  The arrays are copied.  Synchronises `stream`.
+ */
+slk_status slk_graph_from_csr(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                              double sigma2_hint, int32_t reorder, void* stream, slk_graph** g_out);
+
+/* Sizes and statistics of a graph (host struct). */
+slk_status slk_graph_info(const slk_graph* g, slk_graph_info_t* info_host);
+
+/*
+ * Copy the graph out, in the original point order (device outputs, any may be NULL):
+ * row_ptr n+1 int32, col_idx nnz int32 (columns sorted within each row), knn_idx n x k int32,
+ * knn_d2 n x k float64 (kNN outputs need a graph built from points or kNN lists).
+ * perm n int32: perm[i] = original index of internal row i (identity if not reordered).
+ * Synchronises `stream`.
+ */
+slk_status slk_graph_export(const slk_graph* g, int32_t* row_ptr, int32_t* col_idx, int32_t* knn_idx,
+                            double* knn_d2, int32_t* perm, void* stream);
+
+void slk_graph_destroy(slk_graph* g);
+
+typedef struct {
+  double lambda;          /* Laplacian weight (Eq. (1)); >= 0                                   */
+  double sigma2;          /* Gaussian bandwidth; <= 0 uses the graph's estimate (Section 4.2)   */
+  double delta;           /* diagonal shift K + delta I (footnote to Proposition 1); >= 0       */
+  double bound_tol;       /* inner stop: |R(Z^{i+1}) - R(Z^i)| <= tol |R(Z^i)|                  */
+  int32_t max_outer;      /* cap on mode updates (Algorithm 1, outer loop)                      */
+  int32_t max_inner;      /* cap on z-updates per outer iteration                               */
+  int32_t fixed_inner;    /* > 0: run exactly this many z-updates, no convergence test          */
+  int32_t pairwise_scale; /* 1: z = softmax(a + lambda b) as in Eq. (8); 2: softmax(a + 2 lambda b),
+                             the exact minimiser for Eq. (2) as printed                          */
+  slk_precision prec;     /* precision of X in the unary distances                              */
+  int32_t reserved;
+} slk_params;
+
+typedef struct {
+  int32_t outer_iters;        /* outer iterations run                                       */
+  int32_t inner_iters_total;  /* z-updates run over all outer iterations                    */
+  int32_t inner_iters_last;   /* z-updates of the last outer iteration                      */
+  int32_t converged;          /* fit: modes unchanged; assign: bound settled (or fixed count) */
+  int32_t n_distinct_modes;
+  int32_t reserved;
+  double energy;              /* E(l, M) of Eq. (1) at the hard labels, unary term from FP32 A  */
+  double energy_fp64;         /* the same with the unary term recomputed in FP64 from X         */
+  double bound;               /* relaxed bound R(Z^i) of the last z-update's input              */
+  int64_t cut;                /* ordered neighbour pairs with different labels                  */
+} slk_result;
+
+/* Fill *p with defaults: lambda 1, sigma2 0 (graph), delta 0, tol 1e-8, max_outer 20,
+   max_inner 1000, fixed_inner 0, pairwise_scale 1, FP32. */
+slk_status slk_params_default(slk_params* p);
+
+/*
+ * One outer iteration of Algorithm 1 with the modes fixed (its z-update block):
+ *   a_pl = k(x_p, m_l)                                  (Eq. (6a))
+ *   z_p^0 = softmax(a_p)                                (Algorithm 1, initialisation)
+ *   repeat: b_p = sum_q w_pq z_q^i (+ delta z_p^i)      (Eq. (6b))
+ *           z_p^{i+1} = softmax(a_p + lambda b_p)       (Eq. (8)), all p in parallel
+ *   until the relaxed bound settles (see slk_params.bound_tol) or max_inner/fixed_inner.
+ *   Then: labels l_p = argmax_l (a_p + lambda b_p)_l (ties to the smaller l) and the
+ *   byproduct modes m_l = x_q, q = argmax_q z_ql (Eq. (11)), ranked by the log-odds
+ *   log(z_ql / (1 - z_ql)) computed from the logits, ties to the smaller index.
+ *  x            : n x d float32 (device), the points the graph was built on.
+ *  modes_host   : L distinct int32 point indices (host).
+ *  z_out        : n x L float32 (device) receives the last z-update.
+ *  labels_out   : n int32 (device, may be NULL).
+ *  modes_next_host : L int32 (host, may be NULL) receives the byproduct modes.
+ *  bound_trace_host : (host, may be NULL) receives the relaxed bound R(Z^i) of every
+ *                 z-update, up to trace_cap values.
+ *  res_host     : summary (host, may be NULL).  Synchronises `stream`.
+ */
+slk_status slk_assign(const float* x, int64_t n, int32_t d, const slk_graph* g, int32_t L,
+                      const int32_t* modes_host, const slk_params* p, void* stream, float* z_out,
+                      int32_t* labels_out, int32_t* modes_next_host, double* bound_trace_host,
+                      int32_t trace_cap, slk_result* res_host);
+
+/*
+ * SLK-BO (Algorithm 1): alternate slk_assign's z-update block with the byproduct mode
+ * update until the modes do not change (Section 3) or max_outer.  Z restarts from
+ * softmax(a) in every outer iteration, as in Algorithm 1.
+ *  init_modes_host : L distinct int32 indices (host).
+ *  z_out, labels_out : as in slk_assign, for the last outer iteration.
+ *  modes_out_host  : L int32 (host) final modes.
+ *  res_host        : summary (host, may be NULL); energy is E(l, M) at the last labels and
+ *                    the modes that produced them.  Synchronises `stream`.
+ */
+slk_status slk_fit(const float* x, int64_t n, int32_t d, const slk_graph* g, int32_t L,
+                   const int32_t* init_modes_host, const slk_params* p, void* stream, float* z_out,
+                   int32_t* labels_out, int32_t* modes_out_host, slk_result* res_host);
+
+typedef struct {
+  double energy;       /* E(l, M), Eq. (1) with Eq. (3), unary term from FP32 distances      */
+  double energy_fp64;  /* unary term recomputed in FP64                                     */
+  double bound;        /* relaxed bound R(Z) if z was given, else 0                          */
+  int64_t cut;         /* ordered pairs (p, q), w_pq = 1, l_p != l_q                          */
+} slk_energy_out;
+
+/*
+ * Discrete energy of Eq. (1) for hard labels (device, n int32 in [0, L)) and modes
+ * (host, L int32): E = -sum_p k(x_p, m_{l_p}) + lambda * cut.  If z (device, n x L) is
+ * given, also the relaxed bound  R(Z) = sum_p [z_p.log z_p - z_p.a_p - (lambda/2) z_p.b_p],
+ * b = (W + delta I) Z.  sigma2 <= 0 uses the graph's estimate.  Synchronises `stream`.
+ */
+slk_status slk_energy(const float* x, int64_t n, int32_t d, const slk_graph* g, int32_t L,
+                      const int32_t* labels, const float* z, const int32_t* modes_host, double lambda,
+                      double sigma2, double delta, void* stream, slk_energy_out* out_host);
+
+/*
+ * Unary affinities and the initial assignment for fixed modes (Eq. (6a), Algorithm 1):
+ * a_out[p, l] = k(x_p, x_{modes[l]}), z0_out = row softmax of a_out (device n x L float32;
+ * either may be NULL).  Asynchronous.
+ */
+slk_status slk_unary(const float* x, int64_t n, int32_t d, int32_t L, const int32_t* modes_host,
+                     double sigma2, slk_precision prec, void* stream, float* a_out, float* z0_out);
+
+/*
+ * One z-update from a given Z (Eqs. (6b), (8)) with a given unary matrix a (device n x L):
+ * z_out = softmax(a + scale*lambda*(W + delta I) z_in); bound_host receives R(z_in) with
+ * the factor scale*lambda/2 (host, may be NULL).  Synchronises `stream` if bound_host is
+ * given.
+ */
+slk_status slk_inner_step(const slk_graph* g, int32_t L, const float* a, const float* z_in, double lambda,
+                          double delta, int32_t pairwise_scale, void* stream, float* z_out,
+                          double* bound_host);
+
+/* Text for the last non-OK status returned on this thread. */
+const char* slk_last_error(void);
+
+/* Library version string. */
+const char* slk_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SLK_H_ */

@@ -1,0 +1,878 @@
+// The C ABI of libslk: argument validation, graph handles and the SLK-BO driver
+// (Algorithm 1: outer mode updates around inner z-updates).
+#include "common.h"
+
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+namespace slk {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+slk_status fail(slk_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+slk_status pinned(void** out, size_t bytes) {
+  thread_local void* buf = nullptr;
+  thread_local size_t cap = 0;
+  if (bytes > cap) {
+    if (buf) (void)hipHostFree(buf);
+    buf = nullptr;
+    cap = 0;
+    if (hipHostMalloc(&buf, bytes, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      buf = nullptr;
+      return fail(SLK_ERR_OUT_OF_MEMORY, "pinned host buffer");
+    }
+    cap = bytes;
+  }
+  *out = buf;
+  return SLK_OK;
+}
+
+// kernels local to this file ----------------------------------------------------------------
+namespace {
+
+__global__ void init_state_kernel(IterState* st, double tol, int check, int cap) {
+  st->pass = 0;
+  st->done = 0;
+  st->numeric = 0;
+  st->arrive = 0u;
+  st->tol = tol;
+  st->check = check;
+  st->trace_cap = cap;
+  st->last_bound = 0.0;
+}
+
+__global__ void check_indices_kernel(const int32_t* __restrict__ v, int64_t count, int64_t n, int32_t* bad) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    if (v[i] < 0 || v[i] >= n) atomicOr(bad, 1);
+}
+
+__global__ void check_row_ptr_kernel(const int32_t* __restrict__ rp, int64_t n, int64_t nnz, int32_t* bad) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    if (rp[i + 1] < rp[i]) atomicOr(bad, 1);
+    if (i == 0 && rp[0] != 0) atomicOr(bad, 1);
+    if (i == n - 1 && rp[n] != nnz) atomicOr(bad, 1);
+  }
+}
+
+__global__ void check_labels_kernel(const int32_t* __restrict__ v, int64_t n, int L, int32_t* bad) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    if (v[i] < 0 || v[i] >= L) atomicOr(bad, 1);
+}
+
+__global__ void check_finite_kernel(const float* __restrict__ v, int64_t count, int32_t* bad) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    if (!isfinite(v[i])) atomicOr(bad, 1);
+}
+
+__global__ void divide_kernel(double* v, double by) { *v = *v / by; }
+
+slk_status device_flag(hipStream_t s, const char* what, int (*launch)(int32_t*, hipStream_t, const void*),
+                       const void* ctx) {
+  Scratch sc(s);
+  int32_t* bad;
+  SLK_TRY(sc.get(&bad, 1));
+  SLK_HIP(hipMemsetAsync(bad, 0, sizeof(int32_t), s));
+  launch(bad, s, ctx);
+  SLK_LAUNCHED(what);
+  int32_t h = 0;
+  SLK_HIP(hipMemcpyAsync(&h, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  SLK_HIP(hipStreamSynchronize(s));
+  if (h) return fail(SLK_ERR_INVALID_ARG, std::string("invalid device data: ") + what);
+  return SLK_OK;
+}
+
+struct IdxCtx {
+  const int32_t* v;
+  int64_t count, n;
+};
+struct RpCtx {
+  const int32_t* rp;
+  int64_t n, nnz;
+};
+struct LabCtx {
+  const int32_t* v;
+  int64_t n;
+  int L;
+};
+struct FinCtx {
+  const float* v;
+  int64_t count;
+};
+
+inline unsigned grid_for(int64_t count) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((count + 255) / 256, 4096)); }
+
+slk_status check_indices(const int32_t* v, int64_t count, int64_t n, hipStream_t s, const char* what) {
+  IdxCtx c{v, count, n};
+  return device_flag(
+      s, what,
+      [](int32_t* bad, hipStream_t st, const void* p) {
+        auto* c = static_cast<const IdxCtx*>(p);
+        hipLaunchKernelGGL(check_indices_kernel, dim3(grid_for(c->count)), dim3(256), 0, st, c->v, c->count, c->n, bad);
+        return 0;
+      },
+      &c);
+}
+
+slk_status check_finite(const float* v, int64_t count, hipStream_t s) {
+  FinCtx c{v, count};
+  return device_flag(
+      s, "points must be finite",
+      [](int32_t* bad, hipStream_t st, const void* p) {
+        auto* c = static_cast<const FinCtx*>(p);
+        hipLaunchKernelGGL(check_finite_kernel, dim3(grid_for(c->count)), dim3(256), 0, st, c->v, c->count, bad);
+        return 0;
+      },
+      &c);
+}
+
+slk_status check_labels(const int32_t* v, int64_t n, int L, hipStream_t s) {
+  LabCtx c{v, n, L};
+  return device_flag(
+      s, "labels must lie in [0, L)",
+      [](int32_t* bad, hipStream_t st, const void* p) {
+        auto* c = static_cast<const LabCtx*>(p);
+        hipLaunchKernelGGL(check_labels_kernel, dim3(grid_for(c->n)), dim3(256), 0, st, c->v, c->n, c->L, bad);
+        return 0;
+      },
+      &c);
+}
+
+slk_status check_row_ptr(const int32_t* rp, int64_t n, int64_t nnz, hipStream_t s) {
+  RpCtx c{rp, n, nnz};
+  return device_flag(
+      s, "row_ptr must start at 0, be non-decreasing and end at nnz",
+      [](int32_t* bad, hipStream_t st, const void* p) {
+        auto* c = static_cast<const RpCtx*>(p);
+        hipLaunchKernelGGL(check_row_ptr_kernel, dim3(grid_for(c->n)), dim3(256), 0, st, c->rp, c->n, c->nnz, bad);
+        return 0;
+      },
+      &c);
+}
+
+// ------------------------------------------------------------------------------------------
+// graph helpers
+// ------------------------------------------------------------------------------------------
+void free_graph(slk_graph* g) {
+  if (!g) return;
+  (void)hipFree(g->row_ptr);
+  (void)hipFree(g->col_idx);
+  (void)hipFree(g->knn_idx);
+  (void)hipFree(g->knn_d2);
+  (void)hipFree(g->perm);
+  (void)hipFree(g->iperm);
+  delete g;
+}
+
+struct GraphGuard {
+  slk_graph* g;
+  ~GraphGuard() { free_graph(g); }
+  slk_graph* release() {
+    slk_graph* r = g;
+    g = nullptr;
+    return r;
+  }
+};
+
+// Breadth-first order of the graph, component by component (roots in increasing index
+// order), neighbours visited in CSR order.  Points that are neighbours end up close in the
+// internal numbering, so a z-update's neighbour reads stay within a narrow window of Z.
+slk_status bfs_reorder(slk_graph* g, hipStream_t s) {
+  const int64_t n = g->n;
+  std::vector<int32_t> rp(n + 1), ci(std::max<int64_t>(g->nnz, 1));
+  SLK_HIP(hipMemcpyAsync(rp.data(), g->row_ptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, s));
+  if (g->nnz) SLK_HIP(hipMemcpyAsync(ci.data(), g->col_idx, sizeof(int32_t) * g->nnz, hipMemcpyDeviceToHost, s));
+  SLK_HIP(hipStreamSynchronize(s));
+  std::vector<int32_t> order;
+  order.reserve(n);
+  std::vector<uint8_t> seen(n, 0);
+  for (int64_t root = 0; root < n; ++root) {
+    if (seen[root]) continue;
+    size_t head = order.size();
+    order.push_back((int32_t)root);
+    seen[root] = 1;
+    while (head < order.size()) {
+      const int32_t v = order[head++];
+      for (int32_t j = rp[v]; j < rp[v + 1]; ++j) {
+        const int32_t u = ci[j];
+        if (!seen[u]) {
+          seen[u] = 1;
+          order.push_back(u);
+        }
+      }
+    }
+  }
+  std::vector<int32_t> inv(n);
+  for (int64_t i = 0; i < n; ++i) inv[order[i]] = (int32_t)i;
+  SLK_HIP(hipMalloc(&g->perm, sizeof(int32_t) * n));
+  SLK_HIP(hipMalloc(&g->iperm, sizeof(int32_t) * n));
+  SLK_HIP(hipMemcpyAsync(g->perm, order.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+  SLK_HIP(hipMemcpyAsync(g->iperm, inv.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+  int32_t *nrp = nullptr, *nci = nullptr;
+  SLK_HIP(hipMalloc(&nrp, sizeof(int32_t) * (n + 1)));
+  if (hipMalloc(&nci, sizeof(int32_t) * std::max<int64_t>(g->nnz, 1)) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipFree(nrp);
+    return fail(SLK_ERR_OUT_OF_MEMORY, "relabelled CSR");
+  }
+  slk_status st = relabel_csr(n, g->row_ptr, g->col_idx, g->perm, g->iperm, nrp, nci, s);
+  if (st == SLK_OK && hipStreamSynchronize(s) != hipSuccess) st = fail(SLK_ERR_DEVICE, "relabel");
+  if (st != SLK_OK) {
+    (void)hipFree(nrp);
+    (void)hipFree(nci);
+    return st;
+  }
+  (void)hipFree(g->row_ptr);
+  (void)hipFree(g->col_idx);
+  g->row_ptr = nrp;
+  g->col_idx = nci;
+  g->reordered = 1;
+  return SLK_OK;
+}
+
+// CSR, degree statistics, sigma^2 and the optional permutation for a graph whose kNN lists are set
+slk_status finish_from_knn(slk_graph* g, int32_t reorder, hipStream_t s) {
+  SLK_TRY(build_csr(g->n, g->k, g->knn_idx, &g->row_ptr, &g->col_idx, &g->nnz, s));
+  if (g->knn_d2) {
+    Scratch sc(s);
+    double* sum;
+    SLK_TRY(sc.get(&sum, 1));
+    SLK_TRY(sum_f64(g->knn_d2, g->n * g->k, sum, s));
+    double h = 0.0;
+    SLK_HIP(hipMemcpyAsync(&h, sum, sizeof(double), hipMemcpyDeviceToHost, s));
+    SLK_HIP(hipStreamSynchronize(s));
+    g->sigma2 = h / ((double)g->n * (double)g->k);
+  }
+  if (reorder) SLK_TRY(bfs_reorder(g, s));
+  int32_t mn, mx;
+  SLK_TRY(degree_stats(g->row_ptr, g->n, &mn, &mx, s));
+  g->min_degree = mn;
+  g->max_degree = mx;
+  return SLK_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// the z-update loop for fixed modes
+// ------------------------------------------------------------------------------------------
+struct Work {
+  float* A = nullptr;
+  float* Z[2] = {nullptr, nullptr};
+  int32_t* labels_int = nullptr;
+  double* partial = nullptr;
+  double* partial2 = nullptr;
+  float* cand_v = nullptr;
+  int32_t* cand_i = nullptr;
+  IterState* state = nullptr;
+  IterState* state2 = nullptr;
+  double* bound = nullptr;
+  int32_t* modes = nullptr;
+  int32_t* modes_next = nullptr;
+  double* epart_un = nullptr;
+  double* epart_un64 = nullptr;
+  long long* epart_cut = nullptr;
+  double* eout = nullptr;
+  long long* eout_cut = nullptr;
+  uint32_t* earrive = nullptr;
+  double* trace = nullptr;
+  int grid = 0, egrid = 0;
+};
+
+slk_status alloc_work(Scratch& sc, int64_t n, int32_t L, int trace_cap, Work& w) {
+  w.grid = iter_grid(n, L);
+  w.egrid = energy_grid(n);
+  SLK_TRY(sc.get(&w.A, n * L));
+  SLK_TRY(sc.get(&w.Z[0], n * L));
+  SLK_TRY(sc.get(&w.Z[1], n * L));
+  SLK_TRY(sc.get(&w.labels_int, n));
+  SLK_TRY(sc.get(&w.partial, w.grid));
+  SLK_TRY(sc.get(&w.partial2, w.grid));
+  SLK_TRY(sc.get(&w.cand_v, (int64_t)w.grid * L));
+  SLK_TRY(sc.get(&w.cand_i, (int64_t)w.grid * L));
+  SLK_TRY(sc.get(&w.state, 1));
+  SLK_TRY(sc.get(&w.state2, 1));
+  SLK_TRY(sc.get(&w.bound, 1));
+  SLK_TRY(sc.get(&w.modes, L));
+  SLK_TRY(sc.get(&w.modes_next, L));
+  SLK_TRY(sc.get(&w.epart_un, w.egrid));
+  SLK_TRY(sc.get(&w.epart_un64, w.egrid));
+  SLK_TRY(sc.get(&w.epart_cut, w.egrid));
+  SLK_TRY(sc.get(&w.eout, 2));
+  SLK_TRY(sc.get(&w.eout_cut, 1));
+  SLK_TRY(sc.get(&w.earrive, 1));
+  SLK_TRY(sc.get(&w.trace, std::max(trace_cap, 1)));
+  SLK_HIP(hipMemsetAsync(w.earrive, 0, sizeof(uint32_t), sc.stream));
+  return SLK_OK;
+}
+
+struct OuterOut {
+  int passes = 0;
+  int converged = 0;
+  double energy = 0, energy64 = 0, bound = 0;
+  long long cut = 0;
+};
+
+IterArgs make_iter(const slk_graph* g, const Work& w, int64_t n, int32_t L, const slk_params& p) {
+  IterArgs a{};
+  a.row_ptr = g->row_ptr;
+  a.col_idx = g->col_idx;
+  a.A = w.A;
+  a.n = n;
+  a.L = L;
+  a.lam_eff = (float)(p.pairwise_scale * p.lambda);
+  a.half_lam_eff = (float)(0.5 * p.pairwise_scale * p.lambda);
+  a.delta = (float)p.delta;
+  a.partial = w.partial;
+  a.state = w.state;
+  a.trace = w.trace;
+  a.bound_out = nullptr;
+  return a;
+}
+
+// One outer iteration with the modes in w.modes.  Device outputs: z_user / labels_user (may
+// be null), w.modes_next, w.trace.  Host outputs in *o.
+slk_status run_outer(const float* x, int64_t n, int32_t d, const slk_graph* g, int32_t L, const slk_params& p,
+                     double sigma2, int trace_cap, int want_fp64, hipStream_t s, Work& w, float* z_user,
+                     int32_t* labels_user, OuterOut* o) {
+  SLK_TRY(launch_unary(x, n, d, g->perm, w.modes, L, sigma2, p.prec == SLK_PREC_BF16, w.A, w.Z[0], s));
+  const int check = p.fixed_inner > 0 ? 0 : 1;
+  hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(1), 0, s, w.state, p.bound_tol, check, trace_cap);
+  hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(1), 0, s, w.state2, 0.0, 0, 0);
+  SLK_LAUNCHED("init_state_kernel");
+  IterArgs a = make_iter(g, w, n, L, p);
+  IterState hs{};
+  int launched = 0;
+  if (!check) {
+    for (; launched < p.fixed_inner; ++launched) {
+      a.Zin = w.Z[launched & 1];
+      a.Zout = w.Z[(launched + 1) & 1];
+      SLK_TRY(launch_iter(a, w.grid, s));
+    }
+    SLK_HIP(hipMemcpyAsync(&hs, w.state, sizeof(IterState), hipMemcpyDeviceToHost, s));
+    SLK_HIP(hipStreamSynchronize(s));
+  } else {
+    int chunk = 2;
+    while (launched < p.max_inner) {
+      const int c = std::min(chunk, p.max_inner - launched);
+      for (int j = 0; j < c; ++j, ++launched) {
+        a.Zin = w.Z[launched & 1];
+        a.Zout = w.Z[(launched + 1) & 1];
+        SLK_TRY(launch_iter(a, w.grid, s));
+      }
+      void* pin;
+      SLK_TRY(pinned(&pin, sizeof(IterState)));
+      SLK_HIP(hipMemcpyAsync(pin, w.state, sizeof(IterState), hipMemcpyDeviceToHost, s));
+      SLK_HIP(hipStreamSynchronize(s));
+      memcpy(&hs, pin, sizeof(IterState));
+      if (hs.done) break;
+      chunk = std::min(chunk * 2, 16);
+    }
+  }
+  if (hs.numeric) return fail(SLK_ERR_NUMERIC, "relaxed bound is not finite");
+  const int passes = hs.pass;
+  if (passes < 1) return fail(SLK_ERR_INVALID_ARG, "at least one z-update is needed");
+  o->passes = passes;
+  o->converged = check ? hs.done : 1;
+  // final pass on the input of the last z-update: labels, modes, Z in the caller's order
+  FinalArgs f{};
+  f.it = a;
+  f.it.Zin = w.Z[(passes - 1) & 1];
+  f.it.Zout = nullptr;
+  f.it.state = w.state2;
+  f.it.partial = w.partial2;
+  f.it.trace = nullptr;
+  f.it.bound_out = w.bound;
+  f.perm = g->perm;
+  f.z_user = z_user;
+  f.labels_int = w.labels_int;
+  f.labels_user = labels_user;
+  f.cand_v = w.cand_v;
+  f.cand_i = w.cand_i;
+  SLK_TRY(launch_final(f, w.grid, s));
+  SLK_TRY(launch_mode_reduce(w.cand_v, w.cand_i, w.grid, L, w.modes_next, s));
+  EnergyArgs e{};
+  e.row_ptr = g->row_ptr;
+  e.col_idx = g->col_idx;
+  e.labels_int = w.labels_int;
+  e.A = w.A;
+  e.x = want_fp64 ? x : nullptr;
+  e.perm = g->perm;
+  e.modes = w.modes;
+  e.n = n;
+  e.d = d;
+  e.L = L;
+  e.inv2s2 = 1.0 / (2.0 * sigma2);
+  e.part_un = w.epart_un;
+  e.part_un64 = w.epart_un64;
+  e.part_cut = w.epart_cut;
+  e.out = w.eout;
+  e.out_cut = w.eout_cut;
+  e.arrive = w.earrive;
+  SLK_TRY(launch_energy(e, w.egrid, s));
+  double eo[2];
+  long long cut = 0;
+  double bnd = 0;
+  SLK_HIP(hipMemcpyAsync(eo, w.eout, sizeof(eo), hipMemcpyDeviceToHost, s));
+  SLK_HIP(hipMemcpyAsync(&cut, w.eout_cut, sizeof(cut), hipMemcpyDeviceToHost, s));
+  SLK_HIP(hipMemcpyAsync(&bnd, w.bound, sizeof(bnd), hipMemcpyDeviceToHost, s));
+  SLK_HIP(hipStreamSynchronize(s));
+  o->cut = cut;
+  o->energy = -eo[0] + p.lambda * (double)cut;
+  o->energy64 = want_fp64 ? -eo[1] + p.lambda * (double)cut : o->energy;
+  o->bound = bnd;
+  return SLK_OK;
+}
+
+slk_status check_params(const slk_params* p) {
+  if (!p) return fail(SLK_ERR_INVALID_ARG, "params is NULL");
+  if (!(p->lambda >= 0.0) || !isfinite(p->lambda)) return fail(SLK_ERR_INVALID_ARG, "lambda must be finite and >= 0");
+  if (!(p->delta >= 0.0) || !isfinite(p->delta)) return fail(SLK_ERR_INVALID_ARG, "delta must be finite and >= 0");
+  if (!isfinite(p->sigma2)) return fail(SLK_ERR_INVALID_ARG, "sigma2 must be finite");
+  if (!(p->bound_tol >= 0.0)) return fail(SLK_ERR_INVALID_ARG, "bound_tol must be >= 0");
+  if (p->max_outer < 1) return fail(SLK_ERR_INVALID_ARG, "max_outer must be >= 1");
+  if (p->max_inner < 1) return fail(SLK_ERR_INVALID_ARG, "max_inner must be >= 1");
+  if (p->fixed_inner < 0) return fail(SLK_ERR_INVALID_ARG, "fixed_inner must be >= 0");
+  if (p->pairwise_scale != 1 && p->pairwise_scale != 2) return fail(SLK_ERR_INVALID_ARG, "pairwise_scale must be 1 or 2");
+  if (p->prec != SLK_PREC_FP32 && p->prec != SLK_PREC_BF16) return fail(SLK_ERR_INVALID_ARG, "unknown precision");
+  return SLK_OK;
+}
+
+slk_status check_points(const float* x, int64_t n, int32_t d) {
+  if (!x) return fail(SLK_ERR_INVALID_ARG, "x is NULL");
+  if (n < 2 || n >= (int64_t)INT32_MAX) return fail(SLK_ERR_INVALID_ARG, "n must satisfy 2 <= n < 2^31");
+  if (d < 1) return fail(SLK_ERR_INVALID_ARG, "d must be >= 1");
+  return SLK_OK;
+}
+
+slk_status check_problem(const float* x, int64_t n, int32_t d, const slk_graph* g, int32_t L, const int32_t* modes_host) {
+  SLK_TRY(check_points(x, n, d));
+  if (!g) return fail(SLK_ERR_INVALID_ARG, "graph is NULL");
+  if (g->n != n) return fail(SLK_ERR_INVALID_ARG, "graph was built for a different n");
+  if (L < 1 || L > 256 || L > n) return fail(SLK_ERR_INVALID_ARG, "L must satisfy 1 <= L <= min(256, n)");
+  if (!modes_host) return fail(SLK_ERR_INVALID_ARG, "modes is NULL");
+  for (int l = 0; l < L; ++l)
+    if (modes_host[l] < 0 || modes_host[l] >= n) return fail(SLK_ERR_INVALID_ARG, "mode index out of range");
+  int dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess && dev != g->device)
+    return fail(SLK_ERR_INVALID_ARG, "graph lives on another device");
+  return SLK_OK;
+}
+
+double pick_sigma2(const slk_params& p, const slk_graph* g) { return p.sigma2 > 0.0 ? p.sigma2 : g->sigma2; }
+
+}  // namespace
+}  // namespace slk
+
+using namespace slk;
+
+// ============================================================================================
+// exported functions
+// ============================================================================================
+extern "C" {
+
+const char* slk_last_error(void) { return g_err.c_str(); }
+
+const char* slk_version(void) { return "libslk 0.1 (gfx950)"; }
+
+slk_status slk_knn_opts_default(slk_knn_opts* o) {
+  if (!o) return fail(SLK_ERR_INVALID_ARG, "opts is NULL");
+  o->k = 10;
+  o->reorder = 0;
+  o->candidates = 0;
+  o->method = SLK_KNN_AUTO;
+  o->prec = SLK_PREC_FP32;
+  return SLK_OK;
+}
+
+slk_status slk_params_default(slk_params* p) {
+  if (!p) return fail(SLK_ERR_INVALID_ARG, "params is NULL");
+  memset(p, 0, sizeof(*p));
+  p->lambda = 1.0;
+  p->sigma2 = 0.0;
+  p->delta = 0.0;
+  p->bound_tol = 1e-8;
+  p->max_outer = 20;
+  p->max_inner = 1000;
+  p->fixed_inner = 0;
+  p->pairwise_scale = 1;
+  p->prec = SLK_PREC_FP32;
+  return SLK_OK;
+}
+
+slk_status slk_build_knn(const float* x, int64_t n, int32_t d, const slk_knn_opts* opts, void* stream,
+                         slk_graph** g_out) {
+  if (!g_out) return fail(SLK_ERR_INVALID_ARG, "g_out is NULL");
+  *g_out = nullptr;
+  SLK_TRY(check_points(x, n, d));
+  slk_knn_opts o;
+  if (opts) o = *opts;
+  else slk_knn_opts_default(&o);
+  if (o.k < 1 || o.k > 64 || o.k >= n) return fail(SLK_ERR_INVALID_ARG, "k must satisfy 1 <= k <= 64 and k < n");
+  if (o.prec != SLK_PREC_FP32 && o.prec != SLK_PREC_BF16) return fail(SLK_ERR_INVALID_ARG, "unknown precision");
+  if (o.method < SLK_KNN_AUTO || o.method > SLK_KNN_MFMA) return fail(SLK_ERR_INVALID_ARG, "unknown kNN method");
+  if (o.candidates < 0) return fail(SLK_ERR_INVALID_ARG, "candidates must be >= 0");
+  if ((int64_t)n * 2 * o.k >= (int64_t)INT32_MAX) return fail(SLK_ERR_INVALID_ARG, "n * 2k exceeds the CSR index range");
+  hipStream_t s = (hipStream_t)stream;
+  SLK_TRY(check_finite(x, n * (int64_t)d, s));
+  GraphGuard gg{new slk_graph()};
+  slk_graph* g = gg.g;
+  SLK_HIP(hipGetDevice(&g->device));
+  g->n = n;
+  g->k = o.k;
+  SLK_HIP(hipMalloc(&g->knn_idx, sizeof(int32_t) * n * o.k));
+  SLK_HIP(hipMalloc(&g->knn_d2, sizeof(double) * n * o.k));
+  const int bf16 = o.prec == SLK_PREC_BF16;
+  int method = o.method;
+  if (method == SLK_KNN_AUTO) method = ((double)n * (double)n * (double)d <= 4.0e9) ? SLK_KNN_EXACT : SLK_KNN_MFMA;
+  if (method == SLK_KNN_EXACT) {
+    SLK_TRY(knn_exact(x, n, d, o.k, bf16, nullptr, n, g->knn_idx, g->knn_d2, s));
+    g->rows_certified = 0;
+    g->rows_fallback = n;
+  } else {
+    int cand = o.candidates > 0 ? o.candidates : std::max(2 * o.k, 32);
+    cand = std::min(std::max(cand, o.k), 256);
+    SLK_TRY(knn_mfma(x, n, d, o.k, cand, bf16, g->knn_idx, g->knn_d2, &g->rows_certified, &g->rows_fallback, s));
+  }
+  SLK_TRY(finish_from_knn(g, o.reorder, s));
+  *g_out = gg.release();
+  return SLK_OK;
+}
+
+slk_status slk_graph_from_knn(int64_t n, int32_t k, const int32_t* knn_idx, const double* knn_d2, int32_t reorder,
+                              void* stream, slk_graph** g_out) {
+  if (!g_out) return fail(SLK_ERR_INVALID_ARG, "g_out is NULL");
+  *g_out = nullptr;
+  if (n < 2 || n >= (int64_t)INT32_MAX) return fail(SLK_ERR_INVALID_ARG, "n must satisfy 2 <= n < 2^31");
+  if (k < 1 || k > 64 || k >= n) return fail(SLK_ERR_INVALID_ARG, "k must satisfy 1 <= k <= 64 and k < n");
+  if (!knn_idx) return fail(SLK_ERR_INVALID_ARG, "knn_idx is NULL");
+  if ((int64_t)n * 2 * k >= (int64_t)INT32_MAX) return fail(SLK_ERR_INVALID_ARG, "n * 2k exceeds the CSR index range");
+  hipStream_t s = (hipStream_t)stream;
+  SLK_TRY(check_indices(knn_idx, n * (int64_t)k, n, s, "kNN indices must lie in [0, n)"));
+  GraphGuard gg{new slk_graph()};
+  slk_graph* g = gg.g;
+  SLK_HIP(hipGetDevice(&g->device));
+  g->n = n;
+  g->k = k;
+  SLK_HIP(hipMalloc(&g->knn_idx, sizeof(int32_t) * n * k));
+  SLK_HIP(hipMemcpyAsync(g->knn_idx, knn_idx, sizeof(int32_t) * n * k, hipMemcpyDeviceToDevice, s));
+  if (knn_d2) {
+    SLK_HIP(hipMalloc(&g->knn_d2, sizeof(double) * n * k));
+    SLK_HIP(hipMemcpyAsync(g->knn_d2, knn_d2, sizeof(double) * n * k, hipMemcpyDeviceToDevice, s));
+  }
+  SLK_TRY(finish_from_knn(g, reorder, s));
+  *g_out = gg.release();
+  return SLK_OK;
+}
+
+slk_status slk_graph_from_csr(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                              double sigma2_hint, int32_t reorder, void* stream, slk_graph** g_out) {
+  if (!g_out) return fail(SLK_ERR_INVALID_ARG, "g_out is NULL");
+  *g_out = nullptr;
+  if (n < 2 || n >= (int64_t)INT32_MAX) return fail(SLK_ERR_INVALID_ARG, "n must satisfy 2 <= n < 2^31");
+  if (nnz < 0 || nnz >= (int64_t)INT32_MAX) return fail(SLK_ERR_INVALID_ARG, "nnz must satisfy 0 <= nnz < 2^31");
+  if (!row_ptr || (nnz > 0 && !col_idx)) return fail(SLK_ERR_INVALID_ARG, "CSR array is NULL");
+  if (!isfinite(sigma2_hint)) return fail(SLK_ERR_INVALID_ARG, "sigma2_hint must be finite");
+  hipStream_t s = (hipStream_t)stream;
+  SLK_TRY(check_row_ptr(row_ptr, n, nnz, s));
+  if (nnz > 0) SLK_TRY(check_indices(col_idx, nnz, n, s, "CSR columns must lie in [0, n)"));
+  GraphGuard gg{new slk_graph()};
+  slk_graph* g = gg.g;
+  SLK_HIP(hipGetDevice(&g->device));
+  g->n = n;
+  g->k = 0;
+  g->nnz = nnz;
+  g->sigma2 = sigma2_hint > 0 ? sigma2_hint : 0.0;
+  SLK_HIP(hipMalloc(&g->row_ptr, sizeof(int32_t) * (n + 1)));
+  SLK_HIP(hipMalloc(&g->col_idx, sizeof(int32_t) * std::max<int64_t>(nnz, 1)));
+  SLK_HIP(hipMemcpyAsync(g->row_ptr, row_ptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToDevice, s));
+  if (nnz) SLK_HIP(hipMemcpyAsync(g->col_idx, col_idx, sizeof(int32_t) * nnz, hipMemcpyDeviceToDevice, s));
+  if (reorder) SLK_TRY(bfs_reorder(g, s));
+  int32_t mn, mx;
+  SLK_TRY(degree_stats(g->row_ptr, n, &mn, &mx, s));
+  g->min_degree = mn;
+  g->max_degree = mx;
+  *g_out = gg.release();
+  return SLK_OK;
+}
+
+slk_status slk_graph_info(const slk_graph* g, slk_graph_info_t* info) {
+  if (!g || !info) return fail(SLK_ERR_INVALID_ARG, "NULL argument");
+  info->n = g->n;
+  info->k = g->k;
+  info->reordered = g->reordered;
+  info->nnz = g->nnz;
+  info->max_degree = g->max_degree;
+  info->min_degree = g->min_degree;
+  info->sigma2 = g->sigma2;
+  info->rows_certified = g->rows_certified;
+  info->rows_fallback = g->rows_fallback;
+  return SLK_OK;
+}
+
+slk_status slk_graph_export(const slk_graph* g, int32_t* row_ptr, int32_t* col_idx, int32_t* knn_idx, double* knn_d2,
+                            int32_t* perm, void* stream) {
+  if (!g) return fail(SLK_ERR_INVALID_ARG, "graph is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = g->n;
+  if ((knn_idx || knn_d2) && !g->knn_idx) return fail(SLK_ERR_INVALID_ARG, "graph has no kNN lists");
+  if (knn_d2 && !g->knn_d2) return fail(SLK_ERR_INVALID_ARG, "graph has no kNN distances");
+  if (knn_idx) SLK_HIP(hipMemcpyAsync(knn_idx, g->knn_idx, sizeof(int32_t) * n * g->k, hipMemcpyDeviceToDevice, s));
+  if (knn_d2) SLK_HIP(hipMemcpyAsync(knn_d2, g->knn_d2, sizeof(double) * n * g->k, hipMemcpyDeviceToDevice, s));
+  if (perm) {
+    if (g->perm) {
+      SLK_HIP(hipMemcpyAsync(perm, g->perm, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+    } else {
+      std::vector<int32_t> id(n);
+      for (int64_t i = 0; i < n; ++i) id[i] = (int32_t)i;
+      SLK_HIP(hipMemcpyAsync(perm, id.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+      SLK_HIP(hipStreamSynchronize(s));
+    }
+  }
+  if (row_ptr || col_idx) {
+    if (!g->perm) {
+      if (row_ptr) SLK_HIP(hipMemcpyAsync(row_ptr, g->row_ptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToDevice, s));
+      if (col_idx && g->nnz)
+        SLK_HIP(hipMemcpyAsync(col_idx, g->col_idx, sizeof(int32_t) * g->nnz, hipMemcpyDeviceToDevice, s));
+    } else {
+      // back to the original numbering: new row p is internal row iperm[p]
+      Scratch sc(s);
+      int32_t *rp, *ci;
+      SLK_TRY(sc.get(&rp, n + 1));
+      SLK_TRY(sc.get(&ci, g->nnz));
+      SLK_TRY(relabel_csr(n, g->row_ptr, g->col_idx, g->iperm, g->perm, rp, ci, s));
+      if (row_ptr) SLK_HIP(hipMemcpyAsync(row_ptr, rp, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToDevice, s));
+      if (col_idx && g->nnz) SLK_HIP(hipMemcpyAsync(col_idx, ci, sizeof(int32_t) * g->nnz, hipMemcpyDeviceToDevice, s));
+      SLK_HIP(hipStreamSynchronize(s));
+    }
+  }
+  SLK_HIP(hipStreamSynchronize(s));
+  return SLK_OK;
+}
+
+void slk_graph_destroy(slk_graph* g) {
+  if (g) (void)hipDeviceSynchronize();
+  free_graph(g);
+}
+
+slk_status slk_unary(const float* x, int64_t n, int32_t d, int32_t L, const int32_t* modes_host, double sigma2,
+                     slk_precision prec, void* stream, float* a_out, float* z0_out) {
+  SLK_TRY(check_points(x, n, d));
+  if (L < 1 || L > 256 || L > n) return fail(SLK_ERR_INVALID_ARG, "L must satisfy 1 <= L <= min(256, n)");
+  if (!modes_host) return fail(SLK_ERR_INVALID_ARG, "modes is NULL");
+  for (int l = 0; l < L; ++l)
+    if (modes_host[l] < 0 || modes_host[l] >= n) return fail(SLK_ERR_INVALID_ARG, "mode index out of range");
+  if (!(sigma2 > 0.0) || !isfinite(sigma2)) return fail(SLK_ERR_INVALID_ARG, "sigma2 must be > 0");
+  if (prec != SLK_PREC_FP32 && prec != SLK_PREC_BF16) return fail(SLK_ERR_INVALID_ARG, "unknown precision");
+  hipStream_t s = (hipStream_t)stream;
+  Scratch sc(s);
+  int32_t* md;
+  SLK_TRY(sc.get(&md, L));
+  SLK_HIP(hipMemcpyAsync(md, modes_host, sizeof(int32_t) * L, hipMemcpyHostToDevice, s));
+  SLK_TRY(launch_unary(x, n, d, nullptr, md, L, sigma2, prec == SLK_PREC_BF16, a_out, z0_out, s));
+  SLK_HIP(hipStreamSynchronize(s));
+  return SLK_OK;
+}
+
+slk_status slk_inner_step(const slk_graph* g, int32_t L, const float* a, const float* z_in, double lambda,
+                          double delta, int32_t pairwise_scale, void* stream, float* z_out, double* bound_host) {
+  if (!g || !a || !z_in) return fail(SLK_ERR_INVALID_ARG, "NULL argument");
+  if (L < 1 || L > 256 || L > g->n) return fail(SLK_ERR_INVALID_ARG, "L must satisfy 1 <= L <= min(256, n)");
+  if (!(lambda >= 0.0) || !isfinite(lambda) || !(delta >= 0.0) || !isfinite(delta))
+    return fail(SLK_ERR_INVALID_ARG, "lambda and delta must be finite and >= 0");
+  if (pairwise_scale != 1 && pairwise_scale != 2) return fail(SLK_ERR_INVALID_ARG, "pairwise_scale must be 1 or 2");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = g->n;
+  Scratch sc(s);
+  slk_params p;
+  slk_params_default(&p);
+  p.lambda = lambda;
+  p.delta = delta;
+  p.pairwise_scale = pairwise_scale;
+  Work w;
+  w.grid = iter_grid(n, L);
+  SLK_TRY(sc.get(&w.partial, w.grid));
+  SLK_TRY(sc.get(&w.state, 1));
+  SLK_TRY(sc.get(&w.bound, 1));
+  const float* A = a;
+  const float* Zi = z_in;
+  float* Zo = z_out;
+  if (g->perm) {
+    float *ta, *tz, *to;
+    SLK_TRY(sc.get(&ta, n * L));
+    SLK_TRY(sc.get(&tz, n * L));
+    SLK_TRY(sc.get(&to, n * L));
+    SLK_TRY(launch_gather_rows(a, g->perm, n, L, ta, s));
+    SLK_TRY(launch_gather_rows(z_in, g->perm, n, L, tz, s));
+    A = ta;
+    Zi = tz;
+    Zo = z_out ? to : nullptr;
+  }
+  hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(1), 0, s, w.state, 0.0, 0, 0);
+  SLK_LAUNCHED("init_state_kernel");
+  IterArgs ia = make_iter(g, w, n, L, p);
+  ia.A = A;
+  ia.Zin = Zi;
+  ia.Zout = Zo;
+  ia.trace = nullptr;
+  ia.bound_out = w.bound;
+  SLK_TRY(launch_iter(ia, w.grid, s));
+  if (g->perm && z_out) SLK_TRY(launch_scatter_rows(Zo, g->perm, n, L, z_out, s));
+  if (bound_host) {
+    SLK_HIP(hipMemcpyAsync(bound_host, w.bound, sizeof(double), hipMemcpyDeviceToHost, s));
+  }
+  SLK_HIP(hipStreamSynchronize(s));
+  return SLK_OK;
+}
+
+static slk_status assign_or_fit(bool fit, const float* x, int64_t n, int32_t d, const slk_graph* g, int32_t L,
+                                const int32_t* modes_host, const slk_params* pp, void* stream, float* z_out,
+                                int32_t* labels_out, int32_t* modes_next_host, double* trace_host, int32_t trace_cap,
+                                slk_result* res) {
+  SLK_TRY(check_problem(x, n, d, g, L, modes_host));
+  SLK_TRY(check_params(pp));
+  if (!z_out) return fail(SLK_ERR_INVALID_ARG, "z_out is NULL");
+  const slk_params p = *pp;
+  const double sigma2 = pick_sigma2(p, g);
+  if (!(sigma2 > 0.0)) return fail(SLK_ERR_INVALID_ARG, "sigma2 unknown: pass params.sigma2 > 0");
+  if (trace_cap < 0) return fail(SLK_ERR_INVALID_ARG, "trace_cap must be >= 0");
+  hipStream_t s = (hipStream_t)stream;
+  const int cap = std::max(trace_cap, std::max(p.max_inner, p.fixed_inner));
+  Scratch sc(s);
+  Work w;
+  SLK_TRY(alloc_work(sc, n, L, cap, w));
+  std::vector<int32_t> cur(modes_host, modes_host + L), nxt(L);
+  SLK_HIP(hipMemcpyAsync(w.modes, cur.data(), sizeof(int32_t) * L, hipMemcpyHostToDevice, s));
+  slk_result r{};
+  OuterOut o;
+  const int outer_cap = fit ? p.max_outer : 1;
+  for (int t = 0; t < outer_cap; ++t) {
+    const bool last_possible = (t == outer_cap - 1);
+    (void)last_possible;
+    SLK_TRY(run_outer(x, n, d, g, L, p, sigma2, cap, 1, s, w, z_out, labels_out, &o));
+    SLK_HIP(hipMemcpyAsync(nxt.data(), w.modes_next, sizeof(int32_t) * L, hipMemcpyDeviceToHost, s));
+    SLK_HIP(hipStreamSynchronize(s));
+    r.outer_iters = t + 1;
+    r.inner_iters_total += o.passes;
+    r.inner_iters_last = o.passes;
+    r.energy = o.energy;
+    r.energy_fp64 = o.energy64;
+    r.bound = o.bound;
+    r.cut = o.cut;
+    if (!fit) {
+      r.converged = o.converged;
+      break;
+    }
+    if (nxt == cur) {
+      r.converged = 1;
+      break;
+    }
+    cur = nxt;
+    SLK_HIP(hipMemcpyAsync(w.modes, w.modes_next, sizeof(int32_t) * L, hipMemcpyDeviceToDevice, s));
+  }
+  if (trace_host && trace_cap > 0) {
+    const int m = std::min(trace_cap, std::min(o.passes, cap));
+    SLK_HIP(hipMemcpyAsync(trace_host, w.trace, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+  }
+  SLK_HIP(hipStreamSynchronize(s));
+  if (modes_next_host) memcpy(modes_next_host, nxt.data(), sizeof(int32_t) * L);
+  std::vector<int32_t> u(nxt);
+  std::sort(u.begin(), u.end());
+  r.n_distinct_modes = (int32_t)(std::unique(u.begin(), u.end()) - u.begin());
+  if (res) *res = r;
+  return SLK_OK;
+}
+
+slk_status slk_assign(const float* x, int64_t n, int32_t d, const slk_graph* g, int32_t L, const int32_t* modes_host,
+                      const slk_params* p, void* stream, float* z_out, int32_t* labels_out, int32_t* modes_next_host,
+                      double* bound_trace_host, int32_t trace_cap, slk_result* res_host) {
+  return assign_or_fit(false, x, n, d, g, L, modes_host, p, stream, z_out, labels_out, modes_next_host,
+                       bound_trace_host, trace_cap, res_host);
+}
+
+slk_status slk_fit(const float* x, int64_t n, int32_t d, const slk_graph* g, int32_t L, const int32_t* init_modes_host,
+                   const slk_params* p, void* stream, float* z_out, int32_t* labels_out, int32_t* modes_out_host,
+                   slk_result* res_host) {
+  if (!modes_out_host) return fail(SLK_ERR_INVALID_ARG, "modes_out_host is NULL");
+  return assign_or_fit(true, x, n, d, g, L, init_modes_host, p, stream, z_out, labels_out, modes_out_host, nullptr, 0,
+                       res_host);
+}
+
+slk_status slk_energy(const float* x, int64_t n, int32_t d, const slk_graph* g, int32_t L, const int32_t* labels,
+                      const float* z, const int32_t* modes_host, double lambda, double sigma2, double delta,
+                      void* stream, slk_energy_out* out) {
+  SLK_TRY(check_problem(x, n, d, g, L, modes_host));
+  if (!labels || !out) return fail(SLK_ERR_INVALID_ARG, "NULL argument");
+  if (!(lambda >= 0.0) || !isfinite(lambda) || !(delta >= 0.0) || !isfinite(delta))
+    return fail(SLK_ERR_INVALID_ARG, "lambda and delta must be finite and >= 0");
+  const double s2 = sigma2 > 0 ? sigma2 : g->sigma2;
+  if (!(s2 > 0.0)) return fail(SLK_ERR_INVALID_ARG, "sigma2 unknown: pass sigma2 > 0");
+  hipStream_t s = (hipStream_t)stream;
+  SLK_TRY(check_labels(labels, n, L, s));
+  Scratch sc(s);
+  Work w;
+  SLK_TRY(alloc_work(sc, n, L, 1, w));
+  SLK_HIP(hipMemcpyAsync(w.modes, modes_host, sizeof(int32_t) * L, hipMemcpyHostToDevice, s));
+  SLK_TRY(launch_unary(x, n, d, g->perm, w.modes, L, s2, 0, w.A, nullptr, s));
+  SLK_TRY(launch_to_internal_labels(labels, g->iperm, n, w.labels_int, s));
+  EnergyArgs e{};
+  e.row_ptr = g->row_ptr;
+  e.col_idx = g->col_idx;
+  e.labels_int = w.labels_int;
+  e.A = w.A;
+  e.x = x;
+  e.perm = g->perm;
+  e.modes = w.modes;
+  e.n = n;
+  e.d = d;
+  e.L = L;
+  e.inv2s2 = 1.0 / (2.0 * s2);
+  e.part_un = w.epart_un;
+  e.part_un64 = w.epart_un64;
+  e.part_cut = w.epart_cut;
+  e.out = w.eout;
+  e.out_cut = w.eout_cut;
+  e.arrive = w.earrive;
+  SLK_TRY(launch_energy(e, w.egrid, s));
+  double bnd = 0.0;
+  if (z) {
+    slk_params p;
+    slk_params_default(&p);
+    p.lambda = lambda;
+    p.delta = delta;
+    const float* Zi = z;
+    if (g->perm) {
+      SLK_TRY(launch_gather_rows(z, g->perm, n, L, w.Z[0], s));
+      Zi = w.Z[0];
+    }
+    hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(1), 0, s, w.state, 0.0, 0, 0);
+    SLK_LAUNCHED("init_state_kernel");
+    IterArgs ia = make_iter(g, w, n, L, p);
+    ia.Zin = Zi;
+    ia.Zout = nullptr;
+    ia.trace = nullptr;
+    ia.bound_out = w.bound;
+    SLK_TRY(launch_iter(ia, w.grid, s));
+    SLK_HIP(hipMemcpyAsync(&bnd, w.bound, sizeof(double), hipMemcpyDeviceToHost, s));
+  }
+  double eo[2];
+  long long cut;
+  SLK_HIP(hipMemcpyAsync(eo, w.eout, sizeof(eo), hipMemcpyDeviceToHost, s));
+  SLK_HIP(hipMemcpyAsync(&cut, w.eout_cut, sizeof(cut), hipMemcpyDeviceToHost, s));
+  SLK_HIP(hipStreamSynchronize(s));
+  out->energy = -eo[0] + lambda * (double)cut;
+  out->energy_fp64 = -eo[1] + lambda * (double)cut;
+  out->bound = bnd;
+  out->cut = cut;
+  return SLK_OK;
+}
+
+}  // extern "C"

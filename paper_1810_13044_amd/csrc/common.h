@@ -1,0 +1,200 @@
+// Internal declarations shared by the libslk translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+
+#include "../../include/slk.h"
+
+namespace slk {
+
+// Rounds a float to the nearest bfloat16 (ties to even) and returns it widened back to float.
+// bfloat16 keeps the top 16 bits of the IEEE single format; NaN stays NaN.
+__host__ __device__ __forceinline__ float bf16_round(float v) {
+  uint32_t b;
+  __builtin_memcpy(&b, &v, 4);
+  if ((b & 0x7f800000u) == 0x7f800000u && (b & 0x007fffffu)) return v;
+  b += 0x7fffu + ((b >> 16) & 1u);
+  b &= 0xffff0000u;
+  float r;
+  __builtin_memcpy(&r, &b, 4);
+  return r;
+}
+
+// ------------------------------------------------------------------------------------
+// errors
+// ------------------------------------------------------------------------------------
+void set_error(const std::string& msg);
+slk_status fail(slk_status s, const std::string& msg);
+
+#define SLK_HIP(call)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (call);                                                                  \
+    if (e_ != hipSuccess) {                                                                  \
+      (void)hipGetLastError();                                                               \
+      return ::slk::fail(e_ == hipErrorOutOfMemory ? SLK_ERR_OUT_OF_MEMORY : SLK_ERR_DEVICE,   \
+                         std::string(#call) + ": " + hipGetErrorString(e_));                 \
+    }                                                                                        \
+  } while (0)
+
+#define SLK_LAUNCHED(name)                                                                   \
+  do {                                                                                       \
+    hipError_t e_ = hipGetLastError();                                                       \
+    if (e_ != hipSuccess)                                                                    \
+      return ::slk::fail(SLK_ERR_DEVICE, std::string("launch ") + (name) + ": " +            \
+                                             hipGetErrorString(e_));                         \
+  } while (0)
+
+#define SLK_TRY(expr)                     \
+  do {                                    \
+    slk_status s_ = (expr);               \
+    if (s_ != SLK_OK) return s_;          \
+  } while (0)
+
+// ------------------------------------------------------------------------------------
+// stream-ordered device buffers owned by one call
+// ------------------------------------------------------------------------------------
+struct Scratch {
+  hipStream_t stream;
+  void* ptrs[32];
+  int n = 0;
+  explicit Scratch(hipStream_t s) : stream(s) {}
+  ~Scratch() {
+    for (int i = 0; i < n; ++i) (void)hipFreeAsync(ptrs[i], stream);
+  }
+  template <class T>
+  slk_status get(T** out, size_t count) {
+    *out = nullptr;
+    if (count == 0) count = 1;
+    if (n >= 32) return fail(SLK_ERR_INVALID_ARG, "internal: too many scratch buffers");
+    void* p = nullptr;
+    hipError_t e = hipMallocAsync(&p, count * sizeof(T), stream);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(SLK_ERR_OUT_OF_MEMORY, std::string("hipMallocAsync: ") + hipGetErrorString(e));
+    }
+    ptrs[n++] = p;
+    *out = static_cast<T*>(p);
+    return SLK_OK;
+  }
+};
+
+// pinned host staging buffer, one per thread, grown on demand
+slk_status pinned(void** out, size_t bytes);
+
+}  // namespace slk
+
+// ------------------------------------------------------------------------------------
+// the graph handle
+// ------------------------------------------------------------------------------------
+struct slk_graph {
+  int64_t n = 0;
+  int32_t k = 0;
+  int64_t nnz = 0;
+  int32_t max_degree = 0, min_degree = 0;
+  double sigma2 = 0.0;
+  int32_t reordered = 0;
+  int64_t rows_certified = 0, rows_fallback = 0;
+  int device = 0;
+  // device arrays (hipMalloc, owned)
+  int32_t* row_ptr = nullptr;   // n+1, internal order
+  int32_t* col_idx = nullptr;   // nnz, internal indices, sorted per row
+  int32_t* knn_idx = nullptr;   // n*k, original order and indices (may be null)
+  double* knn_d2 = nullptr;     // n*k (may be null)
+  int32_t* perm = nullptr;      // n: internal row -> original index (null = identity)
+  int32_t* iperm = nullptr;     // n: original index -> internal row (null = identity)
+};
+
+namespace slk {
+
+// ------------------------------------------------------------------------------------
+// kernels and launchers (defined in iter.hip / graph.hip)
+// ------------------------------------------------------------------------------------
+
+// Device-side state of one z-update loop.
+struct IterState {
+  int32_t pass;        // index of the next z-update
+  int32_t done;        // 1 once the bound settled (later passes are no-ops)
+  int32_t numeric;     // 1 if the bound became non-finite
+  uint32_t arrive;     // blocks finished in the current pass
+  double tol;
+  int32_t check;       // 1: test convergence; 0: fixed pass count
+  int32_t trace_cap;
+  double last_bound;
+};
+
+struct IterArgs {
+  const int32_t* row_ptr;
+  const int32_t* col_idx;
+  const float* A;        // n x L (internal order)
+  const float* Zin;      // n x L
+  float* Zout;           // n x L (may be null: bound only)
+  int64_t n;
+  int32_t L;
+  float lam_eff;         // pairwise_scale * lambda
+  float half_lam_eff;    // pairwise_scale * lambda / 2
+  float delta;
+  double* partial;       // one double per block
+  IterState* state;      // may be null: no convergence bookkeeping
+  double* trace;         // bound per pass (device, trace_cap entries) or null
+  double* bound_out;     // if non-null, the last block writes the pass's bound here
+};
+
+struct FinalArgs {
+  IterArgs it;
+  const int32_t* perm;   // internal -> original (null = identity)
+  float* z_user;         // n x L output in original order (null = none)
+  int32_t* labels_int;   // n labels, internal order
+  int32_t* labels_user;  // n labels, original order (null = none)
+  float* cand_v;         // grid x L best log-odds per block
+  int32_t* cand_i;       // grid x L original index of that candidate
+};
+
+slk_status launch_unary(const float* x, int64_t n, int32_t d, const int32_t* perm, const int32_t* modes_dev,
+                        int32_t L, double sigma2, int32_t bf16, float* A, float* Z0, hipStream_t s);
+int iter_grid(int64_t n, int32_t L);
+slk_status launch_iter(const IterArgs& a, int grid, hipStream_t s);
+slk_status launch_final(const FinalArgs& a, int grid, hipStream_t s);
+slk_status launch_mode_reduce(const float* cand_v, const int32_t* cand_i, int grid, int32_t L, int32_t* modes_out,
+                              hipStream_t s);
+struct EnergyArgs {
+  const int32_t* row_ptr;
+  const int32_t* col_idx;
+  const int32_t* labels_int;  // internal order
+  const float* A;             // internal order (FP32 unary)
+  const float* x;             // original order points (for the FP64 recheck), may be null
+  const int32_t* perm;        // internal -> original
+  const int32_t* modes;       // L original indices (device)
+  int64_t n;
+  int32_t d, L;
+  double inv2s2;
+  double* part_un;            // grid doubles
+  double* part_un64;          // grid doubles
+  long long* part_cut;        // grid counts
+  double* out;                // [0] unary32, [1] unary64, [2] cut (as double), written by the last block
+  long long* out_cut;
+  uint32_t* arrive;
+};
+int energy_grid(int64_t n);
+slk_status launch_energy(const EnergyArgs& a, int grid, hipStream_t s);
+slk_status launch_gather_rows(const float* src, const int32_t* perm, int64_t n, int32_t L, float* dst, hipStream_t s);
+slk_status launch_scatter_rows(const float* src, const int32_t* perm, int64_t n, int32_t L, float* dst, hipStream_t s);
+slk_status launch_to_internal_labels(const int32_t* labels_user, const int32_t* iperm, int64_t n, int32_t* out,
+                                     hipStream_t s);
+
+// graph construction
+slk_status knn_exact(const float* x, int64_t n, int32_t d, int32_t k, int32_t bf16, const int32_t* rows,
+                     int64_t n_rows, int32_t* out_idx, double* out_d2, hipStream_t s);
+slk_status knn_mfma(const float* x, int64_t n, int32_t d, int32_t k, int32_t cand, int32_t bf16,
+                    int32_t* out_idx, double* out_d2, int64_t* n_certified, int64_t* n_fallback, hipStream_t s);
+slk_status build_csr(int64_t n, int32_t k, const int32_t* knn_idx, int32_t** row_ptr, int32_t** col_idx,
+                     int64_t* nnz, hipStream_t s);
+slk_status sum_f64(const double* v, int64_t count, double* out_dev, hipStream_t s);
+slk_status exclusive_scan_i32(const int32_t* in, int64_t count, int32_t* out, hipStream_t s);
+slk_status sort_rows(const int32_t* row_ptr, int64_t n, int32_t* col_idx, int32_t max_len, hipStream_t s);
+slk_status relabel_csr(int64_t n, const int32_t* row_ptr, const int32_t* col_idx, const int32_t* perm,
+                       const int32_t* iperm, int32_t* new_row_ptr, int32_t* new_col_idx, hipStream_t s);
+slk_status degree_stats(const int32_t* row_ptr, int64_t n, int32_t* mn, int32_t* mx, hipStream_t s);
+
+}  // namespace slk

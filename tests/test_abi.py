@@ -1,0 +1,94 @@
+"""The C ABI without a GPU: the library loads, exports every function declared in
+include/slk.h, fills defaults, and rejects invalid arguments before any device call."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if not fn.endswith(".h"):
+            continue
+        src = open(os.path.join(ROOT, "include", fn)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names.update(re.findall(r"\b(slk_[a-z0-9_]+)\s*\(", src))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1810_13044_amd import _lib
+    return _lib.load()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("slk_build_knn", "slk_fit", "slk_assign", "slk_energy"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_defaults(lib):
+    from paper_1810_13044_amd import _lib
+    p = _lib.Params()
+    assert lib.slk_params_default(C.byref(p)) == 0
+    assert (p.lambda_, p.sigma2, p.delta, p.bound_tol) == (1.0, 0.0, 0.0, 1e-8)
+    assert (p.max_outer, p.max_inner, p.fixed_inner, p.pairwise_scale, p.prec) == (20, 1000, 0, 1, 0)
+    o = _lib.KnnOpts()
+    assert lib.slk_knn_opts_default(C.byref(o)) == 0
+    assert (o.k, o.reorder, o.candidates, o.method, o.prec) == (10, 0, 0, 0, 0)
+    assert lib.slk_version().startswith(b"libslk")
+
+
+def test_invalid_arguments_rejected_before_launch(lib):
+    from paper_1810_13044_amd import _lib
+    h = C.c_void_p()
+    fake = C.c_void_p(0x1000)        # never dereferenced: validation fails first
+    o = _lib.KnnOpts()
+    lib.slk_knn_opts_default(C.byref(o))
+    assert lib.slk_build_knn(None, 100, 4, C.byref(o), None, C.byref(h)) == 1
+    assert b"NULL" in lib.slk_last_error()
+    assert lib.slk_build_knn(fake, 1, 4, C.byref(o), None, C.byref(h)) == 1
+    assert lib.slk_build_knn(fake, 100, 0, C.byref(o), None, C.byref(h)) == 1
+    o.k = 0
+    assert lib.slk_build_knn(fake, 100, 4, C.byref(o), None, C.byref(h)) == 1
+    o.k = 100
+    assert lib.slk_build_knn(fake, 100, 4, C.byref(o), None, C.byref(h)) == 1
+    assert b"k must" in lib.slk_last_error()
+    o.k = 65
+    assert lib.slk_build_knn(fake, 1000, 4, C.byref(o), None, C.byref(h)) == 1
+    assert lib.slk_graph_from_knn(100, 0, fake, None, 0, None, C.byref(h)) == 1
+    assert lib.slk_graph_from_csr(100, -1, fake, fake, 0.0, 0, None, C.byref(h)) == 1
+    p = _lib.Params()
+    lib.slk_params_default(C.byref(p))
+    modes = np.array([0, 1], dtype=np.int32)
+    r = _lib.Result()
+    # graph NULL
+    assert lib.slk_fit(fake, 100, 4, None, 2, modes.ctypes.data_as(C.c_void_p), C.byref(p), None, fake, None,
+                       modes.ctypes.data_as(C.c_void_p), C.byref(r)) == 1
+    assert lib.slk_unary(fake, 100, 4, 0, modes.ctypes.data_as(C.c_void_p), 1.0, 0, None, fake, fake) == 1
+    assert lib.slk_unary(fake, 100, 4, 2, modes.ctypes.data_as(C.c_void_p), -1.0, 0, None, fake, fake) == 1
+    bad = np.array([0, 100], dtype=np.int32)
+    assert lib.slk_unary(fake, 100, 4, 2, bad.ctypes.data_as(C.c_void_p), 1.0, 0, None, fake, fake) == 1
+    assert b"out of range" in lib.slk_last_error()
+    assert lib.slk_unary(fake, 100, 4, 2, modes.ctypes.data_as(C.c_void_p), 1.0, 7, None, fake, fake) == 1
+    assert lib.slk_inner_step(None, 2, fake, fake, 1.0, 0.0, 1, None, fake, None) == 1
+    assert lib.slk_graph_info(None, None) == 1
+    lib.slk_graph_destroy(None)       # a no-op
+
+
+def test_python_layer_fails_loudly_without_library(tmp_path, monkeypatch):
+    from paper_1810_13044_amd import _lib
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(ImportError):
+        _lib.load(str(tmp_path / "missing.so"))
