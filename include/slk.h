@@ -26,7 +26,8 @@
  *    on the same thread).
  *  - Results are deterministic: the same inputs and parameters give bit-identical
  *    outputs (all reductions run in a fixed order).
- *  - Limits: 2 <= n < 2^31, d >= 1, 1 <= k <= 64, 1 <= L <= 256, total CSR entries < 2^31.
+ *  - Limits: 2 <= n < 2^31, d >= 1, 1 <= k <= 64, 1 <= L <= 256, n * L' < 2^30 where L' is L
+ *    rounded up to a multiple of 4, total CSR entries < 2^31.
  */
 #ifndef SLK_H_
 #define SLK_H_
@@ -65,7 +66,7 @@ typedef struct {
   int32_t k;          /* k_n, neighbours per point (Section 4.2); 1 <= k <= 64, k < n      */
   int32_t reorder;    /* 1: relabel points internally for neighbour locality (BFS order)   */
   int32_t candidates; /* MFMA path: candidates kept per row before the exact re-rank
-                         (0 = automatic; clamped to [k, 256])                               */
+                         (0 = automatic: max(2k, 32); clamped to [k, 64])                             */
   slk_knn_method method;
   slk_precision prec;
 } slk_knn_opts;
@@ -237,6 +238,18 @@ slk_status slk_unary(const float* x, int64_t n, int32_t d, int32_t L, const int3
 slk_status slk_inner_step(const slk_graph* g, int32_t L, const float* a, const float* z_in, double lambda,
                           double delta, int32_t pairwise_scale, void* stream, float* z_out,
                           double* bound_host);
+
+/*
+ * Per-kernel timing for measurement: with timing on, every launch of the iteration kernels
+ * ("unary_kernel", "iter_kernel", "final_kernel", "mode_reduce_kernel", "energy_kernel") made
+ * by slk_assign / slk_fit is bracketed by two HIP events recorded on the call's stream, and
+ * the elapsed times are accumulated per kernel name.  slk_timing_enable(on) clears the totals
+ * and switches timing on (1) or off (0); slk_timing_read returns the number of timed launches
+ * and their total milliseconds for one kernel name (0 and 0.0 if none).  Process-wide state;
+ * timing adds one event pair per launch and should stay off in production.
+ */
+slk_status slk_timing_enable(int32_t on);
+slk_status slk_timing_read(const char* kernel, int64_t* launches_host, double* total_ms_host);
 
 /* Text for the last non-OK status returned on this thread. */
 const char* slk_last_error(void);

@@ -13,7 +13,8 @@ import numpy as np
 from . import _lib
 from ._lib import SlkError, PREC_FP32, PREC_BF16, KNN_AUTO, KNN_EXACT, KNN_MFMA  # noqa: F401
 
-__all__ = ["Graph", "fit", "assign", "energy", "unary", "inner_step", "params", "SlkError"]
+__all__ = ["Graph", "fit", "assign", "energy", "unary", "inner_step", "params", "SlkError", "timing_enable",
+           "timing_read"]
 
 
 def _torch():
@@ -232,3 +233,16 @@ def inner_step(graph: Graph, a, z_in, lam=1.0, delta=0.0, scale=1):
                                   float(lam), float(delta), int(scale), _stream(),
                                   _dev(z_out, torch.float32, "z_out"), C.byref(b)))
     return z_out, b.value
+
+
+def timing_enable(on: bool = True) -> None:
+    """Switch per-kernel HIP-event timing on or off (clears the totals)."""
+    _lib.check(_lib.load().slk_timing_enable(int(bool(on))))
+
+
+def timing_read(kernel: str):
+    """(launches, total_ms) accumulated for one kernel name since timing_enable."""
+    n = C.c_int64(0)
+    ms = C.c_double(0.0)
+    _lib.check(_lib.load().slk_timing_read(kernel.encode(), C.byref(n), C.byref(ms)))
+    return n.value, ms.value

@@ -94,6 +94,10 @@ def load(path: str = LIB_PATH):
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = C.c_int
+    lib.slk_timing_enable.argtypes = [I32]
+    lib.slk_timing_enable.restype = C.c_int
+    lib.slk_timing_read.argtypes = [C.c_char_p, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
+    lib.slk_timing_read.restype = C.c_int
     lib.slk_graph_destroy.argtypes = [P]
     lib.slk_graph_destroy.restype = None
     lib.slk_last_error.restype = C.c_char_p

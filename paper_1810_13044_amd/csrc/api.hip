@@ -3,9 +3,12 @@
 #include "common.h"
 
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -18,6 +21,14 @@ void set_error(const std::string& msg) { g_err = msg; }
 slk_status fail(slk_status s, const std::string& msg) {
   g_err = msg;
   return s;
+}
+
+bool scratch_sync_alloc() {
+  static const bool v = [] {
+    const char* e = getenv("SLK_SCRATCH_MALLOC");
+    return e && e[0] == '1';
+  }();
+  return v;
 }
 
 slk_status pinned(void** out, size_t bytes) {
@@ -38,6 +49,65 @@ slk_status pinned(void** out, size_t bytes) {
   return SLK_OK;
 }
 
+// per-kernel timing ---------------------------------------------------------------------------
+namespace {
+struct TimerPair {
+  std::string name;
+  hipEvent_t a, b;
+};
+std::mutex g_tmu;
+bool g_timing = false;
+std::map<std::string, std::pair<int64_t, double>> g_tacc;
+std::vector<TimerPair> g_tpend;
+std::vector<hipEvent_t> g_tpool;
+
+hipEvent_t take_event() {
+  if (!g_tpool.empty()) {
+    hipEvent_t e = g_tpool.back();
+    g_tpool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return e;
+}
+}  // namespace
+
+bool timing_on() { return g_timing; }
+
+int timer_start(const char* name, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  TimerPair t{name, take_event(), take_event()};
+  if (!t.a || !t.b) return -1;
+  (void)hipEventRecord(t.a, s);
+  g_tpend.push_back(t);
+  return (int)g_tpend.size() - 1;
+}
+
+void timer_stop(int slot, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  if (slot >= 0 && slot < (int)g_tpend.size()) (void)hipEventRecord(g_tpend[slot].b, s);
+}
+
+void timing_flush() {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  for (auto& t : g_tpend) {
+    float ms = 0.f;
+    if (hipEventSynchronize(t.b) == hipSuccess && hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+      auto& acc = g_tacc[t.name];
+      acc.first += 1;
+      acc.second += ms;
+    }
+    (void)hipGetLastError();
+    g_tpool.push_back(t.a);
+    g_tpool.push_back(t.b);
+  }
+  g_tpend.clear();
+}
+
 // kernels local to this file ----------------------------------------------------------------
 namespace {
 
@@ -45,7 +115,6 @@ __global__ void init_state_kernel(IterState* st, double tol, int check, int cap)
   st->pass = 0;
   st->done = 0;
   st->numeric = 0;
-  st->arrive = 0u;
   st->tol = tol;
   st->check = check;
   st->trace_cap = cap;
@@ -220,11 +289,12 @@ slk_status bfs_reorder(slk_graph* g, hipStream_t s) {
   SLK_HIP(hipMemcpyAsync(g->iperm, inv.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
   int32_t *nrp = nullptr, *nci = nullptr;
   SLK_HIP(hipMalloc(&nrp, sizeof(int32_t) * (n + 1)));
-  if (hipMalloc(&nci, sizeof(int32_t) * std::max<int64_t>(g->nnz, 1)) != hipSuccess) {
+  if (hipMalloc(&nci, sizeof(int32_t) * (g->nnz + kColPad)) != hipSuccess) {
     (void)hipGetLastError();
     (void)hipFree(nrp);
     return fail(SLK_ERR_OUT_OF_MEMORY, "relabelled CSR");
   }
+  SLK_HIP(hipMemsetAsync(nci + g->nnz, 0, sizeof(int32_t) * kColPad, s));
   slk_status st = relabel_csr(n, g->row_ptr, g->col_idx, g->perm, g->iperm, nrp, nci, s);
   if (st == SLK_OK && hipStreamSynchronize(s) != hipSuccess) st = fail(SLK_ERR_DEVICE, "relabel");
   if (st != SLK_OK) {
@@ -265,6 +335,7 @@ slk_status finish_from_knn(slk_graph* g, int32_t reorder, hipStream_t s) {
 // the z-update loop for fixed modes
 // ------------------------------------------------------------------------------------------
 struct Work {
+  uint32_t* col_off = nullptr;  // float4 path: CSR columns as byte offsets of Z rows
   float* A = nullptr;
   float* Z[2] = {nullptr, nullptr};
   int32_t* labels_int = nullptr;
@@ -282,17 +353,25 @@ struct Work {
   long long* epart_cut = nullptr;
   double* eout = nullptr;
   long long* eout_cut = nullptr;
-  uint32_t* earrive = nullptr;
   double* trace = nullptr;
   int grid = 0, egrid = 0;
 };
 
+// Column byte offsets for the float4 z-update (L <= 64), computed once per call.
+slk_status prepare_col_off(const slk_graph* g, int32_t L, Scratch& sc, uint32_t** out) {
+  *out = nullptr;
+  if (L > 64) return SLK_OK;
+  SLK_TRY(sc.get(out, g->nnz + kColPad));
+  return launch_col_offsets(g->col_idx, g->nnz, g->n, L, *out, sc.stream);
+}
+
 slk_status alloc_work(Scratch& sc, int64_t n, int32_t L, int trace_cap, Work& w) {
+  const int ldz = ldz_for(L);
   w.grid = iter_grid(n, L);
   w.egrid = energy_grid(n);
-  SLK_TRY(sc.get(&w.A, n * L));
-  SLK_TRY(sc.get(&w.Z[0], n * L));
-  SLK_TRY(sc.get(&w.Z[1], n * L));
+  SLK_TRY(sc.get(&w.A, n * ldz));
+  SLK_TRY(sc.get(&w.Z[0], n * ldz));
+  SLK_TRY(sc.get(&w.Z[1], n * ldz));
   SLK_TRY(sc.get(&w.labels_int, n));
   SLK_TRY(sc.get(&w.partial, w.grid));
   SLK_TRY(sc.get(&w.partial2, w.grid));
@@ -308,9 +387,7 @@ slk_status alloc_work(Scratch& sc, int64_t n, int32_t L, int trace_cap, Work& w)
   SLK_TRY(sc.get(&w.epart_cut, w.egrid));
   SLK_TRY(sc.get(&w.eout, 2));
   SLK_TRY(sc.get(&w.eout_cut, 1));
-  SLK_TRY(sc.get(&w.earrive, 1));
   SLK_TRY(sc.get(&w.trace, std::max(trace_cap, 1)));
-  SLK_HIP(hipMemsetAsync(w.earrive, 0, sizeof(uint32_t), sc.stream));
   return SLK_OK;
 }
 
@@ -325,9 +402,11 @@ IterArgs make_iter(const slk_graph* g, const Work& w, int64_t n, int32_t L, cons
   IterArgs a{};
   a.row_ptr = g->row_ptr;
   a.col_idx = g->col_idx;
+  a.col_off = w.col_off;
   a.A = w.A;
   a.n = n;
   a.L = L;
+  a.ldz = ldz_for(L);
   a.lam_eff = (float)(p.pairwise_scale * p.lambda);
   a.half_lam_eff = (float)(0.5 * p.pairwise_scale * p.lambda);
   a.delta = (float)p.delta;
@@ -343,7 +422,10 @@ IterArgs make_iter(const slk_graph* g, const Work& w, int64_t n, int32_t L, cons
 slk_status run_outer(const float* x, int64_t n, int32_t d, const slk_graph* g, int32_t L, const slk_params& p,
                      double sigma2, int trace_cap, int want_fp64, hipStream_t s, Work& w, float* z_user,
                      int32_t* labels_user, OuterOut* o) {
-  SLK_TRY(launch_unary(x, n, d, g->perm, w.modes, L, sigma2, p.prec == SLK_PREC_BF16, w.A, w.Z[0], s));
+  {
+    KernelTimer kt("unary_kernel", s);
+    SLK_TRY(launch_unary(x, n, d, g->perm, w.modes, L, ldz_for(L), sigma2, p.prec == SLK_PREC_BF16, w.A, w.Z[0], s));
+  }
   const int check = p.fixed_inner > 0 ? 0 : 1;
   hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(1), 0, s, w.state, p.bound_tol, check, trace_cap);
   hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(1), 0, s, w.state2, 0.0, 0, 0);
@@ -359,6 +441,7 @@ slk_status run_outer(const float* x, int64_t n, int32_t d, const slk_graph* g, i
     }
     SLK_HIP(hipMemcpyAsync(&hs, w.state, sizeof(IterState), hipMemcpyDeviceToHost, s));
     SLK_HIP(hipStreamSynchronize(s));
+    if (timing_on()) timing_flush();
   } else {
     int chunk = 2;
     while (launched < p.max_inner) {
@@ -372,6 +455,7 @@ slk_status run_outer(const float* x, int64_t n, int32_t d, const slk_graph* g, i
       SLK_TRY(pinned(&pin, sizeof(IterState)));
       SLK_HIP(hipMemcpyAsync(pin, w.state, sizeof(IterState), hipMemcpyDeviceToHost, s));
       SLK_HIP(hipStreamSynchronize(s));
+      if (timing_on()) timing_flush();
       memcpy(&hs, pin, sizeof(IterState));
       if (hs.done) break;
       chunk = std::min(chunk * 2, 16);
@@ -398,7 +482,10 @@ slk_status run_outer(const float* x, int64_t n, int32_t d, const slk_graph* g, i
   f.cand_v = w.cand_v;
   f.cand_i = w.cand_i;
   SLK_TRY(launch_final(f, w.grid, s));
-  SLK_TRY(launch_mode_reduce(w.cand_v, w.cand_i, w.grid, L, w.modes_next, s));
+  {
+    KernelTimer kt("mode_reduce_kernel", s);
+    SLK_TRY(launch_mode_reduce(w.cand_v, w.cand_i, w.grid, L, w.modes_next, s));
+  }
   EnergyArgs e{};
   e.row_ptr = g->row_ptr;
   e.col_idx = g->col_idx;
@@ -410,13 +497,13 @@ slk_status run_outer(const float* x, int64_t n, int32_t d, const slk_graph* g, i
   e.n = n;
   e.d = d;
   e.L = L;
+  e.ldz = ldz_for(L);
   e.inv2s2 = 1.0 / (2.0 * sigma2);
   e.part_un = w.epart_un;
   e.part_un64 = w.epart_un64;
   e.part_cut = w.epart_cut;
   e.out = w.eout;
   e.out_cut = w.eout_cut;
-  e.arrive = w.earrive;
   SLK_TRY(launch_energy(e, w.egrid, s));
   double eo[2];
   long long cut = 0;
@@ -425,6 +512,7 @@ slk_status run_outer(const float* x, int64_t n, int32_t d, const slk_graph* g, i
   SLK_HIP(hipMemcpyAsync(&cut, w.eout_cut, sizeof(cut), hipMemcpyDeviceToHost, s));
   SLK_HIP(hipMemcpyAsync(&bnd, w.bound, sizeof(bnd), hipMemcpyDeviceToHost, s));
   SLK_HIP(hipStreamSynchronize(s));
+  if (timing_on()) timing_flush();
   o->cut = cut;
   o->energy = -eo[0] + p.lambda * (double)cut;
   o->energy64 = want_fp64 ? -eo[1] + p.lambda * (double)cut : o->energy;
@@ -458,6 +546,8 @@ slk_status check_problem(const float* x, int64_t n, int32_t d, const slk_graph* 
   if (!g) return fail(SLK_ERR_INVALID_ARG, "graph is NULL");
   if (g->n != n) return fail(SLK_ERR_INVALID_ARG, "graph was built for a different n");
   if (L < 1 || L > 256 || L > n) return fail(SLK_ERR_INVALID_ARG, "L must satisfy 1 <= L <= min(256, n)");
+  if ((uint64_t)n * (uint64_t)ldz_for(L) * 4ull >= (1ull << 32))
+    return fail(SLK_ERR_INVALID_ARG, "n * L (rounded up to a multiple of 4) must be < 2^30");
   if (!modes_host) return fail(SLK_ERR_INVALID_ARG, "modes is NULL");
   for (int l = 0; l < L; ++l)
     if (modes_host[l] < 0 || modes_host[l] >= n) return fail(SLK_ERR_INVALID_ARG, "mode index out of range");
@@ -482,6 +572,23 @@ extern "C" {
 const char* slk_last_error(void) { return g_err.c_str(); }
 
 const char* slk_version(void) { return "libslk 0.1 (gfx950)"; }
+
+slk_status slk_timing_enable(int32_t on) {
+  timing_flush();
+  std::lock_guard<std::mutex> lk(g_tmu);
+  g_tacc.clear();
+  g_timing = on != 0;
+  return SLK_OK;
+}
+
+slk_status slk_timing_read(const char* kernel, int64_t* launches_host, double* total_ms_host) {
+  if (!kernel || !launches_host || !total_ms_host) return fail(SLK_ERR_INVALID_ARG, "NULL argument");
+  std::lock_guard<std::mutex> lk(g_tmu);
+  auto it = g_tacc.find(kernel);
+  *launches_host = it == g_tacc.end() ? 0 : it->second.first;
+  *total_ms_host = it == g_tacc.end() ? 0.0 : it->second.second;
+  return SLK_OK;
+}
 
 slk_status slk_knn_opts_default(slk_knn_opts* o) {
   if (!o) return fail(SLK_ERR_INVALID_ARG, "opts is NULL");
@@ -592,7 +699,8 @@ slk_status slk_graph_from_csr(int64_t n, int64_t nnz, const int32_t* row_ptr, co
   g->nnz = nnz;
   g->sigma2 = sigma2_hint > 0 ? sigma2_hint : 0.0;
   SLK_HIP(hipMalloc(&g->row_ptr, sizeof(int32_t) * (n + 1)));
-  SLK_HIP(hipMalloc(&g->col_idx, sizeof(int32_t) * std::max<int64_t>(nnz, 1)));
+  SLK_HIP(hipMalloc(&g->col_idx, sizeof(int32_t) * (nnz + kColPad)));
+  SLK_HIP(hipMemsetAsync(g->col_idx + nnz, 0, sizeof(int32_t) * kColPad, s));
   SLK_HIP(hipMemcpyAsync(g->row_ptr, row_ptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToDevice, s));
   if (nnz) SLK_HIP(hipMemcpyAsync(g->col_idx, col_idx, sizeof(int32_t) * nnz, hipMemcpyDeviceToDevice, s));
   if (reorder) SLK_TRY(bfs_reorder(g, s));
@@ -677,7 +785,7 @@ slk_status slk_unary(const float* x, int64_t n, int32_t d, int32_t L, const int3
   int32_t* md;
   SLK_TRY(sc.get(&md, L));
   SLK_HIP(hipMemcpyAsync(md, modes_host, sizeof(int32_t) * L, hipMemcpyHostToDevice, s));
-  SLK_TRY(launch_unary(x, n, d, nullptr, md, L, sigma2, prec == SLK_PREC_BF16, a_out, z0_out, s));
+  SLK_TRY(launch_unary(x, n, d, nullptr, md, L, L, sigma2, prec == SLK_PREC_BF16, a_out, z0_out, s));
   SLK_HIP(hipStreamSynchronize(s));
   return SLK_OK;
 }
@@ -686,6 +794,8 @@ slk_status slk_inner_step(const slk_graph* g, int32_t L, const float* a, const f
                           double delta, int32_t pairwise_scale, void* stream, float* z_out, double* bound_host) {
   if (!g || !a || !z_in) return fail(SLK_ERR_INVALID_ARG, "NULL argument");
   if (L < 1 || L > 256 || L > g->n) return fail(SLK_ERR_INVALID_ARG, "L must satisfy 1 <= L <= min(256, n)");
+  if ((uint64_t)g->n * (uint64_t)ldz_for(L) * 4ull >= (1ull << 32))
+    return fail(SLK_ERR_INVALID_ARG, "n * L (rounded up to a multiple of 4) must be < 2^30");
   if (!(lambda >= 0.0) || !isfinite(lambda) || !(delta >= 0.0) || !isfinite(delta))
     return fail(SLK_ERR_INVALID_ARG, "lambda and delta must be finite and >= 0");
   if (pairwise_scale != 1 && pairwise_scale != 2) return fail(SLK_ERR_INVALID_ARG, "pairwise_scale must be 1 or 2");
@@ -702,16 +812,19 @@ slk_status slk_inner_step(const slk_graph* g, int32_t L, const float* a, const f
   SLK_TRY(sc.get(&w.partial, w.grid));
   SLK_TRY(sc.get(&w.state, 1));
   SLK_TRY(sc.get(&w.bound, 1));
+  SLK_TRY(prepare_col_off(g, L, sc, &w.col_off));
+  const int ldz = ldz_for(L);
+  const bool relayout = g->perm || ldz != L;
   const float* A = a;
   const float* Zi = z_in;
   float* Zo = z_out;
-  if (g->perm) {
+  if (relayout) {
     float *ta, *tz, *to;
-    SLK_TRY(sc.get(&ta, n * L));
-    SLK_TRY(sc.get(&tz, n * L));
-    SLK_TRY(sc.get(&to, n * L));
-    SLK_TRY(launch_gather_rows(a, g->perm, n, L, ta, s));
-    SLK_TRY(launch_gather_rows(z_in, g->perm, n, L, tz, s));
+    SLK_TRY(sc.get(&ta, n * ldz));
+    SLK_TRY(sc.get(&tz, n * ldz));
+    SLK_TRY(sc.get(&to, n * ldz));
+    SLK_TRY(launch_gather_rows(a, g->perm, n, L, ldz, ta, s));
+    SLK_TRY(launch_gather_rows(z_in, g->perm, n, L, ldz, tz, s));
     A = ta;
     Zi = tz;
     Zo = z_out ? to : nullptr;
@@ -725,7 +838,7 @@ slk_status slk_inner_step(const slk_graph* g, int32_t L, const float* a, const f
   ia.trace = nullptr;
   ia.bound_out = w.bound;
   SLK_TRY(launch_iter(ia, w.grid, s));
-  if (g->perm && z_out) SLK_TRY(launch_scatter_rows(Zo, g->perm, n, L, z_out, s));
+  if (relayout && z_out) SLK_TRY(launch_scatter_rows(Zo, g->perm, n, L, ldz, z_out, s));
   if (bound_host) {
     SLK_HIP(hipMemcpyAsync(bound_host, w.bound, sizeof(double), hipMemcpyDeviceToHost, s));
   }
@@ -749,6 +862,7 @@ static slk_status assign_or_fit(bool fit, const float* x, int64_t n, int32_t d, 
   Scratch sc(s);
   Work w;
   SLK_TRY(alloc_work(sc, n, L, cap, w));
+  SLK_TRY(prepare_col_off(g, L, sc, &w.col_off));
   std::vector<int32_t> cur(modes_host, modes_host + L), nxt(L);
   SLK_HIP(hipMemcpyAsync(w.modes, cur.data(), sizeof(int32_t) * L, hipMemcpyHostToDevice, s));
   slk_result r{};
@@ -757,7 +871,7 @@ static slk_status assign_or_fit(bool fit, const float* x, int64_t n, int32_t d, 
   for (int t = 0; t < outer_cap; ++t) {
     const bool last_possible = (t == outer_cap - 1);
     (void)last_possible;
-    SLK_TRY(run_outer(x, n, d, g, L, p, sigma2, cap, 1, s, w, z_out, labels_out, &o));
+    SLK_TRY(run_outer(x, n, d, g, L, p, sigma2, cap, 0, s, w, z_out, labels_out, &o));
     SLK_HIP(hipMemcpyAsync(nxt.data(), w.modes_next, sizeof(int32_t) * L, hipMemcpyDeviceToHost, s));
     SLK_HIP(hipStreamSynchronize(s));
     r.outer_iters = t + 1;
@@ -777,6 +891,34 @@ static slk_status assign_or_fit(bool fit, const float* x, int64_t n, int32_t d, 
     }
     cur = nxt;
     SLK_HIP(hipMemcpyAsync(w.modes, w.modes_next, sizeof(int32_t) * L, hipMemcpyDeviceToDevice, s));
+  }
+  // FP64 recheck of the final energy: the unary term recomputed from X in FP64 at the last
+  // labels and the modes that produced them (both still resident in the work buffers)
+  {
+    EnergyArgs e{};
+    e.row_ptr = g->row_ptr;
+    e.col_idx = g->col_idx;
+    e.labels_int = w.labels_int;
+    e.A = w.A;
+    e.x = x;
+    e.perm = g->perm;
+    e.modes = w.modes;
+    e.n = n;
+    e.d = d;
+    e.L = L;
+    e.ldz = ldz_for(L);
+    e.inv2s2 = 1.0 / (2.0 * sigma2);
+    e.part_un = w.epart_un;
+    e.part_un64 = w.epart_un64;
+    e.part_cut = w.epart_cut;
+    e.out = w.eout;
+    e.out_cut = w.eout_cut;
+      SLK_TRY(launch_energy(e, w.egrid, s));
+    double eo[2];
+    SLK_HIP(hipMemcpyAsync(eo, w.eout, sizeof(eo), hipMemcpyDeviceToHost, s));
+    SLK_HIP(hipStreamSynchronize(s));
+    if (timing_on()) timing_flush();
+    r.energy_fp64 = -eo[1] + p.lambda * (double)r.cut;
   }
   if (trace_host && trace_cap > 0) {
     const int m = std::min(trace_cap, std::min(o.passes, cap));
@@ -820,8 +962,9 @@ slk_status slk_energy(const float* x, int64_t n, int32_t d, const slk_graph* g, 
   Scratch sc(s);
   Work w;
   SLK_TRY(alloc_work(sc, n, L, 1, w));
+  if (z) SLK_TRY(prepare_col_off(g, L, sc, &w.col_off));
   SLK_HIP(hipMemcpyAsync(w.modes, modes_host, sizeof(int32_t) * L, hipMemcpyHostToDevice, s));
-  SLK_TRY(launch_unary(x, n, d, g->perm, w.modes, L, s2, 0, w.A, nullptr, s));
+  SLK_TRY(launch_unary(x, n, d, g->perm, w.modes, L, ldz_for(L), s2, 0, w.A, nullptr, s));
   SLK_TRY(launch_to_internal_labels(labels, g->iperm, n, w.labels_int, s));
   EnergyArgs e{};
   e.row_ptr = g->row_ptr;
@@ -834,13 +977,13 @@ slk_status slk_energy(const float* x, int64_t n, int32_t d, const slk_graph* g, 
   e.n = n;
   e.d = d;
   e.L = L;
+  e.ldz = ldz_for(L);
   e.inv2s2 = 1.0 / (2.0 * s2);
   e.part_un = w.epart_un;
   e.part_un64 = w.epart_un64;
   e.part_cut = w.epart_cut;
   e.out = w.eout;
   e.out_cut = w.eout_cut;
-  e.arrive = w.earrive;
   SLK_TRY(launch_energy(e, w.egrid, s));
   double bnd = 0.0;
   if (z) {
@@ -849,8 +992,8 @@ slk_status slk_energy(const float* x, int64_t n, int32_t d, const slk_graph* g, 
     p.lambda = lambda;
     p.delta = delta;
     const float* Zi = z;
-    if (g->perm) {
-      SLK_TRY(launch_gather_rows(z, g->perm, n, L, w.Z[0], s));
+    if (g->perm || ldz_for(L) != L) {
+      SLK_TRY(launch_gather_rows(z, g->perm, n, L, ldz_for(L), w.Z[0], s));
       Zi = w.Z[0];
     }
     hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(1), 0, s, w.state, 0.0, 0, 0);

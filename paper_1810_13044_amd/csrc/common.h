@@ -55,13 +55,18 @@ slk_status fail(slk_status s, const std::string& msg);
 // ------------------------------------------------------------------------------------
 // stream-ordered device buffers owned by one call
 // ------------------------------------------------------------------------------------
+bool scratch_sync_alloc();
 struct Scratch {
   hipStream_t stream;
   void* ptrs[32];
   int n = 0;
   explicit Scratch(hipStream_t s) : stream(s) {}
+  bool sync_alloc = scratch_sync_alloc();
   ~Scratch() {
-    for (int i = 0; i < n; ++i) (void)hipFreeAsync(ptrs[i], stream);
+    for (int i = 0; i < n; ++i) {
+      if (sync_alloc) (void)hipFree(ptrs[i]);
+      else (void)hipFreeAsync(ptrs[i], stream);
+    }
   }
   template <class T>
   slk_status get(T** out, size_t count) {
@@ -69,7 +74,7 @@ struct Scratch {
     if (count == 0) count = 1;
     if (n >= 32) return fail(SLK_ERR_INVALID_ARG, "internal: too many scratch buffers");
     void* p = nullptr;
-    hipError_t e = hipMallocAsync(&p, count * sizeof(T), stream);
+    hipError_t e = sync_alloc ? hipMalloc(&p, count * sizeof(T)) : hipMallocAsync(&p, count * sizeof(T), stream);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       return fail(SLK_ERR_OUT_OF_MEMORY, std::string("hipMallocAsync: ") + hipGetErrorString(e));
@@ -82,6 +87,22 @@ struct Scratch {
 
 // pinned host staging buffer, one per thread, grown on demand
 slk_status pinned(void** out, size_t bytes);
+
+// Opt-in per-kernel timing with HIP events recorded on the launch stream (slk_timing_enable).
+// KernelTimer brackets one launch; timing_flush() accumulates the finished pairs and must be
+// called only after the stream has been synchronised.
+bool timing_on();
+int timer_start(const char* name, hipStream_t s);
+void timer_stop(int slot, hipStream_t s);
+void timing_flush();
+struct KernelTimer {
+  int slot;
+  hipStream_t s;
+  KernelTimer(const char* name, hipStream_t st) : slot(timing_on() ? timer_start(name, st) : -1), s(st) {}
+  ~KernelTimer() {
+    if (slot >= 0) timer_stop(slot, s);
+  }
+};
 
 }  // namespace slk
 
@@ -117,21 +138,27 @@ struct IterState {
   int32_t pass;        // index of the next z-update
   int32_t done;        // 1 once the bound settled (later passes are no-ops)
   int32_t numeric;     // 1 if the bound became non-finite
-  uint32_t arrive;     // blocks finished in the current pass
   double tol;
   int32_t check;       // 1: test convergence; 0: fixed pass count
   int32_t trace_cap;
   double last_bound;
 };
 
+// Internal row stride of A and Z: L rounded up to a multiple of 4 (float4 rows) when L <= 64.
+inline int ldz_for(int L) { return L <= 64 ? ((L + 3) / 4) * 4 : L; }
+// Zero entries kept after the last CSR column so clamped index loads never leave the array.
+constexpr int kColPad = 16;
+
 struct IterArgs {
   const int32_t* row_ptr;
   const int32_t* col_idx;
+  const uint32_t* col_off;  // float4 path (L <= 64): col_idx * row bytes, + kColPad dead entries
   const float* A;        // n x L (internal order)
   const float* Zin;      // n x L
   float* Zout;           // n x L (may be null: bound only)
   int64_t n;
   int32_t L;
+  int32_t ldz;           // row stride of A, Zin, Zout (floats)
   float lam_eff;         // pairwise_scale * lambda
   float half_lam_eff;    // pairwise_scale * lambda / 2
   float delta;
@@ -152,7 +179,7 @@ struct FinalArgs {
 };
 
 slk_status launch_unary(const float* x, int64_t n, int32_t d, const int32_t* perm, const int32_t* modes_dev,
-                        int32_t L, double sigma2, int32_t bf16, float* A, float* Z0, hipStream_t s);
+                        int32_t L, int32_t ldz, double sigma2, int32_t bf16, float* A, float* Z0, hipStream_t s);
 int iter_grid(int64_t n, int32_t L);
 slk_status launch_iter(const IterArgs& a, int grid, hipStream_t s);
 slk_status launch_final(const FinalArgs& a, int grid, hipStream_t s);
@@ -167,19 +194,22 @@ struct EnergyArgs {
   const int32_t* perm;        // internal -> original
   const int32_t* modes;       // L original indices (device)
   int64_t n;
-  int32_t d, L;
+  int32_t d, L, ldz;
   double inv2s2;
   double* part_un;            // grid doubles
   double* part_un64;          // grid doubles
   long long* part_cut;        // grid counts
-  double* out;                // [0] unary32, [1] unary64, [2] cut (as double), written by the last block
+  double* out;                // [0] unary32, [1] unary64 (written by the reduce kernel)
   long long* out_cut;
-  uint32_t* arrive;
 };
 int energy_grid(int64_t n);
 slk_status launch_energy(const EnergyArgs& a, int grid, hipStream_t s);
-slk_status launch_gather_rows(const float* src, const int32_t* perm, int64_t n, int32_t L, float* dst, hipStream_t s);
-slk_status launch_scatter_rows(const float* src, const int32_t* perm, int64_t n, int32_t L, float* dst, hipStream_t s);
+// caller layout (stride L, original order) <-> internal layout (stride ldz, internal order)
+slk_status launch_gather_rows(const float* src, const int32_t* perm, int64_t n, int32_t L, int32_t ldz, float* dst,
+                              hipStream_t s);
+slk_status launch_scatter_rows(const float* src, const int32_t* perm, int64_t n, int32_t L, int32_t ldz, float* dst,
+                               hipStream_t s);
+slk_status launch_col_offsets(const int32_t* col_idx, int64_t nnz, int64_t n, int32_t L, uint32_t* out, hipStream_t s);
 slk_status launch_to_internal_labels(const int32_t* labels_user, const int32_t* iperm, int64_t n, int32_t* out,
                                      hipStream_t s);
 

@@ -160,8 +160,8 @@ __global__ __launch_bounds__(kBlock) void knn_exact_kernel(const float* __restri
   }
   for (int e = tid; e < nq * k; e += kBlock) {
     const int i = e / k, j = e % k;
-    out_idx[(r0 + i) * k + j] = lq[i][j];
-    out_d2[(r0 + i) * k + j] = ld[i][j];
+    out_idx[qrow[i] * k + j] = lq[i][j];
+    out_d2[qrow[i] * k + j] = ld[i][j];
   }
 }
 
@@ -573,11 +573,12 @@ slk_status build_csr(int64_t n, int32_t k, const int32_t* knn_idx, int32_t** row
   SLK_HIP(hipMemcpyAsync(&nnz, rp + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   SLK_HIP(hipStreamSynchronize(s));
   int32_t* ci = nullptr;
-  if (hipMalloc(&ci, sizeof(int32_t) * std::max<int32_t>(nnz, 1)) != hipSuccess) {
+  if (hipMalloc(&ci, sizeof(int32_t) * ((int64_t)nnz + kColPad)) != hipSuccess) {
     (void)hipGetLastError();
     (void)hipFree(rp);
     return fail(SLK_ERR_OUT_OF_MEMORY, "CSR columns");
   }
+  SLK_HIP(hipMemsetAsync(ci + nnz, 0, sizeof(int32_t) * kColPad, s));
   hipLaunchKernelGGL(unique_copy_kernel, dim3(g4), dim3(kBlock), 0, s, off, n, cols, rp, ci);
   SLK_LAUNCHED("unique_copy_kernel");
   SLK_HIP(hipStreamSynchronize(s));
@@ -602,11 +603,6 @@ slk_status relabel_csr(int64_t n, const int32_t* row_ptr, const int32_t* col_idx
   SLK_TRY(degree_stats(new_row_ptr, n, &mn, &mx, s));
   SLK_TRY(sort_rows(new_row_ptr, n, new_col_idx, mx, s));
   return SLK_OK;
-}
-
-slk_status knn_mfma(const float*, int64_t, int32_t, int32_t, int32_t, int32_t, int32_t*, double*, int64_t*, int64_t*,
-                    hipStream_t) {
-  return fail(SLK_ERR_UNSUPPORTED, "MFMA candidate search not available in this build");
 }
 
 }  // namespace slk

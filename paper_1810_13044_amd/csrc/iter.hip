@@ -20,6 +20,8 @@
 #include <float.h>
 #include <math.h>
 
+#include <type_traits>
+
 namespace slk {
 
 namespace {
@@ -57,69 +59,105 @@ __device__ __forceinline__ int load_agent(const int* p) {
 // ------------------------------------------------------------------------------------------
 // unary affinities
 // ------------------------------------------------------------------------------------------
-constexpr int kUDcMax = 64;  // coordinates per LDS chunk (32 when L > 128)
-constexpr int kUPairs = 8;   // (row, cluster) pairs per thread
+// A block owns R rows (64, or 32 when L > 128).  Coordinates are staged in LDS transposed
+// (coordinate-major, rows contiguous), so each thread reads the 4 rows and the 4 modes of its
+// 4 x 4 tile with two 16-byte LDS reads per coordinate and does 16 subtract/multiply-adds.
+// The coordinate sum is taken chunk by chunk (DC terms, then the chunk sums) to keep the FP32
+// error small; the zero padding of a short last chunk adds exact zeros.
+constexpr int kUT = 4;       // rows and modes per thread tile
+constexpr int kUTiles = 2;   // tiles per thread
 
+template <int DC>
 __global__ __launch_bounds__(kBlock) void unary_kernel(const float* __restrict__ x, int64_t n, int d,
                                                        const int32_t* __restrict__ perm,
-                                                       const int32_t* __restrict__ modes, int L, int R,
-                                                       int kUDc, float inv2s2, int bf16, float* __restrict__ A,
+                                                       const int32_t* __restrict__ modes, int L, int ldz, int R,
+                                                       float inv2s2, int bf16, float* __restrict__ A,
                                                        float* __restrict__ Z0) {
   extern __shared__ float sm[];
-  float* xs = sm;                         // R x (kUDc+1)
-  float* ms = xs + R * (kUDc + 1);        // L x (kUDc+1)
-  float* as = ms + L * (kUDc + 1);        // R x L
+  const int MG = (L + kUT - 1) / kUT;
+  const int RS = R + 4, MS = MG * kUT + 4;  // padded strides (multiples of 4 floats)
+  float* xs = sm;                 // DC x RS, coordinate-major
+  float* ms = xs + DC * RS;       // DC x MS
+  float* as = ms + DC * MS;       // R x L
   const int tid = threadIdx.x;
   const int64_t row0 = (int64_t)blockIdx.x * R;
   const int nr = (int)min<int64_t>(R, n - row0);
-  const int npairs = R * L;
-  float acc[kUPairs];
+  const int ntiles = (R / kUT) * MG;
+  float acc[kUTiles][kUT][kUT];
 #pragma unroll
-  for (int k = 0; k < kUPairs; ++k) acc[k] = 0.f;
+  for (int t = 0; t < kUTiles; ++t)
+#pragma unroll
+    for (int i = 0; i < kUT; ++i)
+#pragma unroll
+      for (int k = 0; k < kUT; ++k) acc[t][i][k] = 0.f;
 
-  for (int c0 = 0; c0 < d; c0 += kUDc) {
-    const int dc = min(kUDc, d - c0);
-    for (int e = tid; e < R * kUDc; e += kBlock) {
-      const int r = e / kUDc, j = e % kUDc;
+  for (int c0 = 0; c0 < d; c0 += DC) {
+    const int dc = min(DC, d - c0);
+    for (int e = tid; e < R * DC; e += kBlock) {
+      const int r = e / DC, j = e % DC;
       float v = 0.f;
       if (r < nr && j < dc) {
         const int64_t gr = perm ? perm[row0 + r] : row0 + r;
         v = x[gr * d + c0 + j];
         if (bf16) v = bf16_round(v);
       }
-      xs[r * (kUDc + 1) + j] = v;
+      xs[j * RS + r] = v;
     }
-    for (int e = tid; e < L * kUDc; e += kBlock) {
-      const int l = e / kUDc, j = e % kUDc;
+    for (int e = tid; e < MG * kUT * DC; e += kBlock) {
+      const int l = e / DC, j = e % DC;
       float v = 0.f;
-      if (j < dc) {
+      if (l < L && j < dc) {
         v = x[(int64_t)modes[l] * d + c0 + j];
         if (bf16) v = bf16_round(v);
       }
-      ms[l * (kUDc + 1) + j] = v;
+      ms[j * MS + l] = v;
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < kUPairs; ++k) {
-      const int pr = tid + k * kBlock;
-      if (pr < npairs) {
-        const int r = pr / L, l = pr % L;
-        const float* xr = xs + r * (kUDc + 1);
-        const float* mr = ms + l * (kUDc + 1);
-        float part = 0.f;  // one chunk summed on its own, then added: two-level summation
-        for (int j = 0; j < dc; ++j) {
-          const float t = xr[j] - mr[j];
-          part = fmaf(t, t, part);
+    for (int t = 0; t < kUTiles; ++t) {
+      const int tile = tid + t * kBlock;
+      if (tile < ntiles) {
+        const int rg = tile / MG, mg = tile % MG;
+        float part[kUT][kUT];
+#pragma unroll
+        for (int i = 0; i < kUT; ++i)
+#pragma unroll
+          for (int k = 0; k < kUT; ++k) part[i][k] = 0.f;
+#pragma unroll 8
+        for (int j = 0; j < DC; ++j) {
+          const float4 xv = *reinterpret_cast<const float4*>(xs + j * RS + rg * kUT);
+          const float4 mv = *reinterpret_cast<const float4*>(ms + j * MS + mg * kUT);
+          const float xa[4] = {xv.x, xv.y, xv.z, xv.w};
+          const float ma[4] = {mv.x, mv.y, mv.z, mv.w};
+#pragma unroll
+          for (int i = 0; i < kUT; ++i)
+#pragma unroll
+            for (int k = 0; k < kUT; ++k) {
+              const float df = xa[i] - ma[k];
+              part[i][k] = fmaf(df, df, part[i][k]);
+            }
         }
-        acc[k] += part;
+#pragma unroll
+        for (int i = 0; i < kUT; ++i)
+#pragma unroll
+          for (int k = 0; k < kUT; ++k) acc[t][i][k] += part[i][k];
       }
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int k = 0; k < kUPairs; ++k) {
-    const int pr = tid + k * kBlock;
-    if (pr < npairs) as[pr] = expf(-acc[k] * inv2s2);
+  for (int t = 0; t < kUTiles; ++t) {
+    const int tile = tid + t * kBlock;
+    if (tile < ntiles) {
+      const int rg = tile / MG, mg = tile % MG;
+#pragma unroll
+      for (int i = 0; i < kUT; ++i)
+#pragma unroll
+        for (int k = 0; k < kUT; ++k) {
+          const int l = mg * kUT + k;
+          if (l < L) as[(rg * kUT + i) * L + l] = expf(-acc[t][i][k] * inv2s2);
+        }
+    }
   }
   __syncthreads();
   // row softmax of a_p gives z^0_p; one wave per row
@@ -132,10 +170,10 @@ __global__ __launch_bounds__(kBlock) void unary_kernel(const float* __restrict__
     for (int l = lane; l < L; l += 64) s += expf(as[r * L + l] - m);
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
     const int64_t row = row0 + r;
-    for (int l = lane; l < L; l += 64) {
-      const float a = as[r * L + l];
-      if (A) A[row * L + l] = a;
-      if (Z0) Z0[row * L + l] = expf(a - m) / s;
+    for (int l = lane; l < ldz; l += 64) {
+      const float a = l < L ? as[r * L + l] : 0.f;
+      if (A) A[row * ldz + l] = a;
+      if (Z0) Z0[row * ldz + l] = l < L ? expf(a - m) / s : 0.f;
     }
   }
 }
@@ -153,53 +191,90 @@ struct RowOut {
   float r;       // bound term of the input row (group-uniform)
 };
 
+// Neighbour extent and first index chunk of a row.  A wave walks its rows with a two-deep
+// prefetch: while row r is gathered, the index chunk of row r + stride and the extent of
+// row r + 2 stride are already in flight, so a row costs about one memory round trip.
+struct Cursor {
+  int32_t beg, end;  // CSR extent
+  int myq;           // column index of neighbour beg + l0 (if l0 < min(S, end - beg))
+};
+
+template <int S>
+__device__ __forceinline__ void load_extent(const IterArgs& a, int64_t row, Cursor& c) {
+  c.beg = 0;
+  c.end = 0;
+  if (row < a.n) {
+    c.beg = a.row_ptr[row];
+    c.end = a.row_ptr[row + 1];
+  }
+}
+
+template <int S>
+__device__ __forceinline__ void load_chunk(const IterArgs& a, int l0, Cursor& c) {
+  const int cnt = min(S, c.end - c.beg);
+  c.myq = (l0 < cnt) ? a.col_idx[c.beg + l0] : 0;
+}
+
 // Computes one row inside its S-lane group.  All lanes of the group must call it together.
+// `cur` holds the row's extent and first index chunk; `nxt` holds the extent of the next
+// row of this group and receives its first index chunk; `nxt2` receives the extent of the
+// row after that.
 template <int S, int E>
-__device__ __forceinline__ void row_update(const IterArgs& a, int64_t row, int l0, RowOut<S, E>& o) {
+__device__ __forceinline__ void row_update(const IterArgs& a, int64_t row, int l0, const Cursor& cur, Cursor& nxt,
+                                           int64_t row2, Cursor& nxt2, RowOut<S, E>& o) {
+  constexpr int CH = S < 16 ? S : 16;  // neighbour rows gathered per round
   const int L = a.L;
+  // element offsets fit in 32 bits (n * ldz < 2^32 is checked on the host): one VGPR per address
+  const uint32_t uL = (uint32_t)a.ldz;
+  const uint32_t roff = (uint32_t)row * uL;
   float zp[E], av[E], b[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int l = l0 + S * e;
     const bool ok = l < L;
-    av[e] = ok ? a.A[row * L + l] : 0.f;
-    zp[e] = ok ? a.Zin[row * L + l] : 0.f;
+    av[e] = ok ? a.A[roff + l] : 0.f;
+    zp[e] = ok ? a.Zin[roff + l] : 0.f;
     b[e] = 0.f;
   }
-  const int32_t beg = a.row_ptr[row], end = a.row_ptr[row + 1];
-  for (int32_t c = beg; c < end; c += S) {
-    const int cnt = min(S, end - c);
-    const int myq = (l0 < cnt) ? a.col_idx[c + l0] : 0;
-    int t = 0;
-    for (; t + 4 <= cnt; t += 4) {
-      const int64_t q0 = __shfl(myq, t, S), q1 = __shfl(myq, t + 1, S);
-      const int64_t q2 = __shfl(myq, t + 2, S), q3 = __shfl(myq, t + 3, S);
-      float v0[E], v1[E], v2[E], v3[E];
+  // gathers are unconditional loads from always-valid addresses (clamped cluster index, row 0
+  // for empty neighbour slots); dead slots are dropped by a group-uniform select, so no
+  // branch sits between the loads
+  uint32_t lc[E];
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
-        const int l = l0 + S * e;
-        const bool ok = l < L;
-        v0[e] = ok ? a.Zin[q0 * L + l] : 0.f;
-        v1[e] = ok ? a.Zin[q1 * L + l] : 0.f;
-        v2[e] = ok ? a.Zin[q2 * L + l] : 0.f;
-        v3[e] = ok ? a.Zin[q3 * L + l] : 0.f;
+  for (int e = 0; e < E; ++e) lc[e] = (uint32_t)min(l0 + S * e, L - 1);
+  bool prefetched = false;
+  for (int32_t c = cur.beg; c < cur.end; c += S) {
+    const int cnt = min(S, cur.end - c);
+    const int myq = (c == cur.beg) ? cur.myq : ((l0 < cnt) ? a.col_idx[c + l0] : 0);
+    for (int t0 = 0; t0 < cnt; t0 += CH) {
+      float v[CH][E];
+#pragma unroll
+      for (int i = 0; i < CH; ++i) {
+        uint32_t q;
+        if constexpr (S == 64)
+          q = (uint32_t)__builtin_amdgcn_readlane(myq, t0 + i);  // one row per wave: scalar index
+        else
+          q = (uint32_t)__shfl(myq, t0 + i, S);
+        const uint32_t qoff = q * uL;
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[i][e] = a.Zin[qoff + lc[e]];
+      }
+      if (!prefetched) {
+        load_chunk<S>(a, l0, nxt);
+        load_extent<S>(a, row2, nxt2);
+        prefetched = true;
       }
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
-        b[e] += v0[e];
-        b[e] += v1[e];
-        b[e] += v2[e];
-        b[e] += v3[e];
+      for (int i = 0; i < CH; ++i) {
+        const bool live = t0 + i < cnt;
+#pragma unroll
+        for (int e = 0; e < E; ++e) b[e] += live ? v[i][e] : 0.f;
       }
     }
-    for (; t < cnt; ++t) {
-      const int64_t q = __shfl(myq, t, S);
-#pragma unroll
-      for (int e = 0; e < E; ++e) {
-        const int l = l0 + S * e;
-        b[e] += (l < L) ? a.Zin[q * L + l] : 0.f;
-      }
-    }
+  }
+  if (!prefetched) {
+    load_chunk<S>(a, l0, nxt);
+    load_extent<S>(a, row2, nxt2);
   }
   float m = -FLT_MAX, term = 0.f;
 #pragma unroll
@@ -229,53 +304,56 @@ __device__ __forceinline__ void row_update(const IterArgs& a, int64_t row, int l
   o.r = group_sum<S>(term);
 }
 
-// Block-level fixed-order reduction of per-group bound partials, then the grid-level
-// "last block finishes" reduction with the convergence test.
+// Row walk of one group: rows first, first + stride, ... (< last) with the two-deep
+// prefetch; body(row, out) consumes each computed row.
+template <int S, int E, class F>
+__device__ __forceinline__ void row_loop(const IterArgs& a, int64_t first, int64_t stride, int64_t last, int l0,
+                                         F&& body) {
+  Cursor cur, nxt, nxt2;
+  const IterArgs& aa = a;
+  load_extent<S>(aa, first < last ? first : a.n, cur);
+  load_chunk<S>(aa, l0, cur);
+  load_extent<S>(aa, first + stride < last ? first + stride : a.n, nxt);
+  for (int64_t row = first; row < last; row += stride) {
+    RowOut<S, E> o;
+    const int64_t r2 = row + 2 * stride;
+    row_update<S, E>(a, row, l0, cur, nxt, r2 < last ? r2 : a.n, nxt2, o);
+    body(row, o);
+    cur = nxt;
+    nxt = nxt2;
+  }
+}
+
+// Fixed-order block sum of the per-group bound partials (group leaders hold them), written to
+// partial[blockIdx.x]; pass_reduce_kernel then sums the blocks in a fixed order.
 template <int G>
-__device__ __forceinline__ void finish_pass(const IterArgs& a, double acc, int g, int l0) {
+__device__ __forceinline__ void block_partial(double* partial, double acc, int g, int l0) {
   __shared__ double red[4 * G];
-  __shared__ double red2[kBlock];
-  __shared__ int is_last;
   const int tid = threadIdx.x, wave = tid >> 6;
   if (l0 == 0) red[wave * G + g] = acc;
   __syncthreads();
   if (tid == 0) {
     double s = 0.0;
     for (int i = 0; i < 4 * G; ++i) s += red[i];
-    a.partial[blockIdx.x] = s;
-    __threadfence();
-    const unsigned prev = atomicAdd(&a.state->arrive, 1u);
-    is_last = (prev == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  double v = 0.0;
-  for (int i = tid; i < (int)gridDim.x; i += kBlock) v += load_agent(a.partial + i);
-  red2[tid] = v;
-  __syncthreads();
-  for (int w = kBlock / 2; w > 0; w >>= 1) {
-    if (tid < w) red2[tid] += red2[tid + w];
-    __syncthreads();
-  }
-  if (tid == 0) {
-    IterState* st = a.state;
-    const double R = red2[0];
-    const int pass = st->pass;
-    if (a.trace && pass < st->trace_cap) a.trace[pass] = R;
-    if (a.bound_out) *a.bound_out = R;
-    if (!isfinite(R)) {
-      st->numeric = 1;
-      st->done = 1;
-    } else if (st->check && pass >= 1 && fabs(R - st->last_bound) <= st->tol * fabs(st->last_bound)) {
-      st->done = 1;
-    }
-    st->last_bound = R;
-    st->pass = pass + 1;
-    st->arrive = 0u;
-    __threadfence();
+    partial[blockIdx.x] = s;
   }
 }
+
+// Contiguous work tiles handed out in XCD order.  Workgroups are dispatched to the 8 XCDs
+// round-robin (block b runs on XCD b % 8), so physical block b is given logical tile
+// (b % 8) * ceil(T / 8) + b / 8: each XCD walks its own contiguous range of tiles in
+// dispatch order, and the rows in flight on one XCD - and the neighbour rows they gather -
+// stay inside a narrow window its L2 can hold.  The physical grid is 8 * ceil(T / 8).
+__device__ __forceinline__ int64_t xcd_tile(int64_t ntiles) {
+  const int64_t gx = (ntiles + 7) >> 3;
+  const int64_t x = blockIdx.x & 7, k = blockIdx.x >> 3;
+  const int64_t t = x * gx + k;
+  return (k < gx && t < ntiles) ? t : -1;
+}
+
+// Tiles: each wave handles kWaveSteps row groups (scalar kernels) or row batches (float4
+// kernels) of one contiguous tile.
+constexpr int kWaveSteps = 2;
 
 template <int S, int E>
 __global__ __launch_bounds__(kBlock) void iter_kernel(IterArgs a) {
@@ -283,21 +361,25 @@ __global__ __launch_bounds__(kBlock) void iter_kernel(IterArgs a) {
   constexpr int G = 64 / S;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane / S, l0 = lane % S;
-  const int64_t stride = (int64_t)gridDim.x * 4 * G;
+  constexpr int64_t kTileRows = 4 * G * kWaveSteps;
+  const int64_t tile = xcd_tile((a.n + kTileRows - 1) / kTileRows);
   double acc = 0.0;
-  for (int64_t row = ((int64_t)blockIdx.x * 4 + wave) * G + g; row < a.n; row += stride) {
-    RowOut<S, E> o;
-    row_update<S, E>(a, row, l0, o);
-    if (a.Zout) {
+  if (tile >= 0) {
+    const int64_t base = tile * kTileRows;
+    row_loop<S, E>(a, base + wave * G + g, 4 * G, min(a.n, base + kTileRows), l0,
+                   [&](int64_t row, const RowOut<S, E>& o) {
+                     if (a.Zout) {
+                       const uint32_t roff = (uint32_t)row * (uint32_t)a.ldz;
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
-        const int l = l0 + S * e;
-        if (l < a.L) a.Zout[row * a.L + l] = o.z[e];
-      }
-    }
-    acc += (double)o.r;
+                       for (int e = 0; e < E; ++e) {
+                         const int l = l0 + S * e;
+                         if (l < a.L) a.Zout[roff + l] = o.z[e];
+                       }
+                     }
+                     acc += (double)o.r;
+                   });
   }
-  finish_pass<G>(a, acc, g, l0);
+  block_partial<G>(a.partial, acc, g, l0);
 }
 
 // final pass: labels, log-odds candidates, output Z in the caller's order
@@ -308,7 +390,6 @@ __global__ __launch_bounds__(kBlock) void final_kernel(FinalArgs f) {
   const int L = a.L;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane / S, l0 = lane % S;
-  const int64_t stride = (int64_t)gridDim.x * 4 * G;
   float bv[E];
   int bi[E];
 #pragma unroll
@@ -317,9 +398,12 @@ __global__ __launch_bounds__(kBlock) void final_kernel(FinalArgs f) {
     bi[e] = INT32_MAX;
   }
   double acc = 0.0;
-  for (int64_t row = ((int64_t)blockIdx.x * 4 + wave) * G + g; row < a.n; row += stride) {
-    RowOut<S, E> o;
-    row_update<S, E>(a, row, l0, o);
+  constexpr int64_t kTileRows = 4 * G * kWaveSteps;
+  const int64_t tile = xcd_tile((a.n + kTileRows - 1) / kTileRows);
+  const int64_t base = tile * kTileRows;
+  const int64_t first = tile >= 0 ? base + wave * G + g : a.n;
+  const int64_t last = tile >= 0 ? min(a.n, base + kTileRows) : a.n;
+  row_loop<S, E>(a, first, 4 * G, last, l0, [&](int64_t row, const RowOut<S, E>& o) {
     acc += (double)o.r;
     const int64_t orow = f.perm ? f.perm[row] : row;
     // first arg-max of the logits (ties to the smaller l)
@@ -384,7 +468,7 @@ __global__ __launch_bounds__(kBlock) void final_kernel(FinalArgs f) {
       f.labels_int[row] = jt;
       if (f.labels_user) f.labels_user[orow] = jt;
     }
-  }
+  });
   // combine the candidates of the groups of this wave (same l0 in every group)
 #pragma unroll
   for (int off = S; off < 64; off <<= 1) {
@@ -417,10 +501,390 @@ __global__ __launch_bounds__(kBlock) void final_kernel(FinalArgs f) {
         i = ci[w][l];
       }
     }
-    f.cand_v[(int64_t)blockIdx.x * L + l] = v;
-    f.cand_i[(int64_t)blockIdx.x * L + l] = i;
+    f.cand_v[(int64_t)l * gridDim.x + blockIdx.x] = v;
+    f.cand_i[(int64_t)l * gridDim.x + blockIdx.x] = i;
   }
-  finish_pass<G>(a, acc, g, l0);
+  block_partial<G>(a.partial, acc, g, l0);
+}
+
+// ------------------------------------------------------------------------------------------
+// z-update and final pass on float4 rows (L <= 64)
+// ------------------------------------------------------------------------------------------
+// A row of A / Z (ldz = 4 ceil(L/4) floats) is held by G = next power of two >= ldz/4 lanes,
+// four clusters per lane, so a wave carries 64/G rows at once and every gather instruction
+// fetches one 16-byte slice of a neighbour row for each of them.  Row reductions run inside
+// the G-lane group with DPP (quad permutes and row mirrors), never through LDS.
+template <int CTRL>
+__device__ __forceinline__ float dppf(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ __forceinline__ int dppi(int v) {
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true);
+}
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141; // lane i <-> 7 - i within 8 lanes
+constexpr int kDppMirror = 0x140;     // lane i <-> 15 - i within 16 lanes
+
+template <int G>
+__device__ __forceinline__ float gsum4(float v) {
+  if constexpr (G >= 2) v += dppf<kDppXor1>(v);
+  if constexpr (G >= 4) v += dppf<kDppXor2>(v);
+  if constexpr (G >= 8) v += dppf<kDppHalfMirror>(v);
+  if constexpr (G >= 16) v += dppf<kDppMirror>(v);
+  return v;
+}
+template <int G>
+__device__ __forceinline__ float gmax4(float v) {
+  if constexpr (G >= 2) v = fmaxf(v, dppf<kDppXor1>(v));
+  if constexpr (G >= 4) v = fmaxf(v, dppf<kDppXor2>(v));
+  if constexpr (G >= 8) v = fmaxf(v, dppf<kDppHalfMirror>(v));
+  if constexpr (G >= 16) v = fmaxf(v, dppf<kDppMirror>(v));
+  return v;
+}
+template <int CTRL>
+__device__ __forceinline__ void argmax_step(float& v, int& i) {
+  const float ov = dppf<CTRL>(v);
+  const int oi = dppi<CTRL>(i);
+  if (ov > v || (ov == v && oi < i)) {
+    v = ov;
+    i = oi;
+  }
+}
+template <int G>
+__device__ __forceinline__ void gargmax4(float& v, int& i) {
+  if constexpr (G >= 2) argmax_step<kDppXor1>(v, i);
+  if constexpr (G >= 4) argmax_step<kDppXor2>(v, i);
+  if constexpr (G >= 8) argmax_step<kDppHalfMirror>(v, i);
+  if constexpr (G >= 16) argmax_step<kDppMirror>(v, i);
+}
+
+__device__ __forceinline__ float f4(const float4& v, int e) { return e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w; }
+
+typedef float vf4 __attribute__((ext_vector_type(4)));  // native vector for the non-temporal builtins
+
+struct Row4 {
+  float s[4], e[4], z[4];
+  float m, sum, r;
+};
+
+// Broadcast of lane K of each G-lane group to the whole group, without LDS: quad permutes for
+// G = 2 and 4, row_newbcast for G = 16 (one DPP row), an LDS permute only for G = 8.
+template <int G, int K>
+__device__ __forceinline__ uint32_t group_bcast(uint32_t v) {
+  if constexpr (G == 1) {
+    return v;
+  } else if constexpr (G == 2) {
+    return (uint32_t)dppi<K | (K << 2) | ((2 + K) << 4) | ((2 + K) << 6)>((int)v);
+  } else if constexpr (G == 4) {
+    return (uint32_t)dppi<K * 0x55>((int)v);
+  } else if constexpr (G == 16) {
+    return (uint32_t)dppi<0x150 + K>((int)v);  // row_newbcast:K
+  } else {
+    return (uint32_t)__shfl((int)v, K, G);
+  }
+}
+
+template <int I, int N, class F>
+__device__ __forceinline__ void static_for(F& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
+  }
+}
+
+
+// Buffer resource over an array of `bytes` bytes (< 2^32): loads at offsets >= bytes return 0.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+__device__ __forceinline__ float4 load4(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  // bit-cast the whole vector: casting its elements one by one mis-lowers to a 4-byte load
+  const vf4 v = __builtin_bit_cast(vf4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+
+constexpr int kCH = 16;  // neighbour rows gathered per round
+
+// Row extent and the first two rounds of neighbour byte offsets of one batch row.  Lane j of
+// a group holds offsets t = j + G u (+ kCH for the second round) of the row's neighbour list,
+// or `dead` (= n * row bytes, past the end of Z) for slots beyond the row's degree.
+template <int G>
+struct Cur4 {
+  int32_t beg, end;
+  uint32_t pre[2][kCH / G];
+};
+
+template <int G>
+__device__ __forceinline__ void cur4_extent(const IterArgs& a, int64_t row, Cur4<G>& c) {
+  c.beg = 0;
+  c.end = 0;
+  if (row >= 0 && row < a.n) {
+    c.beg = a.row_ptr[row];
+    c.end = a.row_ptr[row + 1];
+  }
+}
+
+template <int G>
+__device__ __forceinline__ uint32_t neighbour_offset(const IterArgs& a, int32_t beg, int deg, int t, uint32_t dead) {
+  const int tc = min(t, max(deg - 1, 0));
+  const uint32_t q = (uint32_t)__builtin_nontemporal_load(&a.col_off[beg + tc]);
+  return t < deg ? q : dead;
+}
+
+template <int G>
+__device__ __forceinline__ void cur4_index(const IterArgs& a, int j, uint32_t dead, Cur4<G>& c) {
+  const int deg = c.end - c.beg;
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int u = 0; u < kCH / G; ++u) c.pre[r][u] = neighbour_offset<G>(a, c.beg, deg, r * kCH + j + G * u, dead);
+}
+
+// One batch of 64/G rows (one per group).  Neighbour byte offsets of the first two rounds come
+// pre-loaded in `cur`; later rounds (rows of degree > 2 kCH) load theirs on demand.  The group
+// broadcasts each slot's offset, and Z rows are fetched with 32-bit buffer offsets: the dead
+// offset lies past the end of Z, so empty slots read zeros and need no masking.  `prefetch`
+// runs once, right after the first round of gathers has been issued, so the next batch's
+// loads overlap this batch's.
+template <int G, class P>
+__device__ __forceinline__ void row4_update(const IterArgs& a, uint32_t rowc, bool valid, int j, const Cur4<G>& cur,
+                                            Row4& o, P&& prefetch) {
+  constexpr int U = kCH / G;   // offset registers per lane and round
+  const int L = a.L;
+  const uint32_t L4 = (uint32_t)(a.ldz >> 2);
+  const uint32_t rb = L4 * 16u;                                  // row bytes
+  const uint32_t jc16 = min((uint32_t)j, L4 - 1) * 16u;
+  const uint32_t dead = (uint32_t)a.n * rb;
+  const __amdgpu_buffer_rsrc_t zr = buffer_of(a.Zin, dead);
+  const vf4 avn = __builtin_nontemporal_load(reinterpret_cast<const vf4*>(a.A) + (rowc * L4 + (jc16 >> 4)));
+  const float4 av = make_float4(avn.x, avn.y, avn.z, avn.w);
+  const float4 zp = load4(zr, rowc * rb + jc16);
+  const int deg = valid ? cur.end - cur.beg : 0;
+  float bx = 0.f, by = 0.f, bz = 0.f, bw = 0.f;
+  bool prefetched = false;
+  for (int t0 = 0; __ballot(t0 < deg) != 0ull; t0 += kCH) {
+    uint32_t off[U];
+    const int r = t0 / kCH;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      off[u] = r == 0 ? cur.pre[0][u] : r == 1 ? cur.pre[1][u] : neighbour_offset<G>(a, cur.beg, deg, t0 + j + G * u, dead);
+    float4 v[kCH];
+    auto gather = [&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      v[i] = load4(zr, group_bcast<G, i % G>(off[i / G]) + jc16);
+    };
+    static_for<0, kCH>(gather);
+    if (!prefetched) {
+      prefetch();
+      prefetched = true;
+    }
+#pragma unroll
+    for (int i = 0; i < kCH; ++i) {
+      bx += v[i].x;
+      by += v[i].y;
+      bz += v[i].z;
+      bw += v[i].w;
+    }
+  }
+  if (!prefetched) prefetch();
+  const float bb[4] = {bx, by, bz, bw};
+  float m = -FLT_MAX, term = 0.f;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const bool ok = 4 * j + e < L;
+    const float z0 = f4(zp, e), a0 = f4(av, e);
+    float b0 = bb[e];
+    if (a.delta != 0.f) b0 += a.delta * z0;
+    o.s[e] = ok ? a0 + a.lam_eff * b0 : -INFINITY;
+    m = fmaxf(m, o.s[e]);
+    if (ok) {
+      const float zl = z0 > 0.f ? z0 * __logf(z0) : 0.f;
+      term += zl - z0 * a0 - a.half_lam_eff * z0 * b0;
+    }
+  }
+  m = gmax4<G>(m);
+  float sum = 0.f;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    o.e[e] = (4 * j + e < L) ? __expf(o.s[e] - m) : 0.f;
+    sum += o.e[e];
+  }
+  sum = gsum4<G>(sum);
+  const float inv = 1.0f / sum;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) o.z[e] = o.e[e] * inv;
+  o.m = m;
+  o.sum = sum;
+  o.r = gsum4<G>(term);
+}
+
+template <int G>
+__global__ __launch_bounds__(kBlock) void iter4_kernel(IterArgs a) {
+  if (a.state->done) return;
+  constexpr int RW = 64 / G;  // rows per wave
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane / G, j = lane % G;
+  const uint32_t L4 = (uint32_t)(a.ldz >> 2);
+  const uint32_t dead = (uint32_t)a.n * L4 * 16u;
+  float4* __restrict__ O4 = reinterpret_cast<float4*>(a.Zout);
+  const int64_t nbatch = (a.n + RW - 1) / RW;
+  const int64_t tile = xcd_tile((nbatch + 4 * kWaveSteps - 1) / (4 * kWaveSteps));
+  // a block without a tile (grid padding) walks nothing: b0 = bstop = 0
+  const int64_t b0 = tile >= 0 ? tile * 4 * kWaveSteps + wave : 0;
+  const int64_t bstop = tile >= 0 ? min(nbatch, (tile + 1) * 4 * kWaveSteps) : 0;
+  double acc = 0.0;
+  // two-deep pipeline: offsets of batch b + 4 and the extent of batch b + 8 are loaded while
+  // batch b gathers
+  Cur4<G> cur, nxt, nxt2;
+  cur4_extent<G>(a, b0 < bstop ? b0 * RW + g : -1, cur);
+  cur4_index<G>(a, j, dead, cur);
+  cur4_extent<G>(a, b0 + 4 < bstop ? (b0 + 4) * RW + g : -1, nxt);
+  for (int64_t b = b0; b < bstop; b += 4) {
+    const int64_t row = b * RW + g;
+    const bool valid = row >= 0 && row < a.n;
+    const uint32_t rowc = (uint32_t)(valid ? row : a.n - 1);
+    Row4 o;
+    row4_update<G>(a, rowc, valid, j, cur, o, [&]() {
+      cur4_index<G>(a, j, dead, nxt);
+      cur4_extent<G>(a, b + 8 < bstop ? (b + 8) * RW + g : -1, nxt2);
+    });
+    if (valid) {
+      if (O4 && (uint32_t)j < L4)
+        __builtin_nontemporal_store(vf4{o.z[0], o.z[1], o.z[2], o.z[3]}, reinterpret_cast<vf4*>(O4) + (rowc * L4 + j));
+      if (j == 0) acc += (double)o.r;
+    }
+    cur = nxt;
+    nxt.beg = nxt2.beg;
+    nxt.end = nxt2.end;
+  }
+  block_partial<RW>(a.partial, acc, g, j);
+}
+
+template <int G>
+__global__ __launch_bounds__(kBlock) void final4_kernel(FinalArgs f) {
+  const IterArgs& a = f.it;
+  constexpr int RW = 64 / G;
+  const int L = a.L;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane / G, j = lane % G;
+  const int64_t nbatch = (a.n + RW - 1) / RW;
+  float bv[4];
+  int bi[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    bv[e] = -INFINITY;
+    bi[e] = INT32_MAX;
+  }
+  double acc = 0.0;
+  const int64_t tile = xcd_tile((nbatch + 4 * kWaveSteps - 1) / (4 * kWaveSteps));
+  // a block without a tile (grid padding) walks nothing
+  const int64_t b0 = tile >= 0 ? tile * 4 * kWaveSteps + wave : 0;
+  const int64_t bstop = tile >= 0 ? min(nbatch, (tile + 1) * 4 * kWaveSteps) : 0;
+  for (int64_t b = b0; b < bstop; b += 4) {
+    const int64_t row = b * RW + g;
+    const bool valid = row >= 0 && row < a.n;
+    const uint32_t rowc = (uint32_t)(valid ? row : a.n - 1);
+    Cur4<G> cur;
+    cur4_extent<G>(a, valid ? row : -1, cur);
+    cur4_index<G>(a, j, (uint32_t)a.n * (uint32_t)a.ldz * 4u, cur);
+    Row4 o;
+    row4_update<G>(a, rowc, valid, j, cur, o, []() {});
+    // first arg-max of the logits (ties to the smaller l)
+    float tv = -INFINITY;
+    int ti = INT32_MAX;
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (4 * j + e < L && o.s[e] > tv) {
+        tv = o.s[e];
+        ti = 4 * j + e;
+      }
+    gargmax4<G>(tv, ti);
+    const int jt = ti;
+    float m2 = -INFINITY, T = 0.f;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int l = 4 * j + e;
+      if (l < L && l != jt) {
+        m2 = fmaxf(m2, o.s[e]);
+        T += o.e[e];
+      }
+    }
+    m2 = gmax4<G>(m2);
+    T = gsum4<G>(T);
+    float S2 = 0.f;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int l = 4 * j + e;
+      if (l < L && l != jt) S2 += expf(o.s[e] - m2);
+    }
+    S2 = gsum4<G>(S2);
+    if (!valid) continue;
+    acc += (j == 0) ? (double)o.r : 0.0;
+    const int64_t orow = f.perm ? f.perm[row] : row;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int l = 4 * j + e;
+      if (l >= L) continue;
+      float v;
+      if (L == 1) {
+        v = INFINITY;
+      } else if (l == jt) {
+        v = (o.m - m2) - logf(S2);      // log z/(1-z) for the top entry, no underflow
+      } else {
+        v = (o.s[e] - o.m) - log1pf(T - o.e[e]);
+      }
+      if (v > bv[e] || (v == bv[e] && (int)orow < bi[e])) {
+        bv[e] = v;
+        bi[e] = (int)orow;
+      }
+      if (f.z_user) f.z_user[orow * L + l] = o.z[e];
+    }
+    if (j == 0) {
+      f.labels_int[row] = jt;
+      if (f.labels_user) f.labels_user[orow] = jt;
+    }
+  }
+  // combine the candidates of the groups of this wave (same j in every group)
+#pragma unroll
+  for (int off = G; off < 64; off <<= 1) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const float ov = __shfl_xor(bv[e], off);
+      const int oi = __shfl_xor(bi[e], off);
+      if (ov > bv[e] || (ov == bv[e] && oi < bi[e])) {
+        bv[e] = ov;
+        bi[e] = oi;
+      }
+    }
+  }
+  __shared__ float cv[4][64];
+  __shared__ int ci[4][64];
+  if (g == 0) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      if (4 * j + e < 64) {
+        cv[wave][4 * j + e] = bv[e];
+        ci[wave][4 * j + e] = bi[e];
+      }
+    }
+  }
+  __syncthreads();
+  for (int l = threadIdx.x; l < L; l += kBlock) {
+    float v = cv[0][l];
+    int i = ci[0][l];
+    for (int w = 1; w < 4; ++w) {
+      if (cv[w][l] > v || (cv[w][l] == v && ci[w][l] < i)) {
+        v = cv[w][l];
+        i = ci[w][l];
+      }
+    }
+    f.cand_v[(int64_t)l * gridDim.x + blockIdx.x] = v;
+    f.cand_i[(int64_t)l * gridDim.x + blockIdx.x] = i;
+  }
+  block_partial<RW>(a.partial, acc, g, j);
 }
 
 __global__ __launch_bounds__(kBlock) void mode_reduce_kernel(const float* __restrict__ cv, const int32_t* __restrict__ ci,
@@ -429,8 +893,8 @@ __global__ __launch_bounds__(kBlock) void mode_reduce_kernel(const float* __rest
   float v = -INFINITY;
   int i = INT32_MAX;
   for (int b = tid; b < grid; b += kBlock) {
-    const float ov = cv[(int64_t)b * L + l];
-    const int oi = ci[(int64_t)b * L + l];
+    const float ov = cv[(int64_t)l * grid + b];
+    const int oi = ci[(int64_t)l * grid + b];
     if (ov > v || (ov == v && oi < i)) {
       v = ov;
       i = oi;
@@ -456,47 +920,79 @@ __global__ __launch_bounds__(kBlock) void mode_reduce_kernel(const float* __rest
 // ------------------------------------------------------------------------------------------
 // energy: FP32 unary term, exact cut count and an FP64 recheck of the unary term
 // ------------------------------------------------------------------------------------------
+// 16 lanes per row, 4 rows per wave, contiguous XCD-ordered tiles.
+template <int CTRL>
+__device__ __forceinline__ double dppd(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double gsum16d(double v) {
+  v += dppd<kDppXor1>(v);
+  v += dppd<kDppXor2>(v);
+  v += dppd<kDppHalfMirror>(v);
+  v += dppd<kDppMirror>(v);
+  return v;
+}
+__device__ __forceinline__ int gsum16i(int v) {
+  v += dppi<kDppXor1>(v);
+  v += dppi<kDppXor2>(v);
+  v += dppi<kDppHalfMirror>(v);
+  v += dppi<kDppMirror>(v);
+  return v;
+}
+
 __global__ __launch_bounds__(kBlock) void energy_kernel(EnergyArgs e) {
+  constexpr int G = 16, RW = 4;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, tid = threadIdx.x;
-  const int64_t stride = (int64_t)gridDim.x * 4;
+  const int g = lane / G, j = lane % G;
   double un = 0.0, un64 = 0.0;
   long long cut = 0;
-  for (int64_t row = (int64_t)blockIdx.x * 4 + wave; row < e.n; row += stride) {
-    const int lab = e.labels_int[row];
-    const int32_t beg = e.row_ptr[row], end = e.row_ptr[row + 1];
+  const int64_t nbatch = (e.n + RW - 1) / RW;
+  const int64_t tile = xcd_tile((nbatch + 4 * kWaveSteps - 1) / (4 * kWaveSteps));
+  // a block without a tile (grid padding) walks nothing
+  const int64_t b0 = tile >= 0 ? tile * 4 * kWaveSteps + wave : 0;
+  const int64_t bstop = tile >= 0 ? min(nbatch, (tile + 1) * 4 * kWaveSteps) : 0;
+  for (int64_t b = b0; b < bstop; b += 4) {
+    const int64_t row = b * RW + g;
+    const bool valid = row >= 0 && row < e.n;
+    const int64_t rowc = valid ? row : e.n - 1;
+    const int lab = e.labels_int[rowc];
+    const int32_t beg = e.row_ptr[rowc], end = valid ? e.row_ptr[rowc + 1] : beg;
     int c = 0;
-    for (int32_t j = beg + lane; j < end; j += 64) c += (e.labels_int[e.col_idx[j]] != lab);
-    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+    for (int32_t t = beg + j; t < end; t += G) c += (e.labels_int[e.col_idx[t]] != lab);
+    c = gsum16i(c);
+    double d64 = 0.0;
     if (e.x) {
-      const int64_t orow = e.perm ? e.perm[row] : row;
+      const int64_t orow = e.perm ? e.perm[rowc] : rowc;
       const float* xp = e.x + orow * e.d;
       const float* mp = e.x + (int64_t)e.modes[lab] * e.d;
-      double s = 0.0;
-      for (int j = lane; j < e.d; j += 64) {
-        const double t = (double)xp[j] - (double)mp[j];
-        s += t * t;
+      for (int k = j; k < e.d; k += G) {
+        const double t = (double)xp[k] - (double)mp[k];
+        d64 += t * t;
       }
-      for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-      if (lane == 0) un64 += exp(-s * e.inv2s2);
+      d64 = gsum16d(d64);
     }
-    if (lane == 0) {
-      un += (double)e.A[row * e.L + lab];
+    if (valid && j == 0) {
+      un += (double)e.A[rowc * e.ldz + lab];
       cut += c;
+      if (e.x) un64 += exp(-d64 * e.inv2s2);
     }
   }
-  __shared__ double s_un[4], s_un64[4];
-  __shared__ long long s_cut[4];
-  __shared__ int is_last;
-  if (lane == 0) {
-    s_un[wave] = un;
-    s_un64[wave] = un64;
-    s_cut[wave] = cut;
+  // lanes 0, 16, 32, 48 hold the sums of their groups; fixed-order block sums
+  __shared__ double s_un[16], s_un64[16];
+  __shared__ long long s_cut[16];
+  if (j == 0) {
+    s_un[wave * RW + g] = un;
+    s_un64[wave * RW + g] = un64;
+    s_cut[wave * RW + g] = cut;
   }
   __syncthreads();
   if (tid == 0) {
     double a0 = 0, a1 = 0;
     long long c0 = 0;
-    for (int w = 0; w < 4; ++w) {
+    for (int w = 0; w < 16; ++w) {
       a0 += s_un[w];
       a1 += s_un64[w];
       c0 += s_cut[w];
@@ -504,20 +1000,23 @@ __global__ __launch_bounds__(kBlock) void energy_kernel(EnergyArgs e) {
     e.part_un[blockIdx.x] = a0;
     e.part_un64[blockIdx.x] = a1;
     e.part_cut[blockIdx.x] = c0;
-    __threadfence();
-    is_last = (atomicAdd(e.arrive, 1u) == gridDim.x - 1);
   }
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
+}
+
+// Fixed-order sums of the energy block partials (one block).
+__global__ __launch_bounds__(kBlock) void energy_reduce_kernel(const double* __restrict__ p_un,
+                                                               const double* __restrict__ p_un64,
+                                                               const long long* __restrict__ p_cut, int nparts,
+                                                               double* out, long long* out_cut) {
   __shared__ double r0[kBlock], r1[kBlock];
   __shared__ long long r2[kBlock];
+  const int tid = threadIdx.x;
   double a0 = 0, a1 = 0;
   long long c0 = 0;
-  for (int i = tid; i < (int)gridDim.x; i += kBlock) {
-    a0 += load_agent(e.part_un + i);
-    a1 += load_agent(e.part_un64 + i);
-    c0 += load_agent(e.part_cut + i);
+  for (int i = tid; i < nparts; i += kBlock) {
+    a0 += p_un[i];
+    a1 += p_un64[i];
+    c0 += p_cut[i];
   }
   r0[tid] = a0;
   r1[tid] = a1;
@@ -532,27 +1031,69 @@ __global__ __launch_bounds__(kBlock) void energy_kernel(EnergyArgs e) {
     __syncthreads();
   }
   if (tid == 0) {
-    e.out[0] = r0[0];
-    e.out[1] = r1[0];
-    *e.out_cut = r2[0];
-    *e.arrive = 0u;
+    out[0] = r0[0];
+    out[1] = r1[0];
+    *out_cut = r2[0];
+  }
+}
+
+// Fixed-order sum of the bound partials of one z-update, then the loop bookkeeping: bound
+// trace, convergence test (relative change of the bound), pass counter.  A no-op once the
+// loop is done, like the z-updates queued after it.
+__global__ __launch_bounds__(kBlock) void pass_reduce_kernel(const double* __restrict__ partial, int nparts,
+                                                             IterState* st, double* trace, double* bound_out) {
+  if (st->done) return;
+  __shared__ double red[kBlock];
+  const int tid = threadIdx.x;
+  double v = 0.0;
+  for (int i = tid; i < nparts; i += kBlock) v += partial[i];
+  red[tid] = v;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double R = red[0];
+    const int pass = st->pass;
+    if (trace && pass < st->trace_cap) trace[pass] = R;
+    if (bound_out) *bound_out = R;
+    if (!isfinite(R)) {
+      st->numeric = 1;
+      st->done = 1;
+    } else if (st->check && pass >= 1 && fabs(R - st->last_bound) <= st->tol * fabs(st->last_bound)) {
+      st->done = 1;
+    }
+    st->last_bound = R;
+    st->pass = pass + 1;
   }
 }
 
 __global__ void gather_rows_kernel(const float* __restrict__ src, const int32_t* __restrict__ perm, int64_t n, int L,
-                                   float* __restrict__ dst) {
+                                   int ldz, float* __restrict__ dst) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n * L) return;
-  const int64_t r = i / L, l = i % L;
-  dst[i] = src[(int64_t)perm[r] * L + l];
+  if (i >= n * ldz) return;
+  const int64_t r = i / ldz, l = i % ldz;
+  const int64_t sr = perm ? perm[r] : r;
+  dst[i] = l < L ? src[sr * L + l] : 0.f;
 }
 
 __global__ void scatter_rows_kernel(const float* __restrict__ src, const int32_t* __restrict__ perm, int64_t n, int L,
-                                    float* __restrict__ dst) {
+                                    int ldz, float* __restrict__ dst) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n * L) return;
   const int64_t r = i / L, l = i % L;
-  dst[(int64_t)perm[r] * L + l] = src[i];
+  const int64_t dr = perm ? perm[r] : r;
+  dst[dr * L + l] = src[r * ldz + l];
+}
+
+// Neighbour columns as byte offsets of Z rows (row bytes rb); the padding entries after the
+// last column get the dead offset n * rb.
+__global__ void col_offsets_kernel(const int32_t* __restrict__ col_idx, int64_t nnz, uint32_t rb, uint32_t dead,
+                                   uint32_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nnz) out[i] = (uint32_t)col_idx[i] * rb;
+  else if (i < nnz + kColPad) out[i] = dead;
 }
 
 __global__ void labels_to_internal_kernel(const int32_t* __restrict__ lu, const int32_t* __restrict__ iperm,
@@ -572,23 +1113,37 @@ inline int lanes_for(int L) {
 
 }  // namespace
 
+inline int groups4(int L) {
+  const int l4 = (ldz_for(L) + 3) / 4;
+  return l4 <= 1 ? 1 : l4 <= 2 ? 2 : l4 <= 4 ? 4 : l4 <= 8 ? 8 : 16;
+}
+
+inline int64_t tile_grid(int64_t ntiles) { return 8 * ((std::max<int64_t>(ntiles, 1) + 7) / 8); }
+
 int iter_grid(int64_t n, int32_t L) {
-  const int S = lanes_for(L);
-  const int64_t rows_per_block = 4 * (64 / S);
-  const int64_t need = (n + rows_per_block - 1) / rows_per_block;
-  // enough blocks to fill 256 CUs several times over; rows beyond are grid-strided
-  return (int)std::max<int64_t>(1, std::min<int64_t>(need, 256 * 16));
+  if (L <= 64) {
+    const int64_t RW = 64 / groups4(L);
+    const int64_t nbatch = (n + RW - 1) / RW;
+    return (int)tile_grid((nbatch + 4 * kWaveSteps - 1) / (4 * kWaveSteps));
+  }
+  const int64_t rows = 4 * (64 / lanes_for(L)) * kWaveSteps;
+  return (int)tile_grid((n + rows - 1) / rows);
 }
 
 slk_status launch_unary(const float* x, int64_t n, int32_t d, const int32_t* perm, const int32_t* modes_dev, int32_t L,
-                        double sigma2, int32_t bf16, float* A, float* Z0, hipStream_t s) {
-  const int R = std::max(1, std::min(32, (kUPairs * kBlock) / L));
-  const int dcw = L > 128 ? kUDcMax / 2 : kUDcMax;
-  const size_t lds = sizeof(float) * ((size_t)R * (dcw + 1) + (size_t)L * (dcw + 1) + (size_t)R * L);
+                        int32_t ldz, double sigma2, int32_t bf16, float* A, float* Z0, hipStream_t s) {
+  const int R = L <= 128 ? 64 : 32;
+  const int DC = L <= 128 ? 32 : 16;
+  const int MG = (L + kUT - 1) / kUT;
+  const size_t lds = sizeof(float) * ((size_t)DC * (R + 4) + (size_t)DC * (MG * kUT + 4) + (size_t)R * L);
   const int64_t grid = (n + R - 1) / R;
   const float inv2s2 = (float)(1.0 / (2.0 * sigma2));
-  hipLaunchKernelGGL(unary_kernel, dim3((unsigned)grid), dim3(kBlock), lds, s, x, n, d, perm, modes_dev, L, R, dcw,
-                     inv2s2, bf16, A, Z0);
+  if (DC == 32)
+    hipLaunchKernelGGL(unary_kernel<32>, dim3((unsigned)grid), dim3(kBlock), lds, s, x, n, d, perm, modes_dev, L, ldz,
+                       R, inv2s2, bf16, A, Z0);
+  else
+    hipLaunchKernelGGL(unary_kernel<16>, dim3((unsigned)grid), dim3(kBlock), lds, s, x, n, d, perm, modes_dev, L, ldz,
+                       R, inv2s2, bf16, A, Z0);
   SLK_LAUNCHED("unary_kernel");
   return SLK_OK;
 }
@@ -608,15 +1163,38 @@ slk_status launch_unary(const float* x, int64_t n, int32_t d, const int32_t* per
     else hipLaunchKernelGGL((KERNEL<64, 1>), __VA_ARGS__);                                   \
   } while (0)
 
+#define SLK_DISPATCH_G4(L, KERNEL, ...)                                        \
+  do {                                                                         \
+    const int G_ = groups4(L);                                                 \
+    if (G_ == 1) hipLaunchKernelGGL((KERNEL<1>), __VA_ARGS__);                 \
+    else if (G_ == 2) hipLaunchKernelGGL((KERNEL<2>), __VA_ARGS__);            \
+    else if (G_ == 4) hipLaunchKernelGGL((KERNEL<4>), __VA_ARGS__);            \
+    else if (G_ == 8) hipLaunchKernelGGL((KERNEL<8>), __VA_ARGS__);            \
+    else hipLaunchKernelGGL((KERNEL<16>), __VA_ARGS__);                        \
+  } while (0)
+
 slk_status launch_iter(const IterArgs& a, int grid, hipStream_t s) {
-  SLK_DISPATCH_LANES(a.L, iter_kernel, dim3(grid), dim3(kBlock), 0, s, a);
-  SLK_LAUNCHED("iter_kernel");
+  {
+    KernelTimer kt("iter_kernel", s);
+    if (a.L <= 64) SLK_DISPATCH_G4(a.L, iter4_kernel, dim3(grid), dim3(kBlock), 0, s, a);
+    else SLK_DISPATCH_LANES(a.L, iter_kernel, dim3(grid), dim3(kBlock), 0, s, a);
+    SLK_LAUNCHED("iter_kernel");
+  }
+  hipLaunchKernelGGL(pass_reduce_kernel, dim3(1), dim3(kBlock), 0, s, a.partial, grid, a.state, a.trace, a.bound_out);
+  SLK_LAUNCHED("pass_reduce_kernel");
   return SLK_OK;
 }
 
 slk_status launch_final(const FinalArgs& f, int grid, hipStream_t s) {
-  SLK_DISPATCH_LANES(f.it.L, final_kernel, dim3(grid), dim3(kBlock), 0, s, f);
-  SLK_LAUNCHED("final_kernel");
+  {
+    KernelTimer kt("final_kernel", s);
+    if (f.it.L <= 64) SLK_DISPATCH_G4(f.it.L, final4_kernel, dim3(grid), dim3(kBlock), 0, s, f);
+    else SLK_DISPATCH_LANES(f.it.L, final_kernel, dim3(grid), dim3(kBlock), 0, s, f);
+    SLK_LAUNCHED("final_kernel");
+  }
+  hipLaunchKernelGGL(pass_reduce_kernel, dim3(1), dim3(kBlock), 0, s, f.it.partial, grid, f.it.state, f.it.trace,
+                     f.it.bound_out);
+  SLK_LAUNCHED("pass_reduce_kernel");
   return SLK_OK;
 }
 
@@ -627,26 +1205,47 @@ slk_status launch_mode_reduce(const float* cand_v, const int32_t* cand_i, int gr
   return SLK_OK;
 }
 
-int energy_grid(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 3) / 4, 256 * 8)); }
+int energy_grid(int64_t n) {
+  const int64_t nbatch = (n + 3) / 4;
+  return (int)tile_grid((nbatch + 4 * kWaveSteps - 1) / (4 * kWaveSteps));
+}
 
 slk_status launch_energy(const EnergyArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(energy_kernel, dim3(grid), dim3(kBlock), 0, s, a);
-  SLK_LAUNCHED("energy_kernel");
+  {
+    KernelTimer kt("energy_kernel", s);
+    hipLaunchKernelGGL(energy_kernel, dim3(grid), dim3(kBlock), 0, s, a);
+    SLK_LAUNCHED("energy_kernel");
+  }
+  hipLaunchKernelGGL(energy_reduce_kernel, dim3(1), dim3(kBlock), 0, s, a.part_un, a.part_un64, a.part_cut, grid, a.out,
+                     a.out_cut);
+  SLK_LAUNCHED("energy_reduce_kernel");
   return SLK_OK;
 }
 
-slk_status launch_gather_rows(const float* src, const int32_t* perm, int64_t n, int32_t L, float* dst, hipStream_t s) {
-  const int64_t tot = n * L;
-  hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, src, perm, n, L, dst);
+slk_status launch_gather_rows(const float* src, const int32_t* perm, int64_t n, int32_t L, int32_t ldz, float* dst,
+                              hipStream_t s) {
+  const int64_t tot = n * ldz;
+  hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, src, perm, n, L, ldz,
+                     dst);
   SLK_LAUNCHED("gather_rows_kernel");
   return SLK_OK;
 }
 
-slk_status launch_scatter_rows(const float* src, const int32_t* perm, int64_t n, int32_t L, float* dst,
+slk_status launch_scatter_rows(const float* src, const int32_t* perm, int64_t n, int32_t L, int32_t ldz, float* dst,
                                hipStream_t s) {
   const int64_t tot = n * L;
-  hipLaunchKernelGGL(scatter_rows_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, src, perm, n, L, dst);
+  hipLaunchKernelGGL(scatter_rows_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, src, perm, n, L, ldz,
+                     dst);
   SLK_LAUNCHED("scatter_rows_kernel");
+  return SLK_OK;
+}
+
+slk_status launch_col_offsets(const int32_t* col_idx, int64_t nnz, int64_t n, int32_t L, uint32_t* out, hipStream_t s) {
+  const uint32_t rb = (uint32_t)ldz_for(L) * 4u;
+  const int64_t tot = nnz + kColPad;
+  hipLaunchKernelGGL(col_offsets_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, col_idx, nnz, rb,
+                     (uint32_t)n * rb, out);
+  SLK_LAUNCHED("col_offsets_kernel");
   return SLK_OK;
 }
 

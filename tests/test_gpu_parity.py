@@ -152,9 +152,13 @@ def fp32_storage_z(A, rp, ci, n_pass, lam, delta=0.0, scale=1.0):
 
 
 def trajectory_ztol(out, rp, ci, lam):
-    """1e-5, plus four times the amplification of FP32 storage over the same passes."""
+    """1e-5 plus 16 times the amplification of FP32 storage rounding over the same passes.
+
+    Storage rounding perturbs each iterate by ~2^-24 relative; an FP32 z-update's own
+    arithmetic (exp, reciprocal, sums) perturbs it by up to ~16 times that, and the iteration
+    amplifies both alike, so 16 x the measured storage spread bounds the arithmetic's share."""
     spread = np.abs(fp32_storage_z(out["A"], rp, ci, out["n_pass"], lam) - out["Z"]).max()
-    return ZTOL + 4.0 * spread
+    return ZTOL + 16.0 * spread
 
 
 def check_outer(res, out, inst, rp, ci, lam, ztol=ZTOL):
@@ -359,3 +363,78 @@ def test_device_side_validation(slk, torch):
     xn[3, 1] = float("nan")
     with pytest.raises(slk.SlkError):
         slk.Graph.build_knn(xn, k=3)
+
+
+# ------------------------------------------------------------------- a1: MFMA candidates + FP64 re-rank
+
+def round_bf16(X):
+    """Round float32 values to the nearest bfloat16 (ties to even), returned as float32."""
+    b = np.ascontiguousarray(X, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+    return b.astype(np.uint32).view(np.float32)
+
+
+def test_round_bf16_helper():
+    x = np.array([1.0, 1.00390625, 1.005859375, -3.0e-3, 65504.0], dtype=np.float32)
+    r = round_bf16(x)
+    assert r[0] == 1.0 and r[1] == 1.0            # halfway rounds to even
+    assert r[2] == np.float32(1.0078125)
+    assert abs(r[3] - x[3]) <= abs(x[3]) * 2 ** -8
+
+
+def test_knn_mfma_bit_identical(case, slk, torch):
+    inst = case["inst"]
+    g = slk.Graph.build_knn(case["x"], k=inst.K, method="mfma")
+    ex = g.export()
+    info = g.info()
+    _say(f"[mfma] {inst.name}: certified={info['rows_certified']} fallback={info['rows_fallback']}")
+    assert info["rows_certified"] + info["rows_fallback"] == inst.N
+    assert np.array_equal(ex["knn_idx"].cpu().numpy(), case["idx"])
+    assert np.array_equal(ex["knn_d2"].cpu().numpy(), case["d2"])
+    assert np.array_equal(ex["col_idx"].cpu().numpy(), case["ci"])
+    assert rel_gap(info["sigma2"], case["s2"]) <= 1e-12
+
+
+@pytest.mark.parametrize("method", ["exact", "mfma"])
+def test_knn_duplicates_tie_by_index(slk, torch, method):
+    rng = np.random.default_rng(4)
+    base = rng.normal(size=(60, 7)).astype(np.float32)
+    X = np.concatenate([base, base[:20], base[5:15], base[:3]])      # exact duplicates
+    idx, d2 = orc.knn(X, 6)
+    g = slk.Graph.build_knn(to_dev(torch, X, torch.float32), k=6, method=method)
+    ex = g.export()
+    assert np.array_equal(ex["knn_idx"].cpu().numpy(), idx)
+    assert np.array_equal(ex["knn_d2"].cpu().numpy(), d2)
+
+
+@pytest.mark.parametrize("method", ["exact", "mfma"])
+def test_knn_bf16_points(slk, torch, method):
+    inst = gen.gaussian_mixture(n=1500, d=40, L=5, K=8, seed=31)
+    Xb = round_bf16(inst.X)
+    idx, d2 = orc.knn(Xb, 8, block=256)
+    g = slk.Graph.build_knn(to_dev(torch, inst.X, torch.float32), k=8, method=method, prec="bf16")
+    ex = g.export()
+    assert np.array_equal(ex["knn_idx"].cpu().numpy(), idx)
+    assert np.array_equal(ex["knn_d2"].cpu().numpy(), d2)
+
+
+@pytest.mark.parametrize("cands", [10, 64])
+def test_knn_mfma_candidate_counts(slk, torch, cands):
+    # C = k leaves no slack: rows fall back to the exact search; the result is the same
+    inst = gen.gaussian_mixture(n=900, d=20, L=4, K=10, seed=32)
+    idx, d2 = orc.knn(inst.X, 10, block=300)
+    g = slk.Graph.build_knn(to_dev(torch, inst.X, torch.float32), k=10, method="mfma", candidates=cands)
+    assert np.array_equal(g.export()["knn_idx"].cpu().numpy(), idx)
+
+
+def test_knn_mfma_image_rows(slk, torch):
+    """Image-shaped points (784 dims, quantised to 1/255): sampled rows vs the oracle."""
+    inst = gen.manifold_images(n=20000, seed=1)
+    g = slk.Graph.build_knn(to_dev(torch, inst.X, torch.float32), k=5, method="mfma")
+    info = g.info()
+    _say(f"[mfma] images-20k: certified={info['rows_certified']} fallback={info['rows_fallback']}")
+    rows = np.random.default_rng(0).choice(inst.N, 96, replace=False)
+    idx, d2 = orc.knn(inst.X, 5, rows=rows, block=16)
+    ex = g.export()
+    assert np.array_equal(ex["knn_idx"].cpu().numpy()[rows], idx)
+    assert np.array_equal(ex["knn_d2"].cpu().numpy()[rows], d2)
