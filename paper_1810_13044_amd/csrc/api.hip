@@ -843,6 +843,7 @@ slk_status slk_inner_step(const slk_graph* g, int32_t L, const float* a, const f
     SLK_HIP(hipMemcpyAsync(bound_host, w.bound, sizeof(double), hipMemcpyDeviceToHost, s));
   }
   SLK_HIP(hipStreamSynchronize(s));
+  if (timing_on()) timing_flush();
   return SLK_OK;
 }
 

@@ -606,52 +606,26 @@ __device__ __forceinline__ float4 load4(__amdgpu_buffer_rsrc_t r, uint32_t off) 
   return make_float4(v.x, v.y, v.z, v.w);
 }
 
-constexpr int kCH = 16;  // neighbour rows gathered per round
+constexpr int kCH = 16;  // neighbour slots per round (one index register per lane for G = 16)
+constexpr int kHalf = kCH / 2;
 
-// Row extent and the first two rounds of neighbour byte offsets of one batch row.  Lane j of
-// a group holds offsets t = j + G u (+ kCH for the second round) of the row's neighbour list,
-// or `dead` (= n * row bytes, past the end of Z) for slots beyond the row's degree.
-template <int G>
-struct Cur4 {
-  int32_t beg, end;
-  uint32_t pre[2][kCH / G];
-};
-
-template <int G>
-__device__ __forceinline__ void cur4_extent(const IterArgs& a, int64_t row, Cur4<G>& c) {
-  c.beg = 0;
-  c.end = 0;
-  if (row >= 0 && row < a.n) {
-    c.beg = a.row_ptr[row];
-    c.end = a.row_ptr[row + 1];
-  }
-}
-
-template <int G>
+// Byte offset of neighbour slot t of a row (CSR entries beg..beg+deg), or `dead` (= n * row
+// bytes, past the end of Z) when t >= deg.
 __device__ __forceinline__ uint32_t neighbour_offset(const IterArgs& a, int32_t beg, int deg, int t, uint32_t dead) {
   const int tc = min(t, max(deg - 1, 0));
   const uint32_t q = (uint32_t)__builtin_nontemporal_load(&a.col_off[beg + tc]);
   return t < deg ? q : dead;
 }
 
+// One batch of 64/G rows (one per group), row extent beg..end of this group's row.
+// Per round the lanes of a group load the byte offsets of kCH neighbour slots (lane j holds
+// slots t0 + j + G u) and broadcast them slot by slot; Z rows are fetched with 32-bit buffer
+// offsets.  A round is issued in two halves of kHalf slots, the second only if some row of the
+// wave still has neighbours there, so rows of degree 17..24 cost 24 slots, not 32.  The dead
+// offset lies past the end of Z: empty slots read zeros and need no masking.
 template <int G>
-__device__ __forceinline__ void cur4_index(const IterArgs& a, int j, uint32_t dead, Cur4<G>& c) {
-  const int deg = c.end - c.beg;
-#pragma unroll
-  for (int r = 0; r < 2; ++r)
-#pragma unroll
-    for (int u = 0; u < kCH / G; ++u) c.pre[r][u] = neighbour_offset<G>(a, c.beg, deg, r * kCH + j + G * u, dead);
-}
-
-// One batch of 64/G rows (one per group).  Neighbour byte offsets of the first two rounds come
-// pre-loaded in `cur`; later rounds (rows of degree > 2 kCH) load theirs on demand.  The group
-// broadcasts each slot's offset, and Z rows are fetched with 32-bit buffer offsets: the dead
-// offset lies past the end of Z, so empty slots read zeros and need no masking.  `prefetch`
-// runs once, right after the first round of gathers has been issued, so the next batch's
-// loads overlap this batch's.
-template <int G, class P>
-__device__ __forceinline__ void row4_update(const IterArgs& a, uint32_t rowc, bool valid, int j, const Cur4<G>& cur,
-                                            Row4& o, P&& prefetch) {
+__device__ __forceinline__ void row4_update(const IterArgs& a, uint32_t rowc, bool valid, int j, int32_t beg,
+                                            int32_t end, Row4& o) {
   constexpr int U = kCH / G;   // offset registers per lane and round
   const int L = a.L;
   const uint32_t L4 = (uint32_t)(a.ldz >> 2);
@@ -662,34 +636,41 @@ __device__ __forceinline__ void row4_update(const IterArgs& a, uint32_t rowc, bo
   const vf4 avn = __builtin_nontemporal_load(reinterpret_cast<const vf4*>(a.A) + (rowc * L4 + (jc16 >> 4)));
   const float4 av = make_float4(avn.x, avn.y, avn.z, avn.w);
   const float4 zp = load4(zr, rowc * rb + jc16);
-  const int deg = valid ? cur.end - cur.beg : 0;
+  const int deg = valid ? end - beg : 0;
   float bx = 0.f, by = 0.f, bz = 0.f, bw = 0.f;
-  bool prefetched = false;
   for (int t0 = 0; __ballot(t0 < deg) != 0ull; t0 += kCH) {
     uint32_t off[U];
-    const int r = t0 / kCH;
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-      off[u] = r == 0 ? cur.pre[0][u] : r == 1 ? cur.pre[1][u] : neighbour_offset<G>(a, cur.beg, deg, t0 + j + G * u, dead);
+    for (int u = 0; u < U; ++u) off[u] = neighbour_offset(a, beg, deg, t0 + j + G * u, dead);
     float4 v[kCH];
-    auto gather = [&](auto ic) {
+    auto gather_lo = [&](auto ic) {
       constexpr int i = decltype(ic)::value;
       v[i] = load4(zr, group_bcast<G, i % G>(off[i / G]) + jc16);
     };
-    static_for<0, kCH>(gather);
-    if (!prefetched) {
-      prefetch();
-      prefetched = true;
-    }
+    auto gather_hi = [&](auto ic) {
+      constexpr int i = decltype(ic)::value + kHalf;
+      v[i] = load4(zr, group_bcast<G, i % G>(off[i / G]) + jc16);
+    };
+    static_for<0, kHalf>(gather_lo);
+    const bool hi = __ballot(t0 + kHalf < deg) != 0ull;
+    if (hi) static_for<0, kHalf>(gather_hi);
 #pragma unroll
-    for (int i = 0; i < kCH; ++i) {
+    for (int i = 0; i < kHalf; ++i) {
       bx += v[i].x;
       by += v[i].y;
       bz += v[i].z;
       bw += v[i].w;
     }
+    if (hi) {
+#pragma unroll
+      for (int i = kHalf; i < kCH; ++i) {
+        bx += v[i].x;
+        by += v[i].y;
+        bz += v[i].z;
+        bw += v[i].w;
+      }
+    }
   }
-  if (!prefetched) prefetch();
   const float bb[4] = {bx, by, bz, bw};
   float m = -FLT_MAX, term = 0.f;
 #pragma unroll
@@ -728,7 +709,6 @@ __global__ __launch_bounds__(kBlock) void iter4_kernel(IterArgs a) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane / G, j = lane % G;
   const uint32_t L4 = (uint32_t)(a.ldz >> 2);
-  const uint32_t dead = (uint32_t)a.n * L4 * 16u;
   float4* __restrict__ O4 = reinterpret_cast<float4*>(a.Zout);
   const int64_t nbatch = (a.n + RW - 1) / RW;
   const int64_t tile = xcd_tile((nbatch + 4 * kWaveSteps - 1) / (4 * kWaveSteps));
@@ -736,29 +716,18 @@ __global__ __launch_bounds__(kBlock) void iter4_kernel(IterArgs a) {
   const int64_t b0 = tile >= 0 ? tile * 4 * kWaveSteps + wave : 0;
   const int64_t bstop = tile >= 0 ? min(nbatch, (tile + 1) * 4 * kWaveSteps) : 0;
   double acc = 0.0;
-  // two-deep pipeline: offsets of batch b + 4 and the extent of batch b + 8 are loaded while
-  // batch b gathers
-  Cur4<G> cur, nxt, nxt2;
-  cur4_extent<G>(a, b0 < bstop ? b0 * RW + g : -1, cur);
-  cur4_index<G>(a, j, dead, cur);
-  cur4_extent<G>(a, b0 + 4 < bstop ? (b0 + 4) * RW + g : -1, nxt);
   for (int64_t b = b0; b < bstop; b += 4) {
     const int64_t row = b * RW + g;
     const bool valid = row >= 0 && row < a.n;
     const uint32_t rowc = (uint32_t)(valid ? row : a.n - 1);
+    const int32_t beg = a.row_ptr[rowc], end = a.row_ptr[rowc + 1];
     Row4 o;
-    row4_update<G>(a, rowc, valid, j, cur, o, [&]() {
-      cur4_index<G>(a, j, dead, nxt);
-      cur4_extent<G>(a, b + 8 < bstop ? (b + 8) * RW + g : -1, nxt2);
-    });
+    row4_update<G>(a, rowc, valid, j, beg, end, o);
     if (valid) {
       if (O4 && (uint32_t)j < L4)
         __builtin_nontemporal_store(vf4{o.z[0], o.z[1], o.z[2], o.z[3]}, reinterpret_cast<vf4*>(O4) + (rowc * L4 + j));
       if (j == 0) acc += (double)o.r;
     }
-    cur = nxt;
-    nxt.beg = nxt2.beg;
-    nxt.end = nxt2.end;
   }
   block_partial<RW>(a.partial, acc, g, j);
 }
@@ -787,11 +756,9 @@ __global__ __launch_bounds__(kBlock) void final4_kernel(FinalArgs f) {
     const int64_t row = b * RW + g;
     const bool valid = row >= 0 && row < a.n;
     const uint32_t rowc = (uint32_t)(valid ? row : a.n - 1);
-    Cur4<G> cur;
-    cur4_extent<G>(a, valid ? row : -1, cur);
-    cur4_index<G>(a, j, (uint32_t)a.n * (uint32_t)a.ldz * 4u, cur);
+    const int32_t beg = a.row_ptr[rowc], end = a.row_ptr[rowc + 1];
     Row4 o;
-    row4_update<G>(a, rowc, valid, j, cur, o, []() {});
+    row4_update<G>(a, rowc, valid, j, beg, end, o);
     // first arg-max of the logits (ties to the smaller l)
     float tv = -INFINITY;
     int ti = INT32_MAX;
