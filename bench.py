@@ -172,12 +172,14 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     n_iter, iter_ms = slk.timing_read("iter_kernel")
-    kern = {k: slk.timing_read(k) for k in ("unary_kernel", "iter_kernel", "final_kernel", "energy_kernel",
-                                            "mode_reduce_kernel")}
+    kern = {k: slk.timing_read(k) for k in ("unary_kernel", "iter_kernel", "iter_kernel_after_stop", "final_kernel",
+                                            "energy_kernel")}
     slk.timing_enable(False)
     r0 = results[0]
     assert all(r == r0 for r in results), "fit results differ between steps"
     log(f"[bench] fit: {r0}")
+    if n_iter != r0["inner_iters_total"] * args.steps:
+        log(f"[bench] warning: {n_iter} timed z-updates for {r0['inner_iters_total'] * args.steps} passes")
     ms_step = wall / args.steps * 1e3
     total_bytes = fit_bytes(N, D, L, nnz, r0["inner_iters_total"], r0["outer_iters"])
     value = total_bytes / (ms_step / 1e3) / 1e9

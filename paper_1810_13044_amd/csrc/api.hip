@@ -108,6 +108,53 @@ void timing_flush() {
   g_tpend.clear();
 }
 
+void timing_retag_tail(const char* name, int count, const char* to) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  for (auto it = g_tpend.rbegin(); it != g_tpend.rend() && count > 0; ++it)
+    if (it->name == name) {
+      it->name = to;
+      --count;
+    }
+}
+
+// Host-visible mirror of the z-update loop state (two slots, alternating by pass) and one event
+// per slot, per device and thread.  The pass reduction stores the state there, so the driver
+// watches the loop without a copy on the stream.
+struct Watch {
+  IterState* host = nullptr;
+  IterState* dev = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+};
+
+slk_status watch_for_device(Watch** out) {
+  thread_local std::map<int, Watch> per_dev;
+  int dev = 0;
+  SLK_HIP(hipGetDevice(&dev));
+  Watch& w = per_dev[dev];
+  if (!w.host) {
+    void* h = nullptr;
+    if (hipHostMalloc(&h, 2 * sizeof(IterState), hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(SLK_ERR_OUT_OF_MEMORY, "pinned loop-state mirror");
+    }
+    void* d = nullptr;
+    if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipHostFree(h);
+      return fail(SLK_ERR_DEVICE, "device address of the loop-state mirror");
+    }
+    for (auto& e : w.ev)
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SLK_ERR_DEVICE, "loop-state event");
+      }
+    w.host = (IterState*)h;
+    w.dev = (IterState*)d;
+  }
+  *out = &w;
+  return SLK_OK;
+}
+
 // kernels local to this file ----------------------------------------------------------------
 namespace {
 
@@ -443,22 +490,38 @@ slk_status run_outer(const float* x, int64_t n, int32_t d, const slk_graph* g, i
     SLK_HIP(hipStreamSynchronize(s));
     if (timing_on()) timing_flush();
   } else {
-    int chunk = 2;
-    while (launched < p.max_inner) {
-      const int c = std::min(chunk, p.max_inner - launched);
-      for (int j = 0; j < c; ++j, ++launched) {
-        a.Zin = w.Z[launched & 1];
-        a.Zout = w.Z[(launched + 1) & 1];
-        SLK_TRY(launch_iter(a, w.grid, s));
+    // One pass ahead: pass k+1 is queued before the host looks at the state after pass k, so
+    // the device never waits for the host; once the bound has settled, the one pass already
+    // queued returns at once.
+    Watch* wt = nullptr;
+    SLK_TRY(watch_for_device(&wt));
+    auto enqueue = [&](int k) -> slk_status {
+      a.Zin = w.Z[k & 1];
+      a.Zout = w.Z[(k + 1) & 1];
+      a.mirror = wt->dev + (k & 1);
+      SLK_TRY(launch_iter(a, w.grid, s));
+      SLK_HIP(hipEventRecord(wt->ev[k & 1], s));
+      return SLK_OK;
+    };
+    SLK_TRY(enqueue(0));
+    launched = 1;
+    for (int k = 0; k < launched; ++k) {
+      if (launched < p.max_inner) {
+        SLK_TRY(enqueue(launched));
+        ++launched;
       }
-      void* pin;
-      SLK_TRY(pinned(&pin, sizeof(IterState)));
-      SLK_HIP(hipMemcpyAsync(pin, w.state, sizeof(IterState), hipMemcpyDeviceToHost, s));
-      SLK_HIP(hipStreamSynchronize(s));
-      if (timing_on()) timing_flush();
-      memcpy(&hs, pin, sizeof(IterState));
-      if (hs.done) break;
-      chunk = std::min(chunk * 2, 16);
+      SLK_HIP(hipEventSynchronize(wt->ev[k & 1]));
+      const volatile IterState* m = wt->host + (k & 1);
+      if (m->done) break;
+    }
+    void* pin;
+    SLK_TRY(pinned(&pin, sizeof(IterState)));
+    SLK_HIP(hipMemcpyAsync(pin, w.state, sizeof(IterState), hipMemcpyDeviceToHost, s));
+    SLK_HIP(hipStreamSynchronize(s));
+    memcpy(&hs, pin, sizeof(IterState));
+    if (timing_on()) {
+      timing_retag_tail("iter_kernel", launched - hs.pass, "iter_kernel_after_stop");
+      timing_flush();
     }
   }
   if (hs.numeric) return fail(SLK_ERR_NUMERIC, "relaxed bound is not finite");

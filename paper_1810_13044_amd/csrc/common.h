@@ -95,6 +95,9 @@ bool timing_on();
 int timer_start(const char* name, hipStream_t s);
 void timer_stop(int slot, hipStream_t s);
 void timing_flush();
+// Moves the last `count` pending pairs named `name` to the bucket `to` (z-updates queued after
+// the loop settled, which return at once).
+void timing_retag_tail(const char* name, int count, const char* to);
 struct KernelTimer {
   int slot;
   hipStream_t s;
@@ -166,6 +169,7 @@ struct IterArgs {
   IterState* state;      // may be null: no convergence bookkeeping
   double* trace;         // bound per pass (device, trace_cap entries) or null
   double* bound_out;     // if non-null, the last block writes the pass's bound here
+  IterState* mirror;     // if non-null, host-visible copy of *state stored after the pass
 };
 
 struct FinalArgs {

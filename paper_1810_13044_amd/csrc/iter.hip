@@ -1006,17 +1006,33 @@ __global__ __launch_bounds__(kBlock) void energy_reduce_kernel(const double* __r
 
 // Fixed-order sum of the bound partials of one z-update, then the loop bookkeeping: bound
 // trace, convergence test (relative change of the bound), pass counter.  A no-op once the
-// loop is done, like the z-updates queued after it.
-__global__ __launch_bounds__(kBlock) void pass_reduce_kernel(const double* __restrict__ partial, int nparts,
-                                                             IterState* st, double* trace, double* bound_out) {
+// loop is done, like the z-updates queued after it.  Each thread sums a strided slice with
+// kRedUnroll independent accumulators (so the loads are all in flight together), then the
+// block combines the slices in a fixed tree.
+constexpr int kRedBlock = 1024;
+constexpr int kRedUnroll = 8;
+__global__ __launch_bounds__(kRedBlock) void pass_reduce_kernel(const double* __restrict__ partial, int nparts,
+                                                                IterState* st, double* trace, double* bound_out,
+                                                                IterState* mirror) {
   if (st->done) return;
-  __shared__ double red[kBlock];
+  __shared__ double red[kRedBlock];
   const int tid = threadIdx.x;
+  double acc[kRedUnroll];
+#pragma unroll
+  for (int u = 0; u < kRedUnroll; ++u) acc[u] = 0.0;
+  for (int i0 = tid; i0 < nparts; i0 += kRedBlock * kRedUnroll) {
+#pragma unroll
+    for (int u = 0; u < kRedUnroll; ++u) {
+      const int i = i0 + u * kRedBlock;
+      if (i < nparts) acc[u] += partial[i];
+    }
+  }
   double v = 0.0;
-  for (int i = tid; i < nparts; i += kBlock) v += partial[i];
+#pragma unroll
+  for (int u = 0; u < kRedUnroll; ++u) v += acc[u];
   red[tid] = v;
   __syncthreads();
-  for (int w = kBlock / 2; w > 0; w >>= 1) {
+  for (int w = kRedBlock / 2; w > 0; w >>= 1) {
     if (tid < w) red[tid] += red[tid + w];
     __syncthreads();
   }
@@ -1033,6 +1049,7 @@ __global__ __launch_bounds__(kBlock) void pass_reduce_kernel(const double* __res
     }
     st->last_bound = R;
     st->pass = pass + 1;
+    if (mirror) *mirror = *st;
   }
 }
 
@@ -1147,7 +1164,8 @@ slk_status launch_iter(const IterArgs& a, int grid, hipStream_t s) {
     else SLK_DISPATCH_LANES(a.L, iter_kernel, dim3(grid), dim3(kBlock), 0, s, a);
     SLK_LAUNCHED("iter_kernel");
   }
-  hipLaunchKernelGGL(pass_reduce_kernel, dim3(1), dim3(kBlock), 0, s, a.partial, grid, a.state, a.trace, a.bound_out);
+  hipLaunchKernelGGL(pass_reduce_kernel, dim3(1), dim3(kRedBlock), 0, s, a.partial, grid, a.state, a.trace, a.bound_out,
+                     a.mirror);
   SLK_LAUNCHED("pass_reduce_kernel");
   return SLK_OK;
 }
@@ -1159,8 +1177,8 @@ slk_status launch_final(const FinalArgs& f, int grid, hipStream_t s) {
     else SLK_DISPATCH_LANES(f.it.L, final_kernel, dim3(grid), dim3(kBlock), 0, s, f);
     SLK_LAUNCHED("final_kernel");
   }
-  hipLaunchKernelGGL(pass_reduce_kernel, dim3(1), dim3(kBlock), 0, s, f.it.partial, grid, f.it.state, f.it.trace,
-                     f.it.bound_out);
+  hipLaunchKernelGGL(pass_reduce_kernel, dim3(1), dim3(kRedBlock), 0, s, f.it.partial, grid, f.it.state, f.it.trace,
+                     f.it.bound_out, f.it.mirror);
   SLK_LAUNCHED("pass_reduce_kernel");
   return SLK_OK;
 }
