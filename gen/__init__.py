@@ -20,7 +20,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 __all__ = [
-    "Instance", "mixture", "gaussian_mixture", "manifold_images", "vmf_embeddings",
+    "Instance", "mixture", "gaussian_mixture", "star_hubs", "manifold_images", "vmf_embeddings",
     "anisotropic_mixture", "job_stream", "init_modes", "make", "WORKLOADS",
 ]
 
@@ -81,6 +81,33 @@ def gaussian_mixture(n: int = 2000, d: int = 16, L: int = 5, K: int = 10, lam: f
 
 # the short name used by tests for arbitrary small mixtures
 mixture = gaussian_mixture
+
+
+def star_hubs(n_background: int = 2000, d: int = 64, L: int = 5, K: int = 10, lam: float = 1.0,
+              hub_sizes=(140, 300, 700, 1500), seed: int = 11, name: str = "hubs") -> Instance:
+    """A Gaussian mixture (as `gaussian_mixture`) plus star-shaped groups far from it: a
+    centre point and m points at distance exactly 1 from it in random directions.  In 64
+    dimensions points on the unit sphere are almost never within 1 of each other, so every
+    star point has its centre among its nearest neighbours and the centre's row of the
+    symmetrised kNN graph has about m entries: hubs of chosen degree.  Star points get the
+    label L - 1; the rows are shuffled."""
+    rng = np.random.default_rng(seed)
+    centres = rng.uniform(-10.0, 10.0, size=(L, d))
+    blab = _equal_labels(rng, n_background, L)
+    bg = centres[blab] + rng.standard_normal((n_background, d))
+    parts, labs = [bg], [blab]
+    for h, m in enumerate(hub_sizes):
+        c = np.full(d, 100.0 + 10.0 * h)
+        u = rng.standard_normal((m, d))
+        u /= np.linalg.norm(u, axis=1, keepdims=True)
+        parts += [c[None, :], c + u]
+        labs += [np.full(m + 1, L - 1)]
+    X = np.concatenate(parts)
+    lab = np.concatenate(labs)
+    order = rng.permutation(len(X))
+    X, lab = X[order].astype(np.float32), lab[order]
+    modes = init_modes(rng, len(X), L)
+    return Instance(name, X, L, K, lam, modes, lab.astype(np.int32), seed)
 
 
 def manifold_images(n: int = 70000, d: int = 784, L: int = 10, K: int = 5, lam: float = 1.0,

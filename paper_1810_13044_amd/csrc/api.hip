@@ -287,6 +287,7 @@ void free_graph(slk_graph* g) {
   (void)hipFree(g->knn_d2);
   (void)hipFree(g->perm);
   (void)hipFree(g->iperm);
+  (void)hipFree(g->heavy);
   delete g;
 }
 
@@ -299,6 +300,27 @@ struct GraphGuard {
     return r;
   }
 };
+
+// The rows of degree > kHeavyDeg (internal numbering), largest degree first, ties by row.
+slk_status build_heavy(slk_graph* g, hipStream_t s) {
+  (void)hipFree(g->heavy);
+  g->heavy = nullptr;
+  g->n_heavy = 0;
+  const int64_t n = g->n;
+  std::vector<int32_t> rp(n + 1);
+  SLK_HIP(hipMemcpyAsync(rp.data(), g->row_ptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, s));
+  SLK_HIP(hipStreamSynchronize(s));
+  std::vector<int32_t> h;
+  for (int64_t i = 0; i < n; ++i)
+    if (rp[i + 1] - rp[i] > kHeavyDeg) h.push_back((int32_t)i);
+  std::stable_sort(h.begin(), h.end(), [&](int32_t u, int32_t v) { return rp[u + 1] - rp[u] > rp[v + 1] - rp[v]; });
+  if (h.empty()) return SLK_OK;
+  SLK_HIP(hipMalloc(&g->heavy, sizeof(int32_t) * h.size()));
+  SLK_HIP(hipMemcpyAsync(g->heavy, h.data(), sizeof(int32_t) * h.size(), hipMemcpyHostToDevice, s));
+  SLK_HIP(hipStreamSynchronize(s));
+  g->n_heavy = (int64_t)h.size();
+  return SLK_OK;
+}
 
 // Breadth-first order of the graph, component by component (roots in increasing index
 // order), neighbours visited in CSR order.  Points that are neighbours end up close in the
@@ -371,6 +393,7 @@ slk_status finish_from_knn(slk_graph* g, int32_t reorder, hipStream_t s) {
     g->sigma2 = h / ((double)g->n * (double)g->k);
   }
   if (reorder) SLK_TRY(bfs_reorder(g, s));
+  SLK_TRY(build_heavy(g, s));
   int32_t mn, mx;
   SLK_TRY(degree_stats(g->row_ptr, g->n, &mn, &mx, s));
   g->min_degree = mn;
@@ -412,10 +435,29 @@ slk_status prepare_col_off(const slk_graph* g, int32_t L, Scratch& sc, uint32_t*
   return launch_col_offsets(g->col_idx, g->nnz, g->n, L, *out, sc.stream);
 }
 
-slk_status alloc_work(Scratch& sc, int64_t n, int32_t L, int trace_cap, Work& w) {
+// Heavy rows go to their own work-groups on the float4 path (L <= 64) and in the energy.
+int64_t heavy_rows_for(const slk_graph* g, int32_t L) { return L <= 64 ? g->n_heavy : 0; }
+
+void set_heavy(IterArgs& a, const slk_graph* g, int32_t L) {
+  const int64_t nh = heavy_rows_for(g, L);
+  a.heavy = nh ? g->heavy : nullptr;
+  a.n_heavy = (int32_t)nh;
+  a.hblocks = heavy_blocks(nh);
+  a.heavy_deg = nh ? kHeavyDeg : INT32_MAX;
+}
+
+void set_heavy(EnergyArgs& e, const slk_graph* g) {
+  e.heavy = g->n_heavy ? g->heavy : nullptr;
+  e.n_heavy = (int32_t)g->n_heavy;
+  e.hblocks = heavy_blocks(g->n_heavy);
+  e.heavy_deg = g->n_heavy ? kHeavyDeg : INT32_MAX;
+}
+
+slk_status alloc_work(Scratch& sc, const slk_graph* g, int32_t L, int trace_cap, Work& w) {
+  const int64_t n = g->n;
   const int ldz = ldz_for(L);
-  w.grid = iter_grid(n, L);
-  w.egrid = energy_grid(n);
+  w.grid = iter_grid(n, L, heavy_rows_for(g, L));
+  w.egrid = energy_grid(n, g->n_heavy);
   SLK_TRY(sc.get(&w.A, n * ldz));
   SLK_TRY(sc.get(&w.Z[0], n * ldz));
   SLK_TRY(sc.get(&w.Z[1], n * ldz));
@@ -461,6 +503,8 @@ IterArgs make_iter(const slk_graph* g, const Work& w, int64_t n, int32_t L, cons
   a.state = w.state;
   a.trace = w.trace;
   a.bound_out = nullptr;
+  a.mirror = nullptr;
+  set_heavy(a, g, L);
   return a;
 }
 
@@ -550,6 +594,7 @@ slk_status run_outer(const float* x, int64_t n, int32_t d, const slk_graph* g, i
     SLK_TRY(launch_mode_reduce(w.cand_v, w.cand_i, w.grid, L, w.modes_next, s));
   }
   EnergyArgs e{};
+  set_heavy(e, g);
   e.row_ptr = g->row_ptr;
   e.col_idx = g->col_idx;
   e.labels_int = w.labels_int;
@@ -767,6 +812,7 @@ slk_status slk_graph_from_csr(int64_t n, int64_t nnz, const int32_t* row_ptr, co
   SLK_HIP(hipMemcpyAsync(g->row_ptr, row_ptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToDevice, s));
   if (nnz) SLK_HIP(hipMemcpyAsync(g->col_idx, col_idx, sizeof(int32_t) * nnz, hipMemcpyDeviceToDevice, s));
   if (reorder) SLK_TRY(bfs_reorder(g, s));
+  SLK_TRY(build_heavy(g, s));
   int32_t mn, mx;
   SLK_TRY(degree_stats(g->row_ptr, n, &mn, &mx, s));
   g->min_degree = mn;
@@ -871,7 +917,7 @@ slk_status slk_inner_step(const slk_graph* g, int32_t L, const float* a, const f
   p.delta = delta;
   p.pairwise_scale = pairwise_scale;
   Work w;
-  w.grid = iter_grid(n, L);
+  w.grid = iter_grid(n, L, heavy_rows_for(g, L));
   SLK_TRY(sc.get(&w.partial, w.grid));
   SLK_TRY(sc.get(&w.state, 1));
   SLK_TRY(sc.get(&w.bound, 1));
@@ -925,7 +971,7 @@ static slk_status assign_or_fit(bool fit, const float* x, int64_t n, int32_t d, 
   const int cap = std::max(trace_cap, std::max(p.max_inner, p.fixed_inner));
   Scratch sc(s);
   Work w;
-  SLK_TRY(alloc_work(sc, n, L, cap, w));
+  SLK_TRY(alloc_work(sc, g, L, cap, w));
   SLK_TRY(prepare_col_off(g, L, sc, &w.col_off));
   std::vector<int32_t> cur(modes_host, modes_host + L), nxt(L);
   SLK_HIP(hipMemcpyAsync(w.modes, cur.data(), sizeof(int32_t) * L, hipMemcpyHostToDevice, s));
@@ -960,6 +1006,7 @@ static slk_status assign_or_fit(bool fit, const float* x, int64_t n, int32_t d, 
   // labels and the modes that produced them (both still resident in the work buffers)
   {
     EnergyArgs e{};
+    set_heavy(e, g);
     e.row_ptr = g->row_ptr;
     e.col_idx = g->col_idx;
     e.labels_int = w.labels_int;
@@ -1025,12 +1072,13 @@ slk_status slk_energy(const float* x, int64_t n, int32_t d, const slk_graph* g, 
   SLK_TRY(check_labels(labels, n, L, s));
   Scratch sc(s);
   Work w;
-  SLK_TRY(alloc_work(sc, n, L, 1, w));
+  SLK_TRY(alloc_work(sc, g, L, 1, w));
   if (z) SLK_TRY(prepare_col_off(g, L, sc, &w.col_off));
   SLK_HIP(hipMemcpyAsync(w.modes, modes_host, sizeof(int32_t) * L, hipMemcpyHostToDevice, s));
   SLK_TRY(launch_unary(x, n, d, g->perm, w.modes, L, ldz_for(L), s2, 0, w.A, nullptr, s));
   SLK_TRY(launch_to_internal_labels(labels, g->iperm, n, w.labels_int, s));
   EnergyArgs e{};
+  set_heavy(e, g);
   e.row_ptr = g->row_ptr;
   e.col_idx = g->col_idx;
   e.labels_int = w.labels_int;

@@ -128,6 +128,8 @@ struct slk_graph {
   double* knn_d2 = nullptr;     // n*k (may be null)
   int32_t* perm = nullptr;      // n: internal row -> original index (null = identity)
   int32_t* iperm = nullptr;     // n: original index -> internal row (null = identity)
+  int32_t* heavy = nullptr;     // internal rows of degree > kHeavyDeg, by degree descending
+  int64_t n_heavy = 0;
 };
 
 namespace slk {
@@ -151,6 +153,12 @@ struct IterState {
 inline int ldz_for(int L) { return L <= 64 ? ((L + 3) / 4) * 4 : L; }
 // Zero entries kept after the last CSR column so clamped index loads never leave the array.
 constexpr int kColPad = 16;
+// Rows of more than kHeavyDeg neighbours (the hubs of a kNN graph) are updated by a whole
+// workgroup each, at the front of the grid; the row-per-group path skips them.
+constexpr int kHeavyDeg = 128;
+// Work-groups given to heavy rows: one per row, rounded up to a multiple of the 8 XCDs so the
+// tiles behind them keep their XCD placement.
+inline int heavy_blocks(int64_t n_heavy) { return (int)(8 * ((n_heavy + 7) / 8)); }
 
 struct IterArgs {
   const int32_t* row_ptr;
@@ -170,6 +178,10 @@ struct IterArgs {
   double* trace;         // bound per pass (device, trace_cap entries) or null
   double* bound_out;     // if non-null, the last block writes the pass's bound here
   IterState* mirror;     // if non-null, host-visible copy of *state stored after the pass
+  const int32_t* heavy;  // rows handled by the first hblocks work-groups (float4 path only)
+  int32_t n_heavy;
+  int32_t hblocks;       // heavy_blocks(n_heavy), or 0
+  int32_t heavy_deg;     // rows above this degree belong to the heavy work-groups
 };
 
 struct FinalArgs {
@@ -184,7 +196,7 @@ struct FinalArgs {
 
 slk_status launch_unary(const float* x, int64_t n, int32_t d, const int32_t* perm, const int32_t* modes_dev,
                         int32_t L, int32_t ldz, double sigma2, int32_t bf16, float* A, float* Z0, hipStream_t s);
-int iter_grid(int64_t n, int32_t L);
+int iter_grid(int64_t n, int32_t L, int64_t n_heavy);
 slk_status launch_iter(const IterArgs& a, int grid, hipStream_t s);
 slk_status launch_final(const FinalArgs& a, int grid, hipStream_t s);
 slk_status launch_mode_reduce(const float* cand_v, const int32_t* cand_i, int grid, int32_t L, int32_t* modes_out,
@@ -205,8 +217,13 @@ struct EnergyArgs {
   long long* part_cut;        // grid counts
   double* out;                // [0] unary32, [1] unary64 (written by the reduce kernel)
   long long* out_cut;
+  const int32_t* heavy;       // rows handled by the first hblocks work-groups
+  int32_t n_heavy;
+  int32_t hblocks;
+  int32_t heavy_deg;
 };
-int energy_grid(int64_t n);
+// Grids include the heavy-row work-groups in front (n_heavy = 0: none).
+int energy_grid(int64_t n, int64_t n_heavy);
 slk_status launch_energy(const EnergyArgs& a, int grid, hipStream_t s);
 // caller layout (stride L, original order) <-> internal layout (stride ldz, internal order)
 slk_status launch_gather_rows(const float* src, const int32_t* perm, int64_t n, int32_t L, int32_t ldz, float* dst,

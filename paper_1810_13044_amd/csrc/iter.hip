@@ -344,9 +344,9 @@ __device__ __forceinline__ void block_partial(double* partial, double acc, int g
 // (b % 8) * ceil(T / 8) + b / 8: each XCD walks its own contiguous range of tiles in
 // dispatch order, and the rows in flight on one XCD - and the neighbour rows they gather -
 // stay inside a narrow window its L2 can hold.  The physical grid is 8 * ceil(T / 8).
-__device__ __forceinline__ int64_t xcd_tile(int64_t ntiles) {
+__device__ __forceinline__ int64_t xcd_tile(int64_t ntiles, int64_t bid) {
   const int64_t gx = (ntiles + 7) >> 3;
-  const int64_t x = blockIdx.x & 7, k = blockIdx.x >> 3;
+  const int64_t x = bid & 7, k = bid >> 3;
   const int64_t t = x * gx + k;
   return (k < gx && t < ntiles) ? t : -1;
 }
@@ -362,7 +362,7 @@ __global__ __launch_bounds__(kBlock) void iter_kernel(IterArgs a) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane / S, l0 = lane % S;
   constexpr int64_t kTileRows = 4 * G * kWaveSteps;
-  const int64_t tile = xcd_tile((a.n + kTileRows - 1) / kTileRows);
+  const int64_t tile = xcd_tile((a.n + kTileRows - 1) / kTileRows, blockIdx.x);
   double acc = 0.0;
   if (tile >= 0) {
     const int64_t base = tile * kTileRows;
@@ -399,7 +399,7 @@ __global__ __launch_bounds__(kBlock) void final_kernel(FinalArgs f) {
   }
   double acc = 0.0;
   constexpr int64_t kTileRows = 4 * G * kWaveSteps;
-  const int64_t tile = xcd_tile((a.n + kTileRows - 1) / kTileRows);
+  const int64_t tile = xcd_tile((a.n + kTileRows - 1) / kTileRows, blockIdx.x);
   const int64_t base = tile * kTileRows;
   const int64_t first = tile >= 0 ? base + wave * G + g : a.n;
   const int64_t last = tile >= 0 ? min(a.n, base + kTileRows) : a.n;
@@ -623,25 +623,21 @@ __device__ __forceinline__ uint32_t neighbour_offset(const IterArgs& a, int32_t 
 // offsets.  A round is issued in two halves of kHalf slots, the second only if some row of the
 // wave still has neighbours there, so rows of degree 17..24 cost 24 slots, not 32.  The dead
 // offset lies past the end of Z: empty slots read zeros and need no masking.
+// Sum of the Z rows of the CSR entries beg .. beg+cnt-1 (this lane's 16-byte slice of them).
+// Per round the lanes of a group load the byte offsets of kCH neighbour slots (lane j holds
+// slots t0 + j + G u) and broadcast them slot by slot; Z rows are fetched with 32-bit buffer
+// offsets.  A round is issued in two halves of kHalf slots, the second only if some group of
+// the wave still has neighbours there, so 17..24 neighbours cost 24 slots, not 32.  The dead
+// offset lies past the end of Z: empty slots read zeros and need no masking.
 template <int G>
-__device__ __forceinline__ void row4_update(const IterArgs& a, uint32_t rowc, bool valid, int j, int32_t beg,
-                                            int32_t end, Row4& o) {
+__device__ __forceinline__ float4 gather_sum(const IterArgs& a, __amdgpu_buffer_rsrc_t zr, int j, uint32_t jc16,
+                                             int32_t beg, int cnt, uint32_t dead) {
   constexpr int U = kCH / G;   // offset registers per lane and round
-  const int L = a.L;
-  const uint32_t L4 = (uint32_t)(a.ldz >> 2);
-  const uint32_t rb = L4 * 16u;                                  // row bytes
-  const uint32_t jc16 = min((uint32_t)j, L4 - 1) * 16u;
-  const uint32_t dead = (uint32_t)a.n * rb;
-  const __amdgpu_buffer_rsrc_t zr = buffer_of(a.Zin, dead);
-  const vf4 avn = __builtin_nontemporal_load(reinterpret_cast<const vf4*>(a.A) + (rowc * L4 + (jc16 >> 4)));
-  const float4 av = make_float4(avn.x, avn.y, avn.z, avn.w);
-  const float4 zp = load4(zr, rowc * rb + jc16);
-  const int deg = valid ? end - beg : 0;
   float bx = 0.f, by = 0.f, bz = 0.f, bw = 0.f;
-  for (int t0 = 0; __ballot(t0 < deg) != 0ull; t0 += kCH) {
+  for (int t0 = 0; __ballot(t0 < cnt) != 0ull; t0 += kCH) {
     uint32_t off[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) off[u] = neighbour_offset(a, beg, deg, t0 + j + G * u, dead);
+    for (int u = 0; u < U; ++u) off[u] = neighbour_offset(a, beg, cnt, t0 + j + G * u, dead);
     float4 v[kCH];
     auto gather_lo = [&](auto ic) {
       constexpr int i = decltype(ic)::value;
@@ -652,7 +648,7 @@ __device__ __forceinline__ void row4_update(const IterArgs& a, uint32_t rowc, bo
       v[i] = load4(zr, group_bcast<G, i % G>(off[i / G]) + jc16);
     };
     static_for<0, kHalf>(gather_lo);
-    const bool hi = __ballot(t0 + kHalf < deg) != 0ull;
+    const bool hi = __ballot(t0 + kHalf < cnt) != 0ull;
     if (hi) static_for<0, kHalf>(gather_hi);
 #pragma unroll
     for (int i = 0; i < kHalf; ++i) {
@@ -671,7 +667,15 @@ __device__ __forceinline__ void row4_update(const IterArgs& a, uint32_t rowc, bo
       }
     }
   }
-  const float bb[4] = {bx, by, bz, bw};
+  return make_float4(bx, by, bz, bw);
+}
+
+// Logits s = a + lambda b (+ delta z), the softmax of the row and its bound term, from the
+// neighbour sum b; av and zp are this lane's slices of the row of A and Z^i.
+template <int G>
+__device__ __forceinline__ void row_finish(const IterArgs& a, float4 av, float4 zp, float4 b, int j, Row4& o) {
+  const int L = a.L;
+  const float bb[4] = {b.x, b.y, b.z, b.w};
   float m = -FLT_MAX, term = 0.f;
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
@@ -702,6 +706,73 @@ __device__ __forceinline__ void row4_update(const IterArgs& a, uint32_t rowc, bo
   o.r = gsum4<G>(term);
 }
 
+struct RowGeom {
+  uint32_t L4, rb, jc16, dead;
+  __amdgpu_buffer_rsrc_t zr;
+};
+
+__device__ __forceinline__ RowGeom row_geom(const IterArgs& a, int j) {
+  RowGeom r;
+  r.L4 = (uint32_t)(a.ldz >> 2);
+  r.rb = r.L4 * 16u;                                  // row bytes
+  r.jc16 = min((uint32_t)j, r.L4 - 1) * 16u;
+  r.dead = (uint32_t)a.n * r.rb;
+  r.zr = buffer_of(a.Zin, r.dead);
+  return r;
+}
+
+__device__ __forceinline__ float4 row_slice_A(const IterArgs& a, const RowGeom& r, uint32_t rowc) {
+  const vf4 v = __builtin_nontemporal_load(reinterpret_cast<const vf4*>(a.A) + (rowc * r.L4 + (r.jc16 >> 4)));
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+
+// One batch of 64/G rows (one per group), row extent beg..end of this group's row; a row
+// with valid = false gathers nothing.
+template <int G>
+__device__ __forceinline__ void row4_update(const IterArgs& a, uint32_t rowc, bool valid, int j, int32_t beg,
+                                            int32_t end, Row4& o) {
+  const RowGeom r = row_geom(a, j);
+  const float4 av = row_slice_A(a, r, rowc);
+  const float4 zp = load4(r.zr, rowc * r.rb + r.jc16);
+  const float4 b = gather_sum<G>(a, r.zr, j, r.jc16, beg, valid ? end - beg : 0, r.dead);
+  row_finish<G>(a, av, zp, b, j, o);
+}
+
+// Heavy row hb of the block (a.heavy[hb]; none when hb >= n_heavy).  Every group of the block
+// sums a contiguous share of the row's neighbours; the shares are added in group order through
+// LDS and wave 0 finishes the row - each of its groups computes the same row, group 0's copy is
+// the one stored.  Must be reached by the whole block.
+template <int G>
+__device__ __forceinline__ bool heavy_row(const IterArgs& a, int hb, int wave, int g, int j, uint32_t& rowc, Row4& o) {
+  constexpr int RW = 64 / G, NG = 4 * RW;
+  const bool valid = hb < a.n_heavy;
+  rowc = valid ? (uint32_t)a.heavy[hb] : 0u;
+  const int32_t beg = a.row_ptr[rowc], end = a.row_ptr[rowc + 1];
+  const int deg = valid ? end - beg : 0;
+  const int share = (deg + NG - 1) / NG;
+  const int gid = wave * RW + g;
+  const int s0 = min(deg, gid * share), s1 = min(deg, s0 + share);
+  const RowGeom r = row_geom(a, j);
+  const float4 part = gather_sum<G>(a, r.zr, j, r.jc16, beg + s0, s1 - s0, r.dead);
+  __shared__ float4 hsum[kBlock];
+  hsum[threadIdx.x] = part;
+  __syncthreads();
+  if (wave == 0) {
+    float4 b = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int q = 0; q < NG; ++q) {
+      const float4 v = hsum[q * G + j];
+      b.x += v.x;
+      b.y += v.y;
+      b.z += v.z;
+      b.w += v.w;
+    }
+    const float4 av = row_slice_A(a, r, rowc);
+    const float4 zp = load4(r.zr, rowc * r.rb + r.jc16);
+    row_finish<G>(a, av, zp, b, j, o);
+  }
+  return valid;
+}
+
 template <int G>
 __global__ __launch_bounds__(kBlock) void iter4_kernel(IterArgs a) {
   if (a.state->done) return;
@@ -710,17 +781,30 @@ __global__ __launch_bounds__(kBlock) void iter4_kernel(IterArgs a) {
   const int g = lane / G, j = lane % G;
   const uint32_t L4 = (uint32_t)(a.ldz >> 2);
   float4* __restrict__ O4 = reinterpret_cast<float4*>(a.Zout);
+  double acc = 0.0;
+  if ((int)blockIdx.x < a.hblocks) {
+    uint32_t rowc;
+    Row4 o;
+    const bool valid = heavy_row<G>(a, blockIdx.x, wave, g, j, rowc, o);
+    if (valid && wave == 0 && g == 0) {
+      if (O4 && (uint32_t)j < L4)
+        __builtin_nontemporal_store(vf4{o.z[0], o.z[1], o.z[2], o.z[3]}, reinterpret_cast<vf4*>(O4) + (rowc * L4 + j));
+      if (j == 0) acc = (double)o.r;
+    }
+    block_partial<RW>(a.partial, acc, g, j);
+    return;
+  }
   const int64_t nbatch = (a.n + RW - 1) / RW;
-  const int64_t tile = xcd_tile((nbatch + 4 * kWaveSteps - 1) / (4 * kWaveSteps));
+  const int64_t tile = xcd_tile((nbatch + 4 * kWaveSteps - 1) / (4 * kWaveSteps), (int64_t)blockIdx.x - a.hblocks);
   // a block without a tile (grid padding) walks nothing: b0 = bstop = 0
   const int64_t b0 = tile >= 0 ? tile * 4 * kWaveSteps + wave : 0;
   const int64_t bstop = tile >= 0 ? min(nbatch, (tile + 1) * 4 * kWaveSteps) : 0;
-  double acc = 0.0;
   for (int64_t b = b0; b < bstop; b += 4) {
     const int64_t row = b * RW + g;
-    const bool valid = row >= 0 && row < a.n;
-    const uint32_t rowc = (uint32_t)(valid ? row : a.n - 1);
+    const uint32_t rowc = (uint32_t)(row >= 0 && row < a.n ? row : a.n - 1);
     const int32_t beg = a.row_ptr[rowc], end = a.row_ptr[rowc + 1];
+    // heavy rows belong to the work-groups in front of the grid
+    const bool valid = row >= 0 && row < a.n && end - beg <= a.heavy_deg;
     Row4 o;
     row4_update<G>(a, rowc, valid, j, beg, end, o);
     if (valid) {
@@ -732,6 +816,68 @@ __global__ __launch_bounds__(kBlock) void iter4_kernel(IterArgs a) {
   block_partial<RW>(a.partial, acc, g, j);
 }
 
+// Labels, byproduct-mode candidates and caller-order outputs of one finished row.  `valid`
+// rows update the candidates and the bound sum; `store` rows also write labels and z_user.
+template <int G>
+__device__ __forceinline__ void final_row(const FinalArgs& f, int64_t row, bool valid, bool store, int j, const Row4& o,
+                                          float (&bv)[4], int (&bi)[4], double& acc) {
+  const int L = f.it.L;
+  // first arg-max of the logits (ties to the smaller l)
+  float tv = -INFINITY;
+  int ti = INT32_MAX;
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    if (4 * j + e < L && o.s[e] > tv) {
+      tv = o.s[e];
+      ti = 4 * j + e;
+    }
+  gargmax4<G>(tv, ti);
+  const int jt = ti;
+  float m2 = -INFINITY, T = 0.f;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int l = 4 * j + e;
+    if (l < L && l != jt) {
+      m2 = fmaxf(m2, o.s[e]);
+      T += o.e[e];
+    }
+  }
+  m2 = gmax4<G>(m2);
+  T = gsum4<G>(T);
+  float S2 = 0.f;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int l = 4 * j + e;
+    if (l < L && l != jt) S2 += expf(o.s[e] - m2);
+  }
+  S2 = gsum4<G>(S2);
+  if (!valid) return;
+  if (store) acc += (j == 0) ? (double)o.r : 0.0;
+  const int64_t orow = f.perm ? f.perm[row] : row;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int l = 4 * j + e;
+    if (l >= L) continue;
+    float v;
+    if (L == 1) {
+      v = INFINITY;
+    } else if (l == jt) {
+      v = (o.m - m2) - logf(S2);      // log z/(1-z) for the top entry, no underflow
+    } else {
+      v = (o.s[e] - o.m) - log1pf(T - o.e[e]);
+    }
+    if (v > bv[e] || (v == bv[e] && (int)orow < bi[e])) {
+      bv[e] = v;
+      bi[e] = (int)orow;
+    }
+    if (store && f.z_user) f.z_user[orow * L + l] = o.z[e];
+  }
+  if (store && j == 0) {
+    f.labels_int[row] = jt;
+    if (f.labels_user) f.labels_user[orow] = jt;
+  }
+}
+
 template <int G>
 __global__ __launch_bounds__(kBlock) void final4_kernel(FinalArgs f) {
   const IterArgs& a = f.it;
@@ -739,7 +885,6 @@ __global__ __launch_bounds__(kBlock) void final4_kernel(FinalArgs f) {
   const int L = a.L;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane / G, j = lane % G;
-  const int64_t nbatch = (a.n + RW - 1) / RW;
   float bv[4];
   int bi[4];
 #pragma unroll
@@ -748,70 +893,26 @@ __global__ __launch_bounds__(kBlock) void final4_kernel(FinalArgs f) {
     bi[e] = INT32_MAX;
   }
   double acc = 0.0;
-  const int64_t tile = xcd_tile((nbatch + 4 * kWaveSteps - 1) / (4 * kWaveSteps));
-  // a block without a tile (grid padding) walks nothing
-  const int64_t b0 = tile >= 0 ? tile * 4 * kWaveSteps + wave : 0;
-  const int64_t bstop = tile >= 0 ? min(nbatch, (tile + 1) * 4 * kWaveSteps) : 0;
-  for (int64_t b = b0; b < bstop; b += 4) {
-    const int64_t row = b * RW + g;
-    const bool valid = row >= 0 && row < a.n;
-    const uint32_t rowc = (uint32_t)(valid ? row : a.n - 1);
-    const int32_t beg = a.row_ptr[rowc], end = a.row_ptr[rowc + 1];
+  if ((int)blockIdx.x < a.hblocks) {
+    uint32_t rowc;
     Row4 o;
-    row4_update<G>(a, rowc, valid, j, beg, end, o);
-    // first arg-max of the logits (ties to the smaller l)
-    float tv = -INFINITY;
-    int ti = INT32_MAX;
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-      if (4 * j + e < L && o.s[e] > tv) {
-        tv = o.s[e];
-        ti = 4 * j + e;
-      }
-    gargmax4<G>(tv, ti);
-    const int jt = ti;
-    float m2 = -INFINITY, T = 0.f;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int l = 4 * j + e;
-      if (l < L && l != jt) {
-        m2 = fmaxf(m2, o.s[e]);
-        T += o.e[e];
-      }
-    }
-    m2 = gmax4<G>(m2);
-    T = gsum4<G>(T);
-    float S2 = 0.f;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int l = 4 * j + e;
-      if (l < L && l != jt) S2 += expf(o.s[e] - m2);
-    }
-    S2 = gsum4<G>(S2);
-    if (!valid) continue;
-    acc += (j == 0) ? (double)o.r : 0.0;
-    const int64_t orow = f.perm ? f.perm[row] : row;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int l = 4 * j + e;
-      if (l >= L) continue;
-      float v;
-      if (L == 1) {
-        v = INFINITY;
-      } else if (l == jt) {
-        v = (o.m - m2) - logf(S2);      // log z/(1-z) for the top entry, no underflow
-      } else {
-        v = (o.s[e] - o.m) - log1pf(T - o.e[e]);
-      }
-      if (v > bv[e] || (v == bv[e] && (int)orow < bi[e])) {
-        bv[e] = v;
-        bi[e] = (int)orow;
-      }
-      if (f.z_user) f.z_user[orow * L + l] = o.z[e];
-    }
-    if (j == 0) {
-      f.labels_int[row] = jt;
-      if (f.labels_user) f.labels_user[orow] = jt;
+    const bool valid = heavy_row<G>(a, blockIdx.x, wave, g, j, rowc, o);
+    // every group of wave 0 holds the same row: all offer the same candidates, group 0 stores
+    if (wave == 0) final_row<G>(f, rowc, valid, g == 0, j, o, bv, bi, acc);
+  } else {
+    const int64_t nbatch = (a.n + RW - 1) / RW;
+    const int64_t tile = xcd_tile((nbatch + 4 * kWaveSteps - 1) / (4 * kWaveSteps), (int64_t)blockIdx.x - a.hblocks);
+    // a block without a tile (grid padding) walks nothing
+    const int64_t b0 = tile >= 0 ? tile * 4 * kWaveSteps + wave : 0;
+    const int64_t bstop = tile >= 0 ? min(nbatch, (tile + 1) * 4 * kWaveSteps) : 0;
+    for (int64_t b = b0; b < bstop; b += 4) {
+      const int64_t row = b * RW + g;
+      const uint32_t rowc = (uint32_t)(row >= 0 && row < a.n ? row : a.n - 1);
+      const int32_t beg = a.row_ptr[rowc], end = a.row_ptr[rowc + 1];
+      const bool valid = row >= 0 && row < a.n && end - beg <= a.heavy_deg;
+      Row4 o;
+      row4_update<G>(a, rowc, valid, j, beg, end, o);
+      final_row<G>(f, row, valid, true, j, o, bv, bi, acc);
     }
   }
   // combine the candidates of the groups of this wave (same j in every group)
@@ -910,37 +1011,68 @@ __device__ __forceinline__ int gsum16i(int v) {
   return v;
 }
 
+// FP64 recheck of the unary term of one row (16 lanes; the caller sums them).
+__device__ __forceinline__ double unary64_part(const EnergyArgs& e, int64_t rowc, int lab, int j) {
+  const int64_t orow = e.perm ? e.perm[rowc] : rowc;
+  const float* xp = e.x + orow * e.d;
+  const float* mp = e.x + (int64_t)e.modes[lab] * e.d;
+  double d64 = 0.0;
+  for (int k = j; k < e.d; k += 16) {
+    const double t = (double)xp[k] - (double)mp[k];
+    d64 += t * t;
+  }
+  return d64;
+}
+
 __global__ __launch_bounds__(kBlock) void energy_kernel(EnergyArgs e) {
   constexpr int G = 16, RW = 4;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, tid = threadIdx.x;
   const int g = lane / G, j = lane % G;
+  if ((int)blockIdx.x < e.hblocks) {
+    // one heavy row: the block counts its cut edges, wave 0 rechecks its unary term
+    const int hb = blockIdx.x;
+    const bool valid = hb < e.n_heavy;
+    const int64_t rowc = valid ? e.heavy[hb] : 0;
+    const int lab = e.labels_int[rowc];
+    const int32_t beg = e.row_ptr[rowc], end = valid ? e.row_ptr[rowc + 1] : beg;
+    int c = 0;
+    for (int32_t t = beg + tid; t < end; t += kBlock) c += (e.labels_int[e.col_idx[t]] != lab);
+    __shared__ int hc[kBlock];
+    hc[tid] = c;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+      if (tid < w) hc[tid] += hc[tid + w];
+      __syncthreads();
+    }
+    double d64 = 0.0;
+    if (e.x && wave == 0) d64 = gsum16d(unary64_part(e, rowc, lab, j));
+    if (tid == 0) {
+      e.part_un[blockIdx.x] = valid ? (double)e.A[rowc * e.ldz + lab] : 0.0;
+      e.part_un64[blockIdx.x] = valid && e.x ? exp(-d64 * e.inv2s2) : 0.0;
+      e.part_cut[blockIdx.x] = hc[0];
+    }
+    return;
+  }
   double un = 0.0, un64 = 0.0;
   long long cut = 0;
   const int64_t nbatch = (e.n + RW - 1) / RW;
-  const int64_t tile = xcd_tile((nbatch + 4 * kWaveSteps - 1) / (4 * kWaveSteps));
+  const int64_t tile = xcd_tile((nbatch + 4 * kWaveSteps - 1) / (4 * kWaveSteps), (int64_t)blockIdx.x - e.hblocks);
   // a block without a tile (grid padding) walks nothing
   const int64_t b0 = tile >= 0 ? tile * 4 * kWaveSteps + wave : 0;
   const int64_t bstop = tile >= 0 ? min(nbatch, (tile + 1) * 4 * kWaveSteps) : 0;
   for (int64_t b = b0; b < bstop; b += 4) {
     const int64_t row = b * RW + g;
-    const bool valid = row >= 0 && row < e.n;
-    const int64_t rowc = valid ? row : e.n - 1;
+    const int64_t rowc = row >= 0 && row < e.n ? row : e.n - 1;
     const int lab = e.labels_int[rowc];
-    const int32_t beg = e.row_ptr[rowc], end = valid ? e.row_ptr[rowc + 1] : beg;
+    const int32_t beg = e.row_ptr[rowc], end0 = e.row_ptr[rowc + 1];
+    // heavy rows belong to the work-groups in front of the grid
+    const bool valid = row >= 0 && row < e.n && end0 - beg <= e.heavy_deg;
+    const int32_t end = valid ? end0 : beg;
     int c = 0;
     for (int32_t t = beg + j; t < end; t += G) c += (e.labels_int[e.col_idx[t]] != lab);
     c = gsum16i(c);
     double d64 = 0.0;
-    if (e.x) {
-      const int64_t orow = e.perm ? e.perm[rowc] : rowc;
-      const float* xp = e.x + orow * e.d;
-      const float* mp = e.x + (int64_t)e.modes[lab] * e.d;
-      for (int k = j; k < e.d; k += G) {
-        const double t = (double)xp[k] - (double)mp[k];
-        d64 += t * t;
-      }
-      d64 = gsum16d(d64);
-    }
+    if (e.x) d64 = gsum16d(unary64_part(e, rowc, lab, j));
     if (valid && j == 0) {
       un += (double)e.A[rowc * e.ldz + lab];
       cut += c;
@@ -1104,11 +1236,11 @@ inline int groups4(int L) {
 
 inline int64_t tile_grid(int64_t ntiles) { return 8 * ((std::max<int64_t>(ntiles, 1) + 7) / 8); }
 
-int iter_grid(int64_t n, int32_t L) {
+int iter_grid(int64_t n, int32_t L, int64_t n_heavy) {
   if (L <= 64) {
     const int64_t RW = 64 / groups4(L);
     const int64_t nbatch = (n + RW - 1) / RW;
-    return (int)tile_grid((nbatch + 4 * kWaveSteps - 1) / (4 * kWaveSteps));
+    return heavy_blocks(n_heavy) + (int)tile_grid((nbatch + 4 * kWaveSteps - 1) / (4 * kWaveSteps));
   }
   const int64_t rows = 4 * (64 / lanes_for(L)) * kWaveSteps;
   return (int)tile_grid((n + rows - 1) / rows);
@@ -1190,9 +1322,9 @@ slk_status launch_mode_reduce(const float* cand_v, const int32_t* cand_i, int gr
   return SLK_OK;
 }
 
-int energy_grid(int64_t n) {
+int energy_grid(int64_t n, int64_t n_heavy) {
   const int64_t nbatch = (n + 3) / 4;
-  return (int)tile_grid((nbatch + 4 * kWaveSteps - 1) / (4 * kWaveSteps));
+  return heavy_blocks(n_heavy) + (int)tile_grid((nbatch + 4 * kWaveSteps - 1) / (4 * kWaveSteps));
 }
 
 slk_status launch_energy(const EnergyArgs& a, int grid, hipStream_t s) {

@@ -8,6 +8,18 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 
+@pytest.fixture(scope="session")
+def torch():
+    import torch as t
+    return t
+
+
+@pytest.fixture(scope="session")
+def slk():
+    import paper_1810_13044_amd as s
+    return s
+
+
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: longer CPU test")

@@ -22,18 +22,6 @@ def _say(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-@pytest.fixture(scope="module")
-def torch():
-    import torch as t
-    return t
-
-
-@pytest.fixture(scope="module")
-def slk():
-    import paper_1810_13044_amd as s
-    return s
-
-
 def to_dev(torch, a, dtype):
     return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
 
