@@ -353,7 +353,7 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t ntiles, int64_t bid) {
 
 // Tiles: each wave handles kWaveSteps row groups (scalar kernels) or row batches (float4
 // kernels) of one contiguous tile.
-constexpr int kWaveSteps = 2;
+constexpr int kWaveSteps = 4;
 
 template <int S, int E>
 __global__ __launch_bounds__(kBlock) void iter_kernel(IterArgs a) {
