@@ -240,6 +240,81 @@ slk_status slk_inner_step(const slk_graph* g, int32_t L, const float* a, const f
                           double* bound_host);
 
 /*
+ * Served and batched form (an extension; the paper fits one problem at a time).
+ *
+ * A job is one whole problem: its graph is built from its points (slk_build_knn with
+ * job->knn) and SLK-BO (slk_fit) runs on it with job->params.  A server keeps up to
+ * max_jobs jobs resident on the device and advances all of them together: each step packs
+ * the work every resident job needs next (unary term, z-updates, final pass with labels and
+ * modes, energy) into one launch per kernel, whatever the jobs' sizes, so many small problems
+ * share the GPU.  Queued jobs are admitted whenever a slot is free and the job's estimated
+ * device footprint fits the memory budget (continuous batching: jobs join and leave between
+ * steps while the others keep running).  Every job gets exactly the work-groups, tiles and
+ * reduction order of its own slk_fit, so its outputs are bit-identical to running it alone.
+ *
+ * slk_job: caller-owned descriptions and buffers, which must stay valid until the job is
+ * reported done.
+ *  x               : n x d float32 points (device).
+ *  init_modes_host : L distinct int32 indices (host; copied by slk_server_submit).
+ *  knn             : graph options (as slk_build_knn).
+ *  params          : fit options (as slk_fit).
+ *  z_out           : n x L float32 (device), labels_out: n int32 (device, may be NULL).
+ *  modes_out_host, result_host, status_host : host outputs written when the job is done
+ *                    (status SLK_OK, or the error that stopped this job alone).
+ * Limits of the served form: 1 <= L <= 64 (jobs with larger L are rejected with
+ * SLK_ERR_UNSUPPORTED; use slk_fit).
+ */
+typedef struct {
+  const float* x;
+  int64_t n;
+  int32_t d;
+  int32_t L;
+  const int32_t* init_modes_host;
+  slk_knn_opts knn;
+  slk_params params;
+  float* z_out;
+  int32_t* labels_out;
+  int32_t* modes_out_host;
+  slk_result* result_host;
+  slk_status* status_host;
+} slk_job;
+
+typedef struct {
+  int32_t max_jobs;         /* resident jobs (slots); 1 <= max_jobs <= 1024                    */
+  int32_t passes_per_step;  /* z-updates queued per step for jobs in their inner loop (>= 1)    */
+  int64_t memory_budget;    /* bytes of device memory the resident jobs may use (0 = 80% of
+                               the free memory when the server is created)                     */
+} slk_server_opts;
+
+typedef struct slk_server slk_server;
+
+/* Fill *o with defaults: max_jobs 64, passes_per_step 2, memory_budget 0. */
+slk_status slk_server_opts_default(slk_server_opts* o);
+
+/* Create a server that runs on `stream` (device = the current device).  Release with
+   slk_server_destroy (which drops unfinished jobs). */
+slk_status slk_server_create(const slk_server_opts* opts, void* stream, slk_server** out);
+
+/* Queue a job; *ticket_host receives its id (0, 1, 2, ... in submission order).  Checks the
+   job's arguments at once (n >= 2, d >= 1, 1 <= L <= min(64, n), modes distinct and in range,
+   parameters and kNN options valid). */
+slk_status slk_server_submit(slk_server* sv, const slk_job* job, int64_t* ticket_host);
+
+/* Admit what fits, then run one step for every resident job and synchronise the server's
+   stream.  done_host (may be NULL) receives up to `cap` tickets of jobs finished in this or an
+   earlier step and not yet reported; *n_done_host their number.  *n_active_host and
+   *n_queued_host (may be NULL) receive the resident and waiting job counts after the step. */
+slk_status slk_server_step(slk_server* sv, int64_t* done_host, int32_t cap, int32_t* n_done_host,
+                           int32_t* n_active_host, int32_t* n_queued_host);
+
+void slk_server_destroy(slk_server* sv);
+
+/* Fit every job in jobs[0 .. n_jobs-1] with a server (opts may be NULL: defaults) and return
+   when all are done.  Per-job failures are reported in their status_host; the call itself
+   fails only for invalid arguments or a device error. */
+slk_status slk_fit_batched(const slk_job* jobs, int32_t n_jobs, const slk_server_opts* opts, void* stream);
+
+/*
  * Per-kernel timing for measurement: with timing on, every launch of the iteration kernels
  * ("unary_kernel", "iter_kernel", "final_kernel", "mode_reduce_kernel", "energy_kernel") made
  * by slk_assign / slk_fit is bracketed by two HIP events recorded on the call's stream, and

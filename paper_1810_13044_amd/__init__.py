@@ -235,6 +235,122 @@ def inner_step(graph: Graph, a, z_in, lam=1.0, delta=0.0, scale=1):
     return z_out, b.value
 
 
+# ----------------------------------------------------------------------------- served form
+
+def knn_opts(k=10, method="auto", reorder=False, prec="fp32", candidates=0):
+    o = _lib.KnnOpts()
+    _lib.check(_lib.load().slk_knn_opts_default(C.byref(o)))
+    o.k = int(k)
+    o.reorder = int(bool(reorder))
+    o.candidates = int(candidates)
+    o.method = {"auto": 0, "exact": 1, "mfma": 2}[method]
+    o.prec = _prec(prec)
+    return o
+
+
+class _JobRec:
+    """One submitted job: its C description plus the buffers it points into (kept alive here)."""
+
+    def __init__(self, x, init_modes, lam, k, method, reorder, knn_prec, labels, **kw):
+        torch = _torch()
+        n, d = x.shape
+        self.x = x
+        self.modes_in = _lib.host_i32(init_modes)
+        L = len(self.modes_in)
+        self.z, self.labels = _outputs(n, L, labels)
+        self.modes_out = np.zeros(L, dtype=np.int32)
+        self.res = _lib.Result()
+        self.status = C.c_int(-1)
+        j = _lib.Job()
+        j.x = _dev(x, torch.float32, "x")
+        j.n, j.d, j.L = n, d, L
+        j.init_modes_host = _lib.ptr_i32(self.modes_in)
+        j.knn = knn_opts(k=k, method=method, reorder=reorder, prec=knn_prec)
+        j.params = params(lam=lam, **kw)
+        j.z_out = _dev(self.z, torch.float32, "z")
+        j.labels_out = _dev(self.labels, torch.int32, "labels") if labels else None
+        j.modes_out_host = _lib.ptr_i32(self.modes_out)
+        j.result_host = C.cast(C.pointer(self.res), C.c_void_p)
+        j.status_host = C.cast(C.pointer(self.status), C.c_void_p)
+        self.job = j
+
+    def outcome(self):
+        return dict(z=self.z, labels=self.labels, modes=self.modes_out.copy(), result=self.res.as_dict(),
+                    status=self.status.value)
+
+
+class Server:
+    """Continuous-batching server (slk_server_*): submit jobs at any time, call step() to
+    admit what fits and advance every resident job; finished jobs' outcomes are returned by
+    step() and kept in .done."""
+
+    def __init__(self, max_jobs=64, passes_per_step=2, memory_budget=0):
+        self._lib = _lib.load()
+        o = _lib.ServerOpts()
+        _lib.check(self._lib.slk_server_opts_default(C.byref(o)))
+        o.max_jobs, o.passes_per_step, o.memory_budget = int(max_jobs), int(passes_per_step), int(memory_budget)
+        h = C.c_void_p()
+        _lib.check(self._lib.slk_server_create(C.byref(o), _stream(), C.byref(h)))
+        self._h = h
+        self._jobs = {}
+        self.done = {}
+        self._buf = np.zeros(max(int(max_jobs), 1) * 4, dtype=np.int64)
+
+    def submit(self, x, init_modes, lam=1.0, k=10, method="auto", reorder=False, knn_prec="fp32", labels=True,
+               **kw) -> int:
+        rec = _JobRec(x, init_modes, lam, k, method, reorder, knn_prec, labels, **kw)
+        t = C.c_int64(-1)
+        _lib.check(self._lib.slk_server_submit(self._h, C.byref(rec.job), C.byref(t)))
+        self._jobs[t.value] = rec
+        return t.value
+
+    def step(self):
+        """One step; returns {ticket: outcome} for the jobs that finished."""
+        nd, na, nq = C.c_int32(0), C.c_int32(0), C.c_int32(0)
+        _lib.check(self._lib.slk_server_step(self._h, self._buf.ctypes.data_as(C.c_void_p), len(self._buf),
+                                             C.byref(nd), C.byref(na), C.byref(nq)))
+        self.active, self.queued = na.value, nq.value
+        out = {}
+        for t in self._buf[: nd.value].tolist():
+            out[t] = self._jobs.pop(t).outcome()
+        self.done.update(out)
+        return out
+
+    def pending(self) -> int:
+        return len(self._jobs)
+
+    def close(self):
+        if self._h:
+            self._lib.slk_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fit_batched(problems, max_jobs=64, passes_per_step=2, **common):
+    """Fit a list of problems with slk_fit_batched.  Each problem is a dict with x and
+    init_modes (and optionally lam, k, method, reorder, knn_prec and slk_params keywords);
+    `common` supplies defaults.  Returns one outcome dict per problem, in order."""
+    lib = _lib.load()
+    recs = []
+    for pr in problems:
+        kw = dict(common)
+        kw.update(pr)
+        x, m = kw.pop("x"), kw.pop("init_modes")
+        recs.append(_JobRec(x, m, kw.pop("lam", 1.0), kw.pop("k", 10), kw.pop("method", "auto"),
+                            kw.pop("reorder", False), kw.pop("knn_prec", "fp32"), kw.pop("labels", True), **kw))
+    arr = (_lib.Job * len(recs))(*[r.job for r in recs])
+    o = _lib.ServerOpts()
+    _lib.check(lib.slk_server_opts_default(C.byref(o)))
+    o.max_jobs, o.passes_per_step = int(max_jobs), int(passes_per_step)
+    _lib.check(lib.slk_fit_batched(arr, len(recs), C.byref(o), _stream()))
+    return [r.outcome() for r in recs]
+
+
 def timing_enable(on: bool = True) -> None:
     """Switch per-kernel HIP-event timing on or off (clears the totals)."""
     _lib.check(_lib.load().slk_timing_enable(int(bool(on))))

@@ -59,9 +59,13 @@ class EnergyOut(C.Structure):
 
 class Job(C.Structure):
     _fields_ = [("x", C.c_void_p), ("n", C.c_int64), ("d", C.c_int32), ("L", C.c_int32),
-                ("graph", C.c_void_p), ("init_modes", C.c_void_p), ("z_out", C.c_void_p),
-                ("labels_out", C.c_void_p), ("modes_out", C.c_void_p), ("lambda_", C.c_double),
-                ("sigma2", C.c_double)]
+                ("init_modes_host", C.c_void_p), ("knn", KnnOpts), ("params", Params),
+                ("z_out", C.c_void_p), ("labels_out", C.c_void_p), ("modes_out_host", C.c_void_p),
+                ("result_host", C.c_void_p), ("status_host", C.c_void_p)]
+
+
+class ServerOpts(C.Structure):
+    _fields_ = [("max_jobs", C.c_int32), ("passes_per_step", C.c_int32), ("memory_budget", C.c_int64)]
 
 
 _lib = None
@@ -102,11 +106,19 @@ def load(path: str = LIB_PATH):
     lib.slk_graph_destroy.restype = None
     lib.slk_last_error.restype = C.c_char_p
     lib.slk_version.restype = C.c_char_p
-    if hasattr(lib, "slk_fit_batched"):
-        lib.slk_fit_batched.argtypes = [C.POINTER(Job), I32, C.POINTER(Params), P, P, C.c_size_t, C.POINTER(Result)]
-        lib.slk_fit_batched.restype = C.c_int
-        lib.slk_batch_workspace_size.argtypes = [C.POINTER(Job), I32, C.POINTER(C.c_size_t)]
-        lib.slk_batch_workspace_size.restype = C.c_int
+    srv = {
+        "slk_server_opts_default": [C.POINTER(ServerOpts)],
+        "slk_server_create": [C.POINTER(ServerOpts), P, C.POINTER(P)],
+        "slk_server_submit": [P, C.POINTER(Job), C.POINTER(C.c_int64)],
+        "slk_server_step": [P, P, I32, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32)],
+        "slk_fit_batched": [C.POINTER(Job), I32, C.POINTER(ServerOpts), P],
+    }
+    for name, args in srv.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = C.c_int
+    lib.slk_server_destroy.argtypes = [P]
+    lib.slk_server_destroy.restype = None
     _lib = lib
     return lib
 

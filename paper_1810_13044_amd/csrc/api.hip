@@ -435,23 +435,8 @@ slk_status prepare_col_off(const slk_graph* g, int32_t L, Scratch& sc, uint32_t*
   return launch_col_offsets(g->col_idx, g->nnz, g->n, L, *out, sc.stream);
 }
 
-// Heavy rows go to their own work-groups on the float4 path (L <= 64) and in the energy.
-int64_t heavy_rows_for(const slk_graph* g, int32_t L) { return L <= 64 ? g->n_heavy : 0; }
 
-void set_heavy(IterArgs& a, const slk_graph* g, int32_t L) {
-  const int64_t nh = heavy_rows_for(g, L);
-  a.heavy = nh ? g->heavy : nullptr;
-  a.n_heavy = (int32_t)nh;
-  a.hblocks = heavy_blocks(nh);
-  a.heavy_deg = nh ? kHeavyDeg : INT32_MAX;
-}
 
-void set_heavy(EnergyArgs& e, const slk_graph* g) {
-  e.heavy = g->n_heavy ? g->heavy : nullptr;
-  e.n_heavy = (int32_t)g->n_heavy;
-  e.hblocks = heavy_blocks(g->n_heavy);
-  e.heavy_deg = g->n_heavy ? kHeavyDeg : INT32_MAX;
-}
 
 slk_status alloc_work(Scratch& sc, const slk_graph* g, int32_t L, int trace_cap, Work& w) {
   const int64_t n = g->n;
@@ -628,26 +613,7 @@ slk_status run_outer(const float* x, int64_t n, int32_t d, const slk_graph* g, i
   return SLK_OK;
 }
 
-slk_status check_params(const slk_params* p) {
-  if (!p) return fail(SLK_ERR_INVALID_ARG, "params is NULL");
-  if (!(p->lambda >= 0.0) || !isfinite(p->lambda)) return fail(SLK_ERR_INVALID_ARG, "lambda must be finite and >= 0");
-  if (!(p->delta >= 0.0) || !isfinite(p->delta)) return fail(SLK_ERR_INVALID_ARG, "delta must be finite and >= 0");
-  if (!isfinite(p->sigma2)) return fail(SLK_ERR_INVALID_ARG, "sigma2 must be finite");
-  if (!(p->bound_tol >= 0.0)) return fail(SLK_ERR_INVALID_ARG, "bound_tol must be >= 0");
-  if (p->max_outer < 1) return fail(SLK_ERR_INVALID_ARG, "max_outer must be >= 1");
-  if (p->max_inner < 1) return fail(SLK_ERR_INVALID_ARG, "max_inner must be >= 1");
-  if (p->fixed_inner < 0) return fail(SLK_ERR_INVALID_ARG, "fixed_inner must be >= 0");
-  if (p->pairwise_scale != 1 && p->pairwise_scale != 2) return fail(SLK_ERR_INVALID_ARG, "pairwise_scale must be 1 or 2");
-  if (p->prec != SLK_PREC_FP32 && p->prec != SLK_PREC_BF16) return fail(SLK_ERR_INVALID_ARG, "unknown precision");
-  return SLK_OK;
-}
 
-slk_status check_points(const float* x, int64_t n, int32_t d) {
-  if (!x) return fail(SLK_ERR_INVALID_ARG, "x is NULL");
-  if (n < 2 || n >= (int64_t)INT32_MAX) return fail(SLK_ERR_INVALID_ARG, "n must satisfy 2 <= n < 2^31");
-  if (d < 1) return fail(SLK_ERR_INVALID_ARG, "d must be >= 1");
-  return SLK_OK;
-}
 
 slk_status check_problem(const float* x, int64_t n, int32_t d, const slk_graph* g, int32_t L, const int32_t* modes_host) {
   SLK_TRY(check_points(x, n, d));
@@ -665,9 +631,50 @@ slk_status check_problem(const float* x, int64_t n, int32_t d, const slk_graph* 
   return SLK_OK;
 }
 
-double pick_sigma2(const slk_params& p, const slk_graph* g) { return p.sigma2 > 0.0 ? p.sigma2 : g->sigma2; }
 
 }  // namespace
+
+// Shared with the served form.
+slk_status check_points(const float* x, int64_t n, int32_t d) {
+  if (!x) return fail(SLK_ERR_INVALID_ARG, "x is NULL");
+  if (n < 2 || n >= (int64_t)INT32_MAX) return fail(SLK_ERR_INVALID_ARG, "n must satisfy 2 <= n < 2^31");
+  if (d < 1) return fail(SLK_ERR_INVALID_ARG, "d must be >= 1");
+  return SLK_OK;
+}
+
+slk_status check_params(const slk_params* p) {
+  if (!p) return fail(SLK_ERR_INVALID_ARG, "params is NULL");
+  if (!(p->lambda >= 0.0) || !isfinite(p->lambda)) return fail(SLK_ERR_INVALID_ARG, "lambda must be finite and >= 0");
+  if (!(p->delta >= 0.0) || !isfinite(p->delta)) return fail(SLK_ERR_INVALID_ARG, "delta must be finite and >= 0");
+  if (!isfinite(p->sigma2)) return fail(SLK_ERR_INVALID_ARG, "sigma2 must be finite");
+  if (!(p->bound_tol >= 0.0)) return fail(SLK_ERR_INVALID_ARG, "bound_tol must be >= 0");
+  if (p->max_outer < 1) return fail(SLK_ERR_INVALID_ARG, "max_outer must be >= 1");
+  if (p->max_inner < 1) return fail(SLK_ERR_INVALID_ARG, "max_inner must be >= 1");
+  if (p->fixed_inner < 0) return fail(SLK_ERR_INVALID_ARG, "fixed_inner must be >= 0");
+  if (p->pairwise_scale != 1 && p->pairwise_scale != 2) return fail(SLK_ERR_INVALID_ARG, "pairwise_scale must be 1 or 2");
+  if (p->prec != SLK_PREC_FP32 && p->prec != SLK_PREC_BF16) return fail(SLK_ERR_INVALID_ARG, "unknown precision");
+  return SLK_OK;
+}
+
+double pick_sigma2(const slk_params& p, const slk_graph* g) { return p.sigma2 > 0.0 ? p.sigma2 : g->sigma2; }
+
+int64_t heavy_rows_for(const slk_graph* g, int32_t L) { return L <= 64 ? g->n_heavy : 0; }
+
+void set_heavy(IterArgs& a, const slk_graph* g, int32_t L) {
+  const int64_t nh = heavy_rows_for(g, L);
+  a.heavy = nh ? g->heavy : nullptr;
+  a.n_heavy = (int32_t)nh;
+  a.hblocks = heavy_blocks(nh);
+  a.heavy_deg = nh ? kHeavyDeg : INT32_MAX;
+}
+
+void set_heavy(EnergyArgs& e, const slk_graph* g) {
+  e.heavy = g->n_heavy ? g->heavy : nullptr;
+  e.n_heavy = (int32_t)g->n_heavy;
+  e.hblocks = heavy_blocks(g->n_heavy);
+  e.heavy_deg = g->n_heavy ? kHeavyDeg : INT32_MAX;
+}
+
 }  // namespace slk
 
 using namespace slk;
@@ -979,8 +986,6 @@ static slk_status assign_or_fit(bool fit, const float* x, int64_t n, int32_t d, 
   OuterOut o;
   const int outer_cap = fit ? p.max_outer : 1;
   for (int t = 0; t < outer_cap; ++t) {
-    const bool last_possible = (t == outer_cap - 1);
-    (void)last_possible;
     SLK_TRY(run_outer(x, n, d, g, L, p, sigma2, cap, 0, s, w, z_out, labels_out, &o));
     SLK_HIP(hipMemcpyAsync(nxt.data(), w.modes_next, sizeof(int32_t) * L, hipMemcpyDeviceToHost, s));
     SLK_HIP(hipStreamSynchronize(s));
@@ -999,6 +1004,8 @@ static slk_status assign_or_fit(bool fit, const float* x, int64_t n, int32_t d, 
       r.converged = 1;
       break;
     }
+    // out of outer iterations: w.modes keeps the modes that produced the last labels
+    if (t + 1 == outer_cap) break;
     cur = nxt;
     SLK_HIP(hipMemcpyAsync(w.modes, w.modes_next, sizeof(int32_t) * L, hipMemcpyDeviceToDevice, s));
   }
@@ -1024,7 +1031,7 @@ static slk_status assign_or_fit(bool fit, const float* x, int64_t n, int32_t d, 
     e.part_cut = w.epart_cut;
     e.out = w.eout;
     e.out_cut = w.eout_cut;
-      SLK_TRY(launch_energy(e, w.egrid, s));
+    SLK_TRY(launch_energy(e, w.egrid, s));
     double eo[2];
     SLK_HIP(hipMemcpyAsync(eo, w.eout, sizeof(eo), hipMemcpyDeviceToHost, s));
     SLK_HIP(hipStreamSynchronize(s));

@@ -192,10 +192,57 @@ struct FinalArgs {
   int32_t* labels_user;  // n labels, original order (null = none)
   float* cand_v;         // grid x L best log-odds per block
   int32_t* cand_i;       // grid x L original index of that candidate
+  int32_t grid;          // work-groups of this pass (the candidate arrays' row length)
+};
+
+struct UnaryArgs {
+  const float* x;        // n x d, original order
+  int64_t n;
+  int32_t d, L, ldz, R;  // R rows per work-group
+  const int32_t* perm;   // internal -> original (null = identity)
+  const int32_t* modes;  // L original indices (device)
+  float inv2s2;
+  int32_t bf16;
+  float* A;              // n x ldz, internal order (may be null)
+  float* Z0;             // n x ldz (may be null)
+};
+
+// One job of a packed pass reduction (one work-group per job).
+struct ReduceJob {
+  const double* partial;
+  int32_t nparts;
+  IterState* state;
+  double* trace;
+  double* bound_out;
+};
+
+// One job of a packed mode reduction (one work-group per cluster).
+struct ModeJob {
+  const float* cand_v;
+  const int32_t* cand_i;
+  int32_t grid;
+  int32_t* modes;
 };
 
 slk_status launch_unary(const float* x, int64_t n, int32_t d, const int32_t* perm, const int32_t* modes_dev,
                         int32_t L, int32_t ldz, double sigma2, int32_t bf16, float* A, float* Z0, hipStream_t s);
+UnaryArgs unary_args(const float* x, int64_t n, int32_t d, const int32_t* perm, const int32_t* modes_dev, int32_t L,
+                     int32_t ldz, double sigma2, int32_t bf16, float* A, float* Z0);
+int unary_grid(const UnaryArgs& u);
+size_t unary_lds(const UnaryArgs& u);
+int groups4(int L);
+
+// Packed launches: one launch covers several jobs; `start` (device, njobs + 1 entries) holds the
+// first work-group of each job and the total, `jobs` (device) the per-job arguments.  Every job
+// gets exactly the work-groups, tiles and reduction order of its own unpacked launch, so its
+// results are bit-identical to running it alone.
+slk_status launch_unary_packed(const UnaryArgs* jobs, const int32_t* start, int njobs, int blocks, size_t lds,
+                               hipStream_t s);
+slk_status launch_iter_packed(int G, const IterArgs* jobs, const int32_t* start, int njobs, int blocks, hipStream_t s);
+slk_status launch_final_packed(int G, const FinalArgs* jobs, const int32_t* start, int njobs, int blocks,
+                               hipStream_t s);
+slk_status launch_reduce_packed(const ReduceJob* jobs, int njobs, hipStream_t s);
+slk_status launch_mode_reduce_packed(const ModeJob* jobs, const int32_t* start, int njobs, int blocks, hipStream_t s);
 int iter_grid(int64_t n, int32_t L, int64_t n_heavy);
 slk_status launch_iter(const IterArgs& a, int grid, hipStream_t s);
 slk_status launch_final(const FinalArgs& a, int grid, hipStream_t s);
@@ -225,6 +272,15 @@ struct EnergyArgs {
 // Grids include the heavy-row work-groups in front (n_heavy = 0: none).
 int energy_grid(int64_t n, int64_t n_heavy);
 slk_status launch_energy(const EnergyArgs& a, int grid, hipStream_t s);
+slk_status launch_energy_packed(const EnergyArgs* jobs, const int32_t* start, int njobs, int blocks, hipStream_t s);
+// argument checks and per-graph settings shared by the C ABI and the served form (api.hip)
+slk_status check_points(const float* x, int64_t n, int32_t d);
+slk_status check_params(const slk_params* p);
+double pick_sigma2(const slk_params& p, const slk_graph* g);
+int64_t heavy_rows_for(const slk_graph* g, int32_t L);
+void set_heavy(IterArgs& a, const slk_graph* g, int32_t L);
+void set_heavy(EnergyArgs& e, const slk_graph* g);
+
 // caller layout (stride L, original order) <-> internal layout (stride ldz, internal order)
 slk_status launch_gather_rows(const float* src, const int32_t* perm, int64_t n, int32_t L, int32_t ldz, float* dst,
                               hipStream_t s);

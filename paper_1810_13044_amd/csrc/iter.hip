@@ -68,11 +68,15 @@ constexpr int kUT = 4;       // rows and modes per thread tile
 constexpr int kUTiles = 2;   // tiles per thread
 
 template <int DC>
-__global__ __launch_bounds__(kBlock) void unary_kernel(const float* __restrict__ x, int64_t n, int d,
-                                                       const int32_t* __restrict__ perm,
-                                                       const int32_t* __restrict__ modes, int L, int ldz, int R,
-                                                       float inv2s2, int bf16, float* __restrict__ A,
-                                                       float* __restrict__ Z0) {
+__device__ __forceinline__ void unary_block(const UnaryArgs& u, int64_t bid) {
+  const float* __restrict__ x = u.x;
+  const int64_t n = u.n;
+  const int d = u.d, L = u.L, ldz = u.ldz, R = u.R, bf16 = u.bf16;
+  const int32_t* __restrict__ perm = u.perm;
+  const int32_t* __restrict__ modes = u.modes;
+  const float inv2s2 = u.inv2s2;
+  float* __restrict__ A = u.A;
+  float* __restrict__ Z0 = u.Z0;
   extern __shared__ float sm[];
   const int MG = (L + kUT - 1) / kUT;
   const int RS = R + 4, MS = MG * kUT + 4;  // padded strides (multiples of 4 floats)
@@ -80,7 +84,7 @@ __global__ __launch_bounds__(kBlock) void unary_kernel(const float* __restrict__
   float* ms = xs + DC * RS;       // DC x MS
   float* as = ms + DC * MS;       // R x L
   const int tid = threadIdx.x;
-  const int64_t row0 = (int64_t)blockIdx.x * R;
+  const int64_t row0 = bid * R;
   const int nr = (int)min<int64_t>(R, n - row0);
   const int ntiles = (R / kUT) * MG;
   float acc[kUTiles][kUT][kUT];
@@ -176,6 +180,29 @@ __global__ __launch_bounds__(kBlock) void unary_kernel(const float* __restrict__
       if (Z0) Z0[row * ldz + l] = l < L ? expf(a - m) / s : 0.f;
     }
   }
+}
+
+template <int DC>
+__global__ __launch_bounds__(kBlock) void unary_kernel(UnaryArgs u) {
+  unary_block<DC>(u, blockIdx.x);
+}
+
+// Index of the job owning block b: start[j] <= b < start[j + 1] (start has njobs + 1 entries).
+__device__ __forceinline__ int job_of(const int32_t* __restrict__ start, int njobs, int b) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int DC>
+__global__ __launch_bounds__(kBlock) void unary_packed(const UnaryArgs* __restrict__ jobs,
+                                                       const int32_t* __restrict__ start, int njobs) {
+  const int j = job_of(start, njobs, blockIdx.x);
+  unary_block<DC>(jobs[j], (int64_t)blockIdx.x - start[j]);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -325,9 +352,9 @@ __device__ __forceinline__ void row_loop(const IterArgs& a, int64_t first, int64
 }
 
 // Fixed-order block sum of the per-group bound partials (group leaders hold them), written to
-// partial[blockIdx.x]; pass_reduce_kernel then sums the blocks in a fixed order.
+// partial[bid]; pass_reduce_kernel then sums the blocks in a fixed order.
 template <int G>
-__device__ __forceinline__ void block_partial(double* partial, double acc, int g, int l0) {
+__device__ __forceinline__ void block_partial(double* partial, int64_t bid, double acc, int g, int l0) {
   __shared__ double red[4 * G];
   const int tid = threadIdx.x, wave = tid >> 6;
   if (l0 == 0) red[wave * G + g] = acc;
@@ -335,7 +362,7 @@ __device__ __forceinline__ void block_partial(double* partial, double acc, int g
   if (tid == 0) {
     double s = 0.0;
     for (int i = 0; i < 4 * G; ++i) s += red[i];
-    partial[blockIdx.x] = s;
+    partial[bid] = s;
   }
 }
 
@@ -379,7 +406,7 @@ __global__ __launch_bounds__(kBlock) void iter_kernel(IterArgs a) {
                      acc += (double)o.r;
                    });
   }
-  block_partial<G>(a.partial, acc, g, l0);
+  block_partial<G>(a.partial, blockIdx.x, acc, g, l0);
 }
 
 // final pass: labels, log-odds candidates, output Z in the caller's order
@@ -504,7 +531,7 @@ __global__ __launch_bounds__(kBlock) void final_kernel(FinalArgs f) {
     f.cand_v[(int64_t)l * gridDim.x + blockIdx.x] = v;
     f.cand_i[(int64_t)l * gridDim.x + blockIdx.x] = i;
   }
-  block_partial<G>(a.partial, acc, g, l0);
+  block_partial<G>(a.partial, blockIdx.x, acc, g, l0);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -774,7 +801,7 @@ __device__ __forceinline__ bool heavy_row(const IterArgs& a, int hb, int wave, i
 }
 
 template <int G>
-__global__ __launch_bounds__(kBlock) void iter4_kernel(IterArgs a) {
+__device__ __forceinline__ void iter4_block(const IterArgs& a, int bid) {
   if (a.state->done) return;
   constexpr int RW = 64 / G;  // rows per wave
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -782,20 +809,20 @@ __global__ __launch_bounds__(kBlock) void iter4_kernel(IterArgs a) {
   const uint32_t L4 = (uint32_t)(a.ldz >> 2);
   float4* __restrict__ O4 = reinterpret_cast<float4*>(a.Zout);
   double acc = 0.0;
-  if ((int)blockIdx.x < a.hblocks) {
+  if (bid < a.hblocks) {
     uint32_t rowc;
     Row4 o;
-    const bool valid = heavy_row<G>(a, blockIdx.x, wave, g, j, rowc, o);
+    const bool valid = heavy_row<G>(a, bid, wave, g, j, rowc, o);
     if (valid && wave == 0 && g == 0) {
       if (O4 && (uint32_t)j < L4)
         __builtin_nontemporal_store(vf4{o.z[0], o.z[1], o.z[2], o.z[3]}, reinterpret_cast<vf4*>(O4) + (rowc * L4 + j));
       if (j == 0) acc = (double)o.r;
     }
-    block_partial<RW>(a.partial, acc, g, j);
+    block_partial<RW>(a.partial, bid, acc, g, j);
     return;
   }
   const int64_t nbatch = (a.n + RW - 1) / RW;
-  const int64_t tile = xcd_tile((nbatch + 4 * kWaveSteps - 1) / (4 * kWaveSteps), (int64_t)blockIdx.x - a.hblocks);
+  const int64_t tile = xcd_tile((nbatch + 4 * kWaveSteps - 1) / (4 * kWaveSteps), (int64_t)bid - a.hblocks);
   // a block without a tile (grid padding) walks nothing: b0 = bstop = 0
   const int64_t b0 = tile >= 0 ? tile * 4 * kWaveSteps + wave : 0;
   const int64_t bstop = tile >= 0 ? min(nbatch, (tile + 1) * 4 * kWaveSteps) : 0;
@@ -813,7 +840,19 @@ __global__ __launch_bounds__(kBlock) void iter4_kernel(IterArgs a) {
       if (j == 0) acc += (double)o.r;
     }
   }
-  block_partial<RW>(a.partial, acc, g, j);
+  block_partial<RW>(a.partial, bid, acc, g, j);
+}
+
+template <int G>
+__global__ __launch_bounds__(kBlock) void iter4_kernel(IterArgs a) {
+  iter4_block<G>(a, blockIdx.x);
+}
+
+template <int G>
+__global__ __launch_bounds__(kBlock) void iter4_packed(const IterArgs* __restrict__ jobs,
+                                                       const int32_t* __restrict__ start, int njobs) {
+  const int j = job_of(start, njobs, blockIdx.x);
+  iter4_block<G>(jobs[j], blockIdx.x - start[j]);
 }
 
 // Labels, byproduct-mode candidates and caller-order outputs of one finished row.  `valid`
@@ -879,7 +918,7 @@ __device__ __forceinline__ void final_row(const FinalArgs& f, int64_t row, bool 
 }
 
 template <int G>
-__global__ __launch_bounds__(kBlock) void final4_kernel(FinalArgs f) {
+__device__ __forceinline__ void final4_block(const FinalArgs& f, int bid) {
   const IterArgs& a = f.it;
   constexpr int RW = 64 / G;
   const int L = a.L;
@@ -893,15 +932,15 @@ __global__ __launch_bounds__(kBlock) void final4_kernel(FinalArgs f) {
     bi[e] = INT32_MAX;
   }
   double acc = 0.0;
-  if ((int)blockIdx.x < a.hblocks) {
+  if (bid < a.hblocks) {
     uint32_t rowc;
     Row4 o;
-    const bool valid = heavy_row<G>(a, blockIdx.x, wave, g, j, rowc, o);
+    const bool valid = heavy_row<G>(a, bid, wave, g, j, rowc, o);
     // every group of wave 0 holds the same row: all offer the same candidates, group 0 stores
     if (wave == 0) final_row<G>(f, rowc, valid, g == 0, j, o, bv, bi, acc);
   } else {
     const int64_t nbatch = (a.n + RW - 1) / RW;
-    const int64_t tile = xcd_tile((nbatch + 4 * kWaveSteps - 1) / (4 * kWaveSteps), (int64_t)blockIdx.x - a.hblocks);
+    const int64_t tile = xcd_tile((nbatch + 4 * kWaveSteps - 1) / (4 * kWaveSteps), (int64_t)bid - a.hblocks);
     // a block without a tile (grid padding) walks nothing
     const int64_t b0 = tile >= 0 ? tile * 4 * kWaveSteps + wave : 0;
     const int64_t bstop = tile >= 0 ? min(nbatch, (tile + 1) * 4 * kWaveSteps) : 0;
@@ -949,15 +988,27 @@ __global__ __launch_bounds__(kBlock) void final4_kernel(FinalArgs f) {
         i = ci[w][l];
       }
     }
-    f.cand_v[(int64_t)l * gridDim.x + blockIdx.x] = v;
-    f.cand_i[(int64_t)l * gridDim.x + blockIdx.x] = i;
+    f.cand_v[(int64_t)l * f.grid + bid] = v;
+    f.cand_i[(int64_t)l * f.grid + bid] = i;
   }
-  block_partial<RW>(a.partial, acc, g, j);
+  block_partial<RW>(a.partial, bid, acc, g, j);
 }
 
-__global__ __launch_bounds__(kBlock) void mode_reduce_kernel(const float* __restrict__ cv, const int32_t* __restrict__ ci,
-                                                             int grid, int L, int32_t* __restrict__ modes) {
-  const int l = blockIdx.x, tid = threadIdx.x;
+template <int G>
+__global__ __launch_bounds__(kBlock) void final4_kernel(FinalArgs f) {
+  final4_block<G>(f, blockIdx.x);
+}
+
+template <int G>
+__global__ __launch_bounds__(kBlock) void final4_packed(const FinalArgs* __restrict__ jobs,
+                                                        const int32_t* __restrict__ start, int njobs) {
+  const int j = job_of(start, njobs, blockIdx.x);
+  final4_block<G>(jobs[j], blockIdx.x - start[j]);
+}
+
+__device__ __forceinline__ void mode_reduce_block(const float* __restrict__ cv, const int32_t* __restrict__ ci, int grid,
+                                                  int32_t* __restrict__ modes, int l) {
+  const int tid = threadIdx.x;
   float v = -INFINITY;
   int i = INT32_MAX;
   for (int b = tid; b < grid; b += kBlock) {
@@ -983,6 +1034,19 @@ __global__ __launch_bounds__(kBlock) void mode_reduce_kernel(const float* __rest
     __syncthreads();
   }
   if (tid == 0) modes[l] = si[0] == INT32_MAX ? 0 : si[0];
+}
+
+__global__ __launch_bounds__(kBlock) void mode_reduce_kernel(const float* __restrict__ cv, const int32_t* __restrict__ ci,
+                                                             int grid, int L, int32_t* __restrict__ modes) {
+  mode_reduce_block(cv, ci, grid, modes, blockIdx.x);
+}
+
+// one block per (job, cluster): start[j] = first block of job j, L_j blocks each
+__global__ __launch_bounds__(kBlock) void mode_reduce_packed(const ModeJob* __restrict__ jobs,
+                                                             const int32_t* __restrict__ start, int njobs) {
+  const int j = job_of(start, njobs, blockIdx.x);
+  const ModeJob m = jobs[j];
+  mode_reduce_block(m.cand_v, m.cand_i, m.grid, m.modes, blockIdx.x - start[j]);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1024,13 +1088,13 @@ __device__ __forceinline__ double unary64_part(const EnergyArgs& e, int64_t rowc
   return d64;
 }
 
-__global__ __launch_bounds__(kBlock) void energy_kernel(EnergyArgs e) {
+__device__ __forceinline__ void energy_block(const EnergyArgs& e, int bid) {
   constexpr int G = 16, RW = 4;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, tid = threadIdx.x;
   const int g = lane / G, j = lane % G;
-  if ((int)blockIdx.x < e.hblocks) {
+  if (bid < e.hblocks) {
     // one heavy row: the block counts its cut edges, wave 0 rechecks its unary term
-    const int hb = blockIdx.x;
+    const int hb = bid;
     const bool valid = hb < e.n_heavy;
     const int64_t rowc = valid ? e.heavy[hb] : 0;
     const int lab = e.labels_int[rowc];
@@ -1047,16 +1111,16 @@ __global__ __launch_bounds__(kBlock) void energy_kernel(EnergyArgs e) {
     double d64 = 0.0;
     if (e.x && wave == 0) d64 = gsum16d(unary64_part(e, rowc, lab, j));
     if (tid == 0) {
-      e.part_un[blockIdx.x] = valid ? (double)e.A[rowc * e.ldz + lab] : 0.0;
-      e.part_un64[blockIdx.x] = valid && e.x ? exp(-d64 * e.inv2s2) : 0.0;
-      e.part_cut[blockIdx.x] = hc[0];
+      e.part_un[bid] = valid ? (double)e.A[rowc * e.ldz + lab] : 0.0;
+      e.part_un64[bid] = valid && e.x ? exp(-d64 * e.inv2s2) : 0.0;
+      e.part_cut[bid] = hc[0];
     }
     return;
   }
   double un = 0.0, un64 = 0.0;
   long long cut = 0;
   const int64_t nbatch = (e.n + RW - 1) / RW;
-  const int64_t tile = xcd_tile((nbatch + 4 * kWaveSteps - 1) / (4 * kWaveSteps), (int64_t)blockIdx.x - e.hblocks);
+  const int64_t tile = xcd_tile((nbatch + 4 * kWaveSteps - 1) / (4 * kWaveSteps), (int64_t)bid - e.hblocks);
   // a block without a tile (grid padding) walks nothing
   const int64_t b0 = tile >= 0 ? tile * 4 * kWaveSteps + wave : 0;
   const int64_t bstop = tile >= 0 ? min(nbatch, (tile + 1) * 4 * kWaveSteps) : 0;
@@ -1096,17 +1160,26 @@ __global__ __launch_bounds__(kBlock) void energy_kernel(EnergyArgs e) {
       a1 += s_un64[w];
       c0 += s_cut[w];
     }
-    e.part_un[blockIdx.x] = a0;
-    e.part_un64[blockIdx.x] = a1;
-    e.part_cut[blockIdx.x] = c0;
+    e.part_un[bid] = a0;
+    e.part_un64[bid] = a1;
+    e.part_cut[bid] = c0;
   }
 }
 
+__global__ __launch_bounds__(kBlock) void energy_kernel(EnergyArgs e) {
+  energy_block(e, blockIdx.x);
+}
+
+__global__ __launch_bounds__(kBlock) void energy_packed(const EnergyArgs* __restrict__ jobs,
+                                                        const int32_t* __restrict__ start, int njobs) {
+  const int j = job_of(start, njobs, blockIdx.x);
+  energy_block(jobs[j], blockIdx.x - start[j]);
+}
+
 // Fixed-order sums of the energy block partials (one block).
-__global__ __launch_bounds__(kBlock) void energy_reduce_kernel(const double* __restrict__ p_un,
-                                                               const double* __restrict__ p_un64,
-                                                               const long long* __restrict__ p_cut, int nparts,
-                                                               double* out, long long* out_cut) {
+__device__ __forceinline__ void energy_reduce_block(const double* __restrict__ p_un, const double* __restrict__ p_un64,
+                                                    const long long* __restrict__ p_cut, int nparts, double* out,
+                                                    long long* out_cut) {
   __shared__ double r0[kBlock], r1[kBlock];
   __shared__ long long r2[kBlock];
   const int tid = threadIdx.x;
@@ -1136,6 +1209,20 @@ __global__ __launch_bounds__(kBlock) void energy_reduce_kernel(const double* __r
   }
 }
 
+__global__ __launch_bounds__(kBlock) void energy_reduce_kernel(const double* __restrict__ p_un,
+                                                               const double* __restrict__ p_un64,
+                                                               const long long* __restrict__ p_cut, int nparts,
+                                                               double* out, long long* out_cut) {
+  energy_reduce_block(p_un, p_un64, p_cut, nparts, out, out_cut);
+}
+
+// one block per job
+__global__ __launch_bounds__(kBlock) void energy_reduce_packed(const EnergyArgs* __restrict__ jobs,
+                                                               const int32_t* __restrict__ start, int njobs) {
+  const EnergyArgs& e = jobs[blockIdx.x];
+  energy_reduce_block(e.part_un, e.part_un64, e.part_cut, start[blockIdx.x + 1] - start[blockIdx.x], e.out, e.out_cut);
+}
+
 // Fixed-order sum of the bound partials of one z-update, then the loop bookkeeping: bound
 // trace, convergence test (relative change of the bound), pass counter.  A no-op once the
 // loop is done, like the z-updates queued after it.  Each thread sums a strided slice with
@@ -1143,9 +1230,8 @@ __global__ __launch_bounds__(kBlock) void energy_reduce_kernel(const double* __r
 // block combines the slices in a fixed tree.
 constexpr int kRedBlock = 1024;
 constexpr int kRedUnroll = 8;
-__global__ __launch_bounds__(kRedBlock) void pass_reduce_kernel(const double* __restrict__ partial, int nparts,
-                                                                IterState* st, double* trace, double* bound_out,
-                                                                IterState* mirror) {
+__device__ __forceinline__ void pass_reduce_block(const double* __restrict__ partial, int nparts, IterState* st,
+                                                  double* trace, double* bound_out, IterState* mirror) {
   if (st->done) return;
   __shared__ double red[kRedBlock];
   const int tid = threadIdx.x;
@@ -1183,6 +1269,18 @@ __global__ __launch_bounds__(kRedBlock) void pass_reduce_kernel(const double* __
     st->pass = pass + 1;
     if (mirror) *mirror = *st;
   }
+}
+
+__global__ __launch_bounds__(kRedBlock) void pass_reduce_kernel(const double* __restrict__ partial, int nparts,
+                                                                IterState* st, double* trace, double* bound_out,
+                                                                IterState* mirror) {
+  pass_reduce_block(partial, nparts, st, trace, bound_out, mirror);
+}
+
+// one block per job
+__global__ __launch_bounds__(kRedBlock) void pass_reduce_packed(const ReduceJob* __restrict__ jobs) {
+  const ReduceJob r = jobs[blockIdx.x];
+  pass_reduce_block(r.partial, r.nparts, r.state, r.trace, r.bound_out, nullptr);
 }
 
 __global__ void gather_rows_kernel(const float* __restrict__ src, const int32_t* __restrict__ perm, int64_t n, int L,
@@ -1229,7 +1327,7 @@ inline int lanes_for(int L) {
 
 }  // namespace
 
-inline int groups4(int L) {
+int groups4(int L) {
   const int l4 = (ldz_for(L) + 3) / 4;
   return l4 <= 1 ? 1 : l4 <= 2 ? 2 : l4 <= 4 ? 4 : l4 <= 8 ? 8 : 16;
 }
@@ -1246,21 +1344,90 @@ int iter_grid(int64_t n, int32_t L, int64_t n_heavy) {
   return (int)tile_grid((n + rows - 1) / rows);
 }
 
+UnaryArgs unary_args(const float* x, int64_t n, int32_t d, const int32_t* perm, const int32_t* modes_dev, int32_t L,
+                     int32_t ldz, double sigma2, int32_t bf16, float* A, float* Z0) {
+  UnaryArgs u{};
+  u.x = x;
+  u.n = n;
+  u.d = d;
+  u.L = L;
+  u.ldz = ldz;
+  u.R = L <= 128 ? 64 : 32;
+  u.perm = perm;
+  u.modes = modes_dev;
+  u.inv2s2 = (float)(1.0 / (2.0 * sigma2));
+  u.bf16 = bf16;
+  u.A = A;
+  u.Z0 = Z0;
+  return u;
+}
+
+int unary_grid(const UnaryArgs& u) { return (int)((u.n + u.R - 1) / u.R); }
+
+size_t unary_lds(const UnaryArgs& u) {
+  const int DC = u.L <= 128 ? 32 : 16;
+  const int MG = (u.L + kUT - 1) / kUT;
+  return sizeof(float) * ((size_t)DC * (u.R + 4) + (size_t)DC * (MG * kUT + 4) + (size_t)u.R * u.L);
+}
+
 slk_status launch_unary(const float* x, int64_t n, int32_t d, const int32_t* perm, const int32_t* modes_dev, int32_t L,
                         int32_t ldz, double sigma2, int32_t bf16, float* A, float* Z0, hipStream_t s) {
-  const int R = L <= 128 ? 64 : 32;
-  const int DC = L <= 128 ? 32 : 16;
-  const int MG = (L + kUT - 1) / kUT;
-  const size_t lds = sizeof(float) * ((size_t)DC * (R + 4) + (size_t)DC * (MG * kUT + 4) + (size_t)R * L);
-  const int64_t grid = (n + R - 1) / R;
-  const float inv2s2 = (float)(1.0 / (2.0 * sigma2));
-  if (DC == 32)
-    hipLaunchKernelGGL(unary_kernel<32>, dim3((unsigned)grid), dim3(kBlock), lds, s, x, n, d, perm, modes_dev, L, ldz,
-                       R, inv2s2, bf16, A, Z0);
-  else
-    hipLaunchKernelGGL(unary_kernel<16>, dim3((unsigned)grid), dim3(kBlock), lds, s, x, n, d, perm, modes_dev, L, ldz,
-                       R, inv2s2, bf16, A, Z0);
+  const UnaryArgs u = unary_args(x, n, d, perm, modes_dev, L, ldz, sigma2, bf16, A, Z0);
+  const size_t lds = unary_lds(u);
+  if (L <= 128) hipLaunchKernelGGL(unary_kernel<32>, dim3((unsigned)unary_grid(u)), dim3(kBlock), lds, s, u);
+  else hipLaunchKernelGGL(unary_kernel<16>, dim3((unsigned)unary_grid(u)), dim3(kBlock), lds, s, u);
   SLK_LAUNCHED("unary_kernel");
+  return SLK_OK;
+}
+
+// Packed jobs all have L <= 64 (the float4 path), so DC = 32 and R = 64 for every one.
+slk_status launch_unary_packed(const UnaryArgs* jobs, const int32_t* start, int njobs, int blocks, size_t lds,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(unary_packed<32>, dim3((unsigned)blocks), dim3(kBlock), lds, s, jobs, start, njobs);
+  SLK_LAUNCHED("unary_packed");
+  return SLK_OK;
+}
+
+#define SLK_DISPATCH_G(G, KERNEL, ...)                                         \
+  do {                                                                         \
+    if (G == 1) hipLaunchKernelGGL((KERNEL<1>), __VA_ARGS__);                  \
+    else if (G == 2) hipLaunchKernelGGL((KERNEL<2>), __VA_ARGS__);             \
+    else if (G == 4) hipLaunchKernelGGL((KERNEL<4>), __VA_ARGS__);             \
+    else if (G == 8) hipLaunchKernelGGL((KERNEL<8>), __VA_ARGS__);             \
+    else hipLaunchKernelGGL((KERNEL<16>), __VA_ARGS__);                        \
+  } while (0)
+
+slk_status launch_iter_packed(int G, const IterArgs* jobs, const int32_t* start, int njobs, int blocks, hipStream_t s) {
+  SLK_DISPATCH_G(G, iter4_packed, dim3((unsigned)blocks), dim3(kBlock), 0, s, jobs, start, njobs);
+  SLK_LAUNCHED("iter4_packed");
+  return SLK_OK;
+}
+
+slk_status launch_final_packed(int G, const FinalArgs* jobs, const int32_t* start, int njobs, int blocks,
+                               hipStream_t s) {
+  SLK_DISPATCH_G(G, final4_packed, dim3((unsigned)blocks), dim3(kBlock), 0, s, jobs, start, njobs);
+  SLK_LAUNCHED("final4_packed");
+  return SLK_OK;
+}
+
+slk_status launch_reduce_packed(const ReduceJob* jobs, int njobs, hipStream_t s) {
+  hipLaunchKernelGGL(pass_reduce_packed, dim3((unsigned)njobs), dim3(kRedBlock), 0, s, jobs);
+  SLK_LAUNCHED("pass_reduce_packed");
+  return SLK_OK;
+}
+
+slk_status launch_mode_reduce_packed(const ModeJob* jobs, const int32_t* start, int njobs, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(mode_reduce_packed, dim3((unsigned)blocks), dim3(kBlock), 0, s, jobs, start, njobs);
+  SLK_LAUNCHED("mode_reduce_packed");
+  return SLK_OK;
+}
+
+// energy partials per job, then one reduction work-group per job (start gives each job's count)
+slk_status launch_energy_packed(const EnergyArgs* jobs, const int32_t* start, int njobs, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(energy_packed, dim3((unsigned)blocks), dim3(kBlock), 0, s, jobs, start, njobs);
+  SLK_LAUNCHED("energy_packed");
+  hipLaunchKernelGGL(energy_reduce_packed, dim3((unsigned)njobs), dim3(kBlock), 0, s, jobs, start, njobs);
+  SLK_LAUNCHED("energy_reduce_packed");
   return SLK_OK;
 }
 
@@ -1302,7 +1469,9 @@ slk_status launch_iter(const IterArgs& a, int grid, hipStream_t s) {
   return SLK_OK;
 }
 
-slk_status launch_final(const FinalArgs& f, int grid, hipStream_t s) {
+slk_status launch_final(const FinalArgs& f0, int grid, hipStream_t s) {
+  FinalArgs f = f0;
+  f.grid = grid;
   {
     KernelTimer kt("final_kernel", s);
     if (f.it.L <= 64) SLK_DISPATCH_G4(f.it.L, final4_kernel, dim3(grid), dim3(kBlock), 0, s, f);
