@@ -109,6 +109,80 @@ def cpu_baseline(graph, A, Z0, lam, N, nnz, L, budget_s=20.0):
                       f"host has {os.cpu_count()} logical CPUs"}
 
 
+def serving(slk, torch, n_jobs, rate, max_jobs, passes, prec="fp32"):
+    """Poisson stream of independent jobs (N log-uniform in [500, 50000], D in {64, 128, 256},
+    L in [5, 50], k = 10, lambda = 1), points resident on the device before the clock starts.
+    plain: one job at a time, each slk_build_knn + slk_fit, in arrival order.
+    served: the continuous-batching server, jobs submitted as they arrive.
+    Latency = completion - arrival; solves/s = jobs / (last completion - first arrival)."""
+    import gen
+    specs = gen.job_stream(n_jobs=n_jobs, rate=rate, seed=5)
+    t0 = time.perf_counter()
+    insts = [gen.materialise(sp, K=10) for sp in specs]
+    xs = [torch.from_numpy(i.X).to("cuda") for i in insts]
+    arr = np.array([sp[1] for sp in specs])
+    torch.cuda.synchronize()
+    log(f"[serve] {n_jobs} jobs at {rate}/s materialised in {time.perf_counter() - t0:.1f}s "
+        f"(N {min(i.N for i in insts)}..{max(i.N for i in insts)})")
+
+    def stats(done_t, wall):
+        lat = (done_t - arr) * 1e3
+        return {"solves_per_s": round(float(n_jobs / wall), 2), "p50_ms": round(float(np.percentile(lat, 50)), 2),
+                "p99_ms": round(float(np.percentile(lat, 99)), 2), "mean_ms": round(float(lat.mean()), 2)}
+
+    # warm-up (kernels loaded, allocator primed)
+    w = insts[0]
+    g = slk.Graph.build_knn(xs[0], k=10, prec=prec)
+    slk.fit(xs[0], g, w.init_modes, lam=w.lam, prec=prec)
+    del g
+    torch.cuda.synchronize()
+
+    # plain: one job at a time
+    done = np.zeros(n_jobs)
+    start = time.perf_counter()
+    for j, (inst, x) in enumerate(zip(insts, xs)):
+        now = time.perf_counter() - start
+        if now < arr[j]:
+            time.sleep(arr[j] - now)
+        g = slk.Graph.build_knn(x, k=10, prec=prec)
+        slk.fit(x, g, inst.init_modes, lam=inst.lam, prec=prec)
+        done[j] = time.perf_counter() - start
+        del g
+    plain = stats(done, done.max() - arr[0])
+
+    # served
+    sv = slk.Server(max_jobs=max_jobs, passes_per_step=passes)
+    done = np.zeros(n_jobs)
+    tick = {}
+    nxt, finished, steps = 0, 0, 0
+    start = time.perf_counter()
+    while finished < n_jobs:
+        now = time.perf_counter() - start
+        while nxt < n_jobs and arr[nxt] <= now:
+            inst = insts[nxt]
+            tick[sv.submit(xs[nxt], inst.init_modes, lam=inst.lam, k=10, knn_prec=prec, prec=prec)] = nxt
+            nxt += 1
+        if sv.pending() == 0:
+            time.sleep(max(0.0, min(arr[nxt] - now, 0.001)))
+            continue
+        out = sv.step()
+        steps += 1
+        t = time.perf_counter() - start
+        for tk, o in out.items():
+            assert o["status"] == 0, o["status"]
+            done[tick[tk]] = t
+            finished += 1
+    sv.close()
+    served = stats(done, done.max() - arr[0])
+    served["steps"] = steps
+    return {"jobs": n_jobs, "rate_per_s": rate, "max_jobs": max_jobs, "passes_per_step": passes, "precision": prec,
+            "plain": plain, "served": served,
+            "speedup_solves": round(float(served["solves_per_s"] / plain["solves_per_s"]), 2),
+            "p99_ratio": round(float(plain["p99_ms"] / served["p99_ms"]), 2),
+            "workload": "Poisson arrivals (seed 5); N log-uniform [500, 50000], D in {64,128,256}, L in [5,50], "
+                        "k=10, lambda=1; Gaussian mixtures seeded per job (10000 + id)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,6 +192,9 @@ def main():
     ap.add_argument("--n", type=int, default=0, help="override N (testing only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--reorder", type=int, default=1)
+    ap.add_argument("--serve-jobs", type=int, default=300, help="jobs in the served-form run (0 = skip)")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -188,6 +265,11 @@ def main():
     log(f"[bench] {args.steps} fits in {wall:.3f}s ({ms_step:.2f} ms/fit); iter_kernel avg {iter_avg_ms * 1e3:.1f} us "
         f"over {n_iter} launches -> {achieved:.0f} GB/s; kernels {kern}")
 
+    serve = None
+    if args.serve_jobs > 0:
+        serve = serving(slk, torch, args.serve_jobs, args.serve_rate, args.serve_slots, 2)
+        log(f"[serve] {serve}")
+
     cpu = None
     if not args.no_cpu_baseline:
         a, z0 = slk.unary(x, inst.init_modes, info["sigma2"])
@@ -238,6 +320,7 @@ def main():
             "rows_certified": info["rows_certified"],
             "rows_fallback": info["rows_fallback"],
         },
+        "serving": serve,
         "fit": {k: r0[k] for k in ("energy", "energy_fp64", "bound", "cut", "n_distinct_modes", "converged")},
         "kernels_ms": {k: {"launches": v[0], "total_ms": round(v[1], 3)} for k, v in kern.items()},
     }
