@@ -21,6 +21,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 namespace slk {
@@ -156,143 +157,264 @@ __device__ __forceinline__ void wave_sort128(float (&v)[2], int (&ix)[2]) {
   }
 }
 
-struct CandSmem {
-  union {
-    struct {
-      uint16_t qh[kTile * kRow], ql[kTile * kRow], kh[kTile * kRow], kl[kTile * kRow];
-    } st;
-    float S[kTile][kTile + 1];
-  } u;
-  float lv[kTile][kMaxCand];
-  int li[kTile][kMaxCand];
-  float tau[kTile];
-  float nq[kTile];
-  float nk[kTile];
-  int any;
-};
-
 __device__ __forceinline__ bf16x8 load8(const uint16_t* p) {
   bf16x8 v;
   __builtin_memcpy(&v, p, 16);
   return v;
 }
 
-template <bool SPLIT>
-__global__ __launch_bounds__(kBlock) void cand_kernel(const uint16_t* __restrict__ xh, const uint16_t* __restrict__ xl,
+__device__ __forceinline__ bf16x8 gload8(const uint16_t* __restrict__ p) {
+  const uint4 u = *reinterpret_cast<const uint4*>(p);
+  return __builtin_bit_cast(bf16x8, u);
+}
+
+// Candidate search.  A work-group owns kQT = 128 query rows, 32 per wave; keys stream past in
+// tiles of kKT = 64, each tile one 32-coordinate chunk at a time through a double-buffered LDS
+// stage (one barrier per chunk).  A wave multiplies its 32 rows by the 64 keys of a tile as two
+// 32 x 32 MFMA tiles; the query operands (bf16 hi and lo slices) stay in registers for the
+// whole scan when d <= 32 RES, else they are loaded with each chunk.  Each wave keeps the C
+// best lower bounds of each of its rows, sorted by (bound, index), in its own part of LDS, so
+// candidate merges need no barrier: a row with a few new candidates inserts them one by one, a
+// row with many merges them with a 128-wide bitonic sort.
+template <int I, int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
+  }
+}
+
+constexpr int kQT = 128;
+constexpr int kKT = 64;
+constexpr int kBulk = 4;   // more new candidates than this: bulk merge
+
+// Insert (v, key) into the sorted list of one row (lanes < C hold it); returns the new C-th bound.
+__device__ __forceinline__ float list_insert(float* lv, int* li, int C, float v, int key) {
+  const int lane = threadIdx.x & 63;
+  const float cv = lane < C ? lv[lane] : INFINITY;
+  const int ci = lane < C ? li[lane] : INT32_MAX;
+  const bool before = lane < C && lex_less(cv, ci, v, key);
+  const int pos = __popcll(__ballot(before));
+  const float pv = __shfl_up(cv, 1);
+  const int pi = __shfl_up(ci, 1);
+  if (pos < C && lane < C && lane >= pos) {
+    lv[lane] = lane == pos ? v : pv;
+    li[lane] = lane == pos ? key : pi;
+  }
+  // the C-th entry after the insert (unchanged when the candidate did not enter)
+  const float last = __shfl(cv, C - 1), prev = __shfl(cv, C - 2 < 0 ? 0 : C - 2);
+  if (pos >= C) return last;
+  if (C == 1) return v;
+  return pos == C - 1 ? v : prev;
+}
+
+// Two waves per SIMD (at most 256 registers per lane): the scan is latency-bound below that.
+template <bool SPLIT, int RES>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void cand_kernel(const uint16_t* __restrict__ xh, const uint16_t* __restrict__ xl,
                                                       const float* __restrict__ nrm, int64_t n, int dp, int C,
                                                       float c1, int32_t* __restrict__ cand, float* __restrict__ tau_out) {
-  __shared__ CandSmem sm;
+  extern __shared__ unsigned char smraw[];
+  // key stage ring: [3 buffers][hi/lo][key][kRow] bf16, then the candidate lists [wave][row][C]
+  uint16_t* kst = reinterpret_cast<uint16_t*>(smraw);
+  constexpr int kStage = kKT * kRow;  // bf16 per array
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wr = wave >> 1, wc = wave & 1;  // 32-row half, 32-key half
-  const int64_t q0 = (int64_t)blockIdx.x * kTile;
-  for (int e = tid; e < kTile * kMaxCand; e += kBlock) {
-    sm.lv[e / kMaxCand][e % kMaxCand] = INFINITY;
-    sm.li[e / kMaxCand][e % kMaxCand] = INT32_MAX;
+  const int half = lane >> 5, col = lane & 31;
+  float* lvw = reinterpret_cast<float*>(smraw + sizeof(uint16_t) * 6 * kStage) + wave * 32 * C;
+  int* liw = reinterpret_cast<int*>(smraw + sizeof(uint16_t) * 6 * kStage + sizeof(float) * 4 * 32 * C) + wave * 32 * C;
+  const int64_t q0 = (int64_t)blockIdx.x * kQT + 32 * wave;
+  const int nch = RES > 0 ? RES : dp / kDK;
+  for (int e = lane; e < 32 * C; e += 64) {
+    lvw[e] = INFINITY;
+    liw[e] = INT32_MAX;
   }
-  if (tid < kTile) {
-    sm.tau[tid] = INFINITY;
-    sm.nq[tid] = (q0 + tid < n) ? nrm[q0 + tid] : 0.f;
+  // this lane's rows (accumulator r): 8 (r / 4) + 4 half + r % 4; qv = c1 |y_q|^2, tau = C-th bound
+  float qv[16], tau[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int64_t q = q0 + 8 * (r >> 2) + 4 * half + (r & 3);
+    qv[r] = q < n ? c1 * nrm[q] : 0.f;
+    tau[r] = INFINITY;
   }
-  // staging: 64 rows x 32 bf16 = 256 x 16 bytes per array, one 16-byte piece per thread
-  const int srow = tid >> 2, spiece = (tid & 3) * 8;
-  __syncthreads();
-
-  for (int64_t k0 = 0; k0 < n; k0 += kTile) {
-    f32x16 tot = {};
-    for (int c0 = 0; c0 < dp; c0 += kDK) {
-      __syncthreads();
-      {
-        const int64_t qr = q0 + srow, kr = k0 + srow;
-        uint4 zh = {0, 0, 0, 0}, a = zh, b = zh, cc = zh, dd = zh;
-        if (qr < n) {
-          a = *reinterpret_cast<const uint4*>(xh + qr * dp + c0 + spiece);
-          if (SPLIT) b = *reinterpret_cast<const uint4*>(xl + qr * dp + c0 + spiece);
-        }
-        if (kr < n) {
-          cc = *reinterpret_cast<const uint4*>(xh + kr * dp + c0 + spiece);
-          if (SPLIT) dd = *reinterpret_cast<const uint4*>(xl + kr * dp + c0 + spiece);
-        }
-        *reinterpret_cast<uint4*>(&sm.u.st.qh[srow * kRow + spiece]) = a;
-        *reinterpret_cast<uint4*>(&sm.u.st.kh[srow * kRow + spiece]) = cc;
-        if (SPLIT) {
-          *reinterpret_cast<uint4*>(&sm.u.st.ql[srow * kRow + spiece]) = b;
-          *reinterpret_cast<uint4*>(&sm.u.st.kl[srow * kRow + spiece]) = dd;
-        }
-        if (c0 == 0 && tid < kTile) sm.nk[tid] = (k0 + tid < n) ? nrm[k0 + tid] : 0.f;
-      }
-      __syncthreads();
-      f32x16 part = {};
+  // query operands: row q0 + col, coordinates 16 s + 8 half .. + 7 of each chunk
+  const int64_t arow = min<int64_t>(q0 + col, n - 1);
+  const uint16_t* aph = xh + arow * dp + 8 * half;
+  const uint16_t* apl = xl + arow * dp + 8 * half;
+  constexpr int NA = RES > 0 ? RES : 1;
+  bf16x8 ah[NA][2], al[NA][2];
+  if constexpr (RES > 0) {
 #pragma unroll
-      for (int ks = 0; ks < kDK; ks += 16) {
-        const int ar = (32 * wr + (lane & 31)) * kRow + ks + 8 * (lane >> 5);
-        const int br = (32 * wc + (lane & 31)) * kRow + ks + 8 * (lane >> 5);
-        const bf16x8 ah = load8(&sm.u.st.qh[ar]);
-        const bf16x8 bh = load8(&sm.u.st.kh[br]);
-        part = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, part, 0, 0, 0);
-        if (SPLIT) {
-          const bf16x8 al = load8(&sm.u.st.ql[ar]);
-          const bf16x8 bl = load8(&sm.u.st.kl[br]);
-          part = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, part, 0, 0, 0);
-          part = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, part, 0, 0, 0);
-        }
-      }
+    for (int c = 0; c < RES; ++c)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) tot[r] += part[r];
+      for (int s2 = 0; s2 < 2; ++s2) {
+        ah[c][s2] = gload8(aph + kDK * c + 16 * s2);
+        al[c][s2] = SPLIT ? gload8(apl + kDK * c + 16 * s2) : ah[c][s2];
+      }
+  }
+  // staging: thread tid moves key tid / 4, 8 coordinates at (tid % 4) * 8, hi and lo, through
+  // two register slots (loads in flight two chunks ahead) into a ring of three LDS buffers
+  const int skey = tid >> 2, spiece = (tid & 3) * 8;
+  const int64_t nkt = (n + kKT - 1) / kKT;
+  const int64_t steps = nkt * nch;
+  uint4 ph[2], pl[2];
+  bf16x8 sah[2][2], sal[2][2];  // query operands in flight (RES == 0)
+  auto fetch = [&](auto slot_c, int64_t i) __attribute__((always_inline)) {
+    constexpr int SL = decltype(slot_c)::value;
+    const int64_t kt = i / nch;
+    const int c = (int)(i - kt * nch);
+    const int64_t kr = kt * kKT + skey;
+    ph[SL] = make_uint4(0, 0, 0, 0);
+    pl[SL] = ph[SL];
+    if (kr < n) {
+      ph[SL] = *reinterpret_cast<const uint4*>(xh + kr * dp + kDK * c + spiece);
+      if (SPLIT) pl[SL] = *reinterpret_cast<const uint4*>(xl + kr * dp + kDK * c + spiece);
     }
-    // lower bounds and the filter against each row's current C-th bound
-    const int kc = 32 * wc + (lane & 31);
-    const int64_t key = k0 + kc;
-    const float nkv = sm.nk[kc];
-    float lbv[16];
-    bool pass = false;
+    if constexpr (RES == 0) {
+#pragma unroll
+      for (int s2 = 0; s2 < 2; ++s2) {
+        sah[SL][s2] = gload8(aph + kDK * c + 16 * s2);
+        sal[SL][s2] = SPLIT ? gload8(apl + kDK * c + 16 * s2) : sah[SL][s2];
+      }
+    }
+  };
+  auto stash = [&](auto slot_c, int64_t i) __attribute__((always_inline)) {
+    constexpr int SL = decltype(slot_c)::value;
+    uint16_t* b = kst + (int)(i % 3) * 2 * kStage;
+    *reinterpret_cast<uint4*>(b + skey * kRow + spiece) = ph[SL];
+    if (SPLIT) *reinterpret_cast<uint4*>(b + kStage + skey * kRow + spiece) = pl[SL];
+    if constexpr (RES == 0) {
+      ah[0][0] = sah[SL][0];
+      ah[0][1] = sah[SL][1];
+      al[0][0] = sal[SL][0];
+      al[0][1] = sal[SL][1];
+    }
+  };
+  f32x16 tot[2], part[2];
+  float nk[2] = {0.f, 0.f};
+  // lower bounds of tile kt; rows with a bound below their C-th bound merge (wave-local)
+  auto epilogue = [&](int64_t kt) __attribute__((always_inline)) {
+    const int64_t k0 = kt * kKT;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const int qi = 32 * wr + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-      const int64_t qrow = q0 + qi;
-      float lb = c1 * (sm.nq[qi] + nkv) - 2.0f * tot[r];
-      if (key >= n || key == qrow || qrow >= n) lb = INFINITY;
-      lbv[r] = lb;
-      pass |= lb < sm.tau[qi];
-    }
-    if (tid == 0) sm.any = 0;
-    __syncthreads();
-    if (__ballot(pass) != 0ull && lane == 0) sm.any = 1;
-    __syncthreads();
-    if (!sm.any) continue;
-    // merge path: bounds to LDS (aliases the staging buffers, all reads of which are done)
+      const int64_t q = q0 + 8 * (r >> 2) + 4 * half + (r & 3);
+      float lb[2];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int qi = 32 * wr + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-      sm.u.S[qi][kc] = lbv[r];
-    }
-    __syncthreads();
-    for (int qi = wave; qi < kTile; qi += 4) {
-      const float t = sm.tau[qi];
-      const float v = sm.u.S[qi][lane];
-      const bool p = v < t;
-      if (__ballot(p) == 0ull) continue;
-      float vv[2];
-      int ii[2];
-      vv[0] = lane < C ? sm.lv[qi][lane] : INFINITY;
-      ii[0] = lane < C ? sm.li[qi][lane] : INT32_MAX;
-      vv[1] = p ? v : INFINITY;
-      ii[1] = p ? (int)(k0 + lane) : INT32_MAX;
-      wave_sort128(vv, ii);
-      if (lane < C) {
-        sm.lv[qi][lane] = vv[0];
-        sm.li[qi][lane] = ii[0];
+      for (int j = 0; j < 2; ++j) {
+        const int64_t key = k0 + 32 * j + col;
+        lb[j] = qv[r] + nk[j] - 2.0f * tot[j][r];
+        if (key >= n || key == q || q >= n) lb[j] = INFINITY;
       }
-      const float nt = __shfl(vv[0], C - 1);
-      if (lane == 0) sm.tau[qi] = nt;
+      const uint64_t m0 = __ballot(lb[0] < tau[r]), m1 = __ballot(lb[1] < tau[r]);
+      if ((m0 | m1) == 0ull) continue;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const uint32_t b0 = (uint32_t)(m0 >> (32 * h)), b1 = (uint32_t)(m1 >> (32 * h));
+        const int cnt = __popc(b0) + __popc(b1);
+        if (cnt == 0) continue;
+        const int rho = 8 * (r >> 2) + 4 * h + (r & 3);
+        float* lv = lvw + rho * C;
+        int* li = liw + rho * C;
+        float nt;
+        if (cnt <= kBulk) {
+          nt = INFINITY;
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            uint32_t bb = j == 0 ? b0 : b1;
+            while (bb) {
+              const int bit = __builtin_ctz(bb);
+              bb &= bb - 1;
+              const float v =
+                  __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, lb[j]), 32 * h + bit));
+              nt = list_insert(lv, li, C, v, (int)(k0 + 32 * j + bit));
+            }
+          }
+        } else {
+          // the row's 64 bounds of this tile: lanes 0-31 keys k0 .. k0+31, lanes 32-63 the rest
+          const int src = 32 * h + col;
+          const float v0 = __shfl(lb[0], src), v1 = __shfl(lb[1], src);
+          float vv[2];
+          int ii[2];
+          vv[0] = lane < C ? lv[lane] : INFINITY;
+          ii[0] = lane < C ? li[lane] : INT32_MAX;
+          vv[1] = half == 0 ? v0 : v1;
+          ii[1] = vv[1] == INFINITY ? INT32_MAX : (int)(k0 + lane);
+          wave_sort128(vv, ii);
+          if (lane < C) {
+            lv[lane] = vv[0];
+            li[lane] = ii[0];
+          }
+          nt = __shfl(vv[0], C - 1);
+        }
+        if (half == h) tau[r] = nt;
+      }
     }
+  };
+  // step i: loads for step i + 2 go out, chunk i is multiplied from the ring, step i + 1's
+  // registers land in the ring, one barrier
+  auto step = [&](auto slot_c, int64_t i, auto ai_c) __attribute__((always_inline)) {
+    constexpr int ai = decltype(ai_c)::value;
+    constexpr int SL = decltype(slot_c)::value;
+    const int64_t kt = i / nch;
+    const int c = (int)(i - kt * nch);
+    if (c == 0) {
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int64_t key = kt * kKT + 32 * j + col;
+        nk[j] = key < n ? c1 * nrm[key] : 0.f;
+      }
+    }
+    if (i + 2 < steps) fetch(slot_c, i + 2);
+    const uint16_t* b = kst + (int)(i % 3) * 2 * kStage;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) part[j] = f32x16{};
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2) {
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int o = (32 * j + col) * kRow + 16 * s2 + 8 * half;
+        const bf16x8 bh = load8(b + o);
+        part[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[ai][s2], bh, part[j], 0, 0, 0);
+        if (SPLIT) {
+          const bf16x8 bl = load8(b + kStage + o);
+          part[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[ai][s2], bl, part[j], 0, 0, 0);
+          part[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[ai][s2], bh, part[j], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) tot[j][r] = c == 0 ? part[j][r] : tot[j][r] + part[j][r];
+    if (c == nch - 1) epilogue(kt);
+    if (i + 1 < steps) stash(std::integral_constant<int, 1 - SL>{}, i + 1);
     __syncthreads();
-  }
+  };
+  using S0 = std::integral_constant<int, 0>;
+  using S1 = std::integral_constant<int, 1>;
+  fetch(S0{}, 0);
+  stash(S0{}, 0);
+  if (steps > 1) fetch(S1{}, 1);
   __syncthreads();
-  for (int e = tid; e < kTile * C; e += kBlock) {
-    const int qi = e / C, j = e % C;
-    if (q0 + qi < n) cand[(q0 + qi) * C + j] = sm.li[qi][j];
+  if constexpr (RES > 0) {
+    // two tiles per iteration, so every step's register slot and query chunk are static
+    for (int64_t kt = 0; kt < nkt; kt += 2) {
+      static_for<0, 2 * RES>([&](auto tc) __attribute__((always_inline)) {
+        constexpr int u = decltype(tc)::value;   // step within the pair of tiles
+        constexpr int t = u / RES, c = u % RES;
+        if (kt + t < nkt) step(std::integral_constant<int, u & 1>{}, (kt + t) * RES + c, std::integral_constant<int, c>{});
+      });
+    }
+  } else {
+    for (int64_t i = 0; i < steps; i += 2) {
+      step(S0{}, i, S0{});
+      if (i + 1 < steps) step(S1{}, i + 1, S0{});
+    }
   }
-  if (tid < kTile && q0 + tid < n) tau_out[q0 + tid] = sm.tau[tid];
+  for (int e = lane; e < 32 * C; e += 64) {
+    const int rho = e / C, j = e % C;
+    const int64_t q = q0 + rho;
+    if (q < n) cand[q * C + j] = liw[e];
+  }
+  if (lane < 32 && q0 + lane < n) tau_out[q0 + lane] = lvw[lane * C + C - 1];
 }
 
 // ------------------------------------------------------------------------------------------
@@ -394,13 +516,27 @@ slk_status knn_mfma(const float* x, int64_t n, int32_t d, int32_t k, int32_t can
   const double cG = (bf16 ? 0.0 : 3.05 * std::ldexp(1.0, -16)) + 1.01 * (terms + dp / kDK + 2) * u;
   const double c = 2.0 * (cG + 8 * u);
   const float c1 = (float)(1.0 - c);
-  const unsigned grid = (unsigned)((n + kTile - 1) / kTile);
+  const unsigned grid = (unsigned)((n + kQT - 1) / kQT);
+  const size_t lds = sizeof(uint16_t) * 6 * kKT * kRow + (sizeof(float) + sizeof(int)) * (size_t)kQT * C;
+  const int res = dp <= 4 * kDK ? dp / kDK : 0;
   {
     KernelTimer kt("cand_kernel", s);
-    if (bf16)
-      hipLaunchKernelGGL(cand_kernel<false>, dim3(grid), dim3(kBlock), 0, s, xh, xl, nrm, n, dp, C, c1, cidx, tau);
-    else
-      hipLaunchKernelGGL(cand_kernel<true>, dim3(grid), dim3(kBlock), 0, s, xh, xl, nrm, n, dp, C, c1, cidx, tau);
+#define SLK_CAND(SPL, R) hipLaunchKernelGGL((cand_kernel<SPL, R>), dim3(grid), dim3(kBlock), lds, s, xh, xl, nrm, n, dp, C, c1, cidx, tau)
+#define SLK_CAND_RES(SPL)                  \
+    switch (res) {                         \
+      case 1: SLK_CAND(SPL, 1); break;     \
+      case 2: SLK_CAND(SPL, 2); break;     \
+      case 3: SLK_CAND(SPL, 3); break;     \
+      case 4: SLK_CAND(SPL, 4); break;     \
+      default: SLK_CAND(SPL, 0); break;    \
+    }
+    if (bf16) {
+      SLK_CAND_RES(false)
+    } else {
+      SLK_CAND_RES(true)
+    }
+#undef SLK_CAND_RES
+#undef SLK_CAND
     SLK_LAUNCHED("cand_kernel");
   }
   {
