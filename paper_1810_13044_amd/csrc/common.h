@@ -232,6 +232,17 @@ int unary_grid(const UnaryArgs& u);
 size_t unary_lds(const UnaryArgs& u);
 int groups4(int L);
 
+// Index of the job owning block b: start[j] <= b < start[j + 1] (start has njobs + 1 entries).
+__device__ __forceinline__ inline int job_of(const int32_t* __restrict__ start, int njobs, int b) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 // Packed launches: one launch covers several jobs; `start` (device, njobs + 1 entries) holds the
 // first work-group of each job and the total, `jobs` (device) the per-job arguments.  Every job
 // gets exactly the work-groups, tiles and reduction order of its own unpacked launch, so its

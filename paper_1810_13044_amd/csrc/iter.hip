@@ -1,6 +1,5 @@
 // Kernels of the SLK-BO iteration for CDNA4 (gfx950, wave64).
 //
-//   unary_kernel   a_pl = k(x_p, m_l) and z^0_p = softmax(a_p)            (Eq. (6a), Algorithm 1)
 //   iter_kernel    b_p = sum_q w_pq z_q (+ delta z_p), z_p' = softmax(a_p + lambda b_p) and the
 //                  per-point relaxed-bound terms of the input Z            (Eqs. (6b), (8), (2)/(5))
 //   final_kernel   the same logits once more for the last input, hard labels, the result Z in
@@ -56,154 +55,7 @@ __device__ __forceinline__ int load_agent(const int* p) {
 }
 
 
-// ------------------------------------------------------------------------------------------
-// unary affinities
-// ------------------------------------------------------------------------------------------
-// A block owns R rows (64, or 32 when L > 128).  Coordinates are staged in LDS transposed
-// (coordinate-major, rows contiguous), so each thread reads the 4 rows and the 4 modes of its
-// 4 x 4 tile with two 16-byte LDS reads per coordinate and does 16 subtract/multiply-adds.
-// The coordinate sum is taken chunk by chunk (DC terms, then the chunk sums) to keep the FP32
-// error small; the zero padding of a short last chunk adds exact zeros.
-constexpr int kUT = 4;       // rows and modes per thread tile
-constexpr int kUTiles = 2;   // tiles per thread
 
-template <int DC>
-__device__ __forceinline__ void unary_block(const UnaryArgs& u, int64_t bid) {
-  const float* __restrict__ x = u.x;
-  const int64_t n = u.n;
-  const int d = u.d, L = u.L, ldz = u.ldz, R = u.R, bf16 = u.bf16;
-  const int32_t* __restrict__ perm = u.perm;
-  const int32_t* __restrict__ modes = u.modes;
-  const float inv2s2 = u.inv2s2;
-  float* __restrict__ A = u.A;
-  float* __restrict__ Z0 = u.Z0;
-  extern __shared__ float sm[];
-  const int MG = (L + kUT - 1) / kUT;
-  const int RS = R + 4, MS = MG * kUT + 4;  // padded strides (multiples of 4 floats)
-  float* xs = sm;                 // DC x RS, coordinate-major
-  float* ms = xs + DC * RS;       // DC x MS
-  float* as = ms + DC * MS;       // R x L
-  const int tid = threadIdx.x;
-  const int64_t row0 = bid * R;
-  const int nr = (int)min<int64_t>(R, n - row0);
-  const int ntiles = (R / kUT) * MG;
-  float acc[kUTiles][kUT][kUT];
-#pragma unroll
-  for (int t = 0; t < kUTiles; ++t)
-#pragma unroll
-    for (int i = 0; i < kUT; ++i)
-#pragma unroll
-      for (int k = 0; k < kUT; ++k) acc[t][i][k] = 0.f;
-
-  for (int c0 = 0; c0 < d; c0 += DC) {
-    const int dc = min(DC, d - c0);
-    for (int e = tid; e < R * DC; e += kBlock) {
-      const int r = e / DC, j = e % DC;
-      float v = 0.f;
-      if (r < nr && j < dc) {
-        const int64_t gr = perm ? perm[row0 + r] : row0 + r;
-        v = x[gr * d + c0 + j];
-        if (bf16) v = bf16_round(v);
-      }
-      xs[j * RS + r] = v;
-    }
-    for (int e = tid; e < MG * kUT * DC; e += kBlock) {
-      const int l = e / DC, j = e % DC;
-      float v = 0.f;
-      if (l < L && j < dc) {
-        v = x[(int64_t)modes[l] * d + c0 + j];
-        if (bf16) v = bf16_round(v);
-      }
-      ms[j * MS + l] = v;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int t = 0; t < kUTiles; ++t) {
-      const int tile = tid + t * kBlock;
-      if (tile < ntiles) {
-        const int rg = tile / MG, mg = tile % MG;
-        float part[kUT][kUT];
-#pragma unroll
-        for (int i = 0; i < kUT; ++i)
-#pragma unroll
-          for (int k = 0; k < kUT; ++k) part[i][k] = 0.f;
-#pragma unroll 8
-        for (int j = 0; j < DC; ++j) {
-          const float4 xv = *reinterpret_cast<const float4*>(xs + j * RS + rg * kUT);
-          const float4 mv = *reinterpret_cast<const float4*>(ms + j * MS + mg * kUT);
-          const float xa[4] = {xv.x, xv.y, xv.z, xv.w};
-          const float ma[4] = {mv.x, mv.y, mv.z, mv.w};
-#pragma unroll
-          for (int i = 0; i < kUT; ++i)
-#pragma unroll
-            for (int k = 0; k < kUT; ++k) {
-              const float df = xa[i] - ma[k];
-              part[i][k] = fmaf(df, df, part[i][k]);
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < kUT; ++i)
-#pragma unroll
-          for (int k = 0; k < kUT; ++k) acc[t][i][k] += part[i][k];
-      }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int t = 0; t < kUTiles; ++t) {
-    const int tile = tid + t * kBlock;
-    if (tile < ntiles) {
-      const int rg = tile / MG, mg = tile % MG;
-#pragma unroll
-      for (int i = 0; i < kUT; ++i)
-#pragma unroll
-        for (int k = 0; k < kUT; ++k) {
-          const int l = mg * kUT + k;
-          if (l < L) as[(rg * kUT + i) * L + l] = expf(-acc[t][i][k] * inv2s2);
-        }
-    }
-  }
-  __syncthreads();
-  // row softmax of a_p gives z^0_p; one wave per row
-  const int wave = tid >> 6, lane = tid & 63;
-  for (int r = wave; r < nr; r += kBlock / 64) {
-    float m = -FLT_MAX;
-    for (int l = lane; l < L; l += 64) m = fmaxf(m, as[r * L + l]);
-    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
-    float s = 0.f;
-    for (int l = lane; l < L; l += 64) s += expf(as[r * L + l] - m);
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    const int64_t row = row0 + r;
-    for (int l = lane; l < ldz; l += 64) {
-      const float a = l < L ? as[r * L + l] : 0.f;
-      if (A) A[row * ldz + l] = a;
-      if (Z0) Z0[row * ldz + l] = l < L ? expf(a - m) / s : 0.f;
-    }
-  }
-}
-
-template <int DC>
-__global__ __launch_bounds__(kBlock) void unary_kernel(UnaryArgs u) {
-  unary_block<DC>(u, blockIdx.x);
-}
-
-// Index of the job owning block b: start[j] <= b < start[j + 1] (start has njobs + 1 entries).
-__device__ __forceinline__ int job_of(const int32_t* __restrict__ start, int njobs, int b) {
-  int lo = 0, hi = njobs - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (start[mid] <= b) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
-
-template <int DC>
-__global__ __launch_bounds__(kBlock) void unary_packed(const UnaryArgs* __restrict__ jobs,
-                                                       const int32_t* __restrict__ start, int njobs) {
-  const int j = job_of(start, njobs, blockIdx.x);
-  unary_block<DC>(jobs[j], (int64_t)blockIdx.x - start[j]);
-}
 
 // ------------------------------------------------------------------------------------------
 // one z-update: fused SpMM + softmax + bound terms
@@ -1342,50 +1194,6 @@ int iter_grid(int64_t n, int32_t L, int64_t n_heavy) {
   }
   const int64_t rows = 4 * (64 / lanes_for(L)) * kWaveSteps;
   return (int)tile_grid((n + rows - 1) / rows);
-}
-
-UnaryArgs unary_args(const float* x, int64_t n, int32_t d, const int32_t* perm, const int32_t* modes_dev, int32_t L,
-                     int32_t ldz, double sigma2, int32_t bf16, float* A, float* Z0) {
-  UnaryArgs u{};
-  u.x = x;
-  u.n = n;
-  u.d = d;
-  u.L = L;
-  u.ldz = ldz;
-  u.R = L <= 128 ? 64 : 32;
-  u.perm = perm;
-  u.modes = modes_dev;
-  u.inv2s2 = (float)(1.0 / (2.0 * sigma2));
-  u.bf16 = bf16;
-  u.A = A;
-  u.Z0 = Z0;
-  return u;
-}
-
-int unary_grid(const UnaryArgs& u) { return (int)((u.n + u.R - 1) / u.R); }
-
-size_t unary_lds(const UnaryArgs& u) {
-  const int DC = u.L <= 128 ? 32 : 16;
-  const int MG = (u.L + kUT - 1) / kUT;
-  return sizeof(float) * ((size_t)DC * (u.R + 4) + (size_t)DC * (MG * kUT + 4) + (size_t)u.R * u.L);
-}
-
-slk_status launch_unary(const float* x, int64_t n, int32_t d, const int32_t* perm, const int32_t* modes_dev, int32_t L,
-                        int32_t ldz, double sigma2, int32_t bf16, float* A, float* Z0, hipStream_t s) {
-  const UnaryArgs u = unary_args(x, n, d, perm, modes_dev, L, ldz, sigma2, bf16, A, Z0);
-  const size_t lds = unary_lds(u);
-  if (L <= 128) hipLaunchKernelGGL(unary_kernel<32>, dim3((unsigned)unary_grid(u)), dim3(kBlock), lds, s, u);
-  else hipLaunchKernelGGL(unary_kernel<16>, dim3((unsigned)unary_grid(u)), dim3(kBlock), lds, s, u);
-  SLK_LAUNCHED("unary_kernel");
-  return SLK_OK;
-}
-
-// Packed jobs all have L <= 64 (the float4 path), so DC = 32 and R = 64 for every one.
-slk_status launch_unary_packed(const UnaryArgs* jobs, const int32_t* start, int njobs, int blocks, size_t lds,
-                               hipStream_t s) {
-  hipLaunchKernelGGL(unary_packed<32>, dim3((unsigned)blocks), dim3(kBlock), lds, s, jobs, start, njobs);
-  SLK_LAUNCHED("unary_packed");
-  return SLK_OK;
 }
 
 #define SLK_DISPATCH_G(G, KERNEL, ...)                                         \

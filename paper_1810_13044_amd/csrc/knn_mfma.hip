@@ -5,7 +5,8 @@
 //      (|y - h - l| <= ~2^-16 |y|); row norms n_p = ||y_p||^2 in FP64.  With bf16 points
 //      (SLK_PREC_BF16) the points are bf16(x) themselves: h = bf16(x), l = 0, no centring.
 //   2. cand_kernel: G~ = h_p.h_q + h_p.l_q + l_p.h_q on v_mfma_f32_32x32x16_bf16 with FP32
-//      accumulation (a fresh accumulator per 32 coordinates, then summed).  For every pair a
+//      accumulation (one accumulator for d <= 128; above, a fresh one per 32 coordinates, then
+//      summed).  For every pair a
 //      rigorous lower bound of the squared distance is formed,
 //          lb_pq = (1 - c) (n_p + n_q) - 2 G~   <=  ||x_p - x_q||^2,
 //      where c bounds the split residual, the FP32 accumulation and the final roundings (times a
@@ -293,15 +294,20 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   // lower bounds of tile kt; rows with a bound below their C-th bound merge (wave-local)
   auto epilogue = [&](int64_t kt) __attribute__((always_inline)) {
     const int64_t k0 = kt * kKT;
+    // only the last tile has keys past n, only the tiles holding this wave's rows hold a self
+    // pair, only the last work-group has rows past n: other tiles need no masking
+    const bool clean = k0 + kKT <= n && (k0 >= q0 + 32 || k0 + kKT <= q0) && q0 + 32 <= n;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int64_t q = q0 + 8 * (r >> 2) + 4 * half + (r & 3);
       float lb[2];
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        const int64_t key = k0 + 32 * j + col;
         lb[j] = qv[r] + nk[j] - 2.0f * tot[j][r];
-        if (key >= n || key == q || q >= n) lb[j] = INFINITY;
+        if (!clean) {
+          const int64_t key = k0 + 32 * j + col;
+          if (key >= n || key == q || q >= n) lb[j] = INFINITY;
+        }
       }
       const uint64_t m0 = __ballot(lb[0] < tau[r]), m1 = __ballot(lb[1] < tau[r]);
       if ((m0 | m1) == 0ull) continue;
@@ -364,26 +370,33 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     }
     if (i + 2 < steps) fetch(slot_c, i + 2);
     const uint16_t* b = kst + (int)(i % 3) * 2 * kStage;
+    // d <= 128 (RES > 0): one accumulator over all coordinates; else a fresh one per chunk,
+    // added to the total (the error constant of the bound follows the same structure)
+    f32x16* acc = RES > 0 ? tot : part;
+    if (RES == 0 || c == 0) {
 #pragma unroll
-    for (int j = 0; j < 2; ++j) part[j] = f32x16{};
+      for (int j = 0; j < 2; ++j) acc[j] = f32x16{};
+    }
 #pragma unroll
     for (int s2 = 0; s2 < 2; ++s2) {
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         const int o = (32 * j + col) * kRow + 16 * s2 + 8 * half;
         const bf16x8 bh = load8(b + o);
-        part[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[ai][s2], bh, part[j], 0, 0, 0);
+        acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[ai][s2], bh, acc[j], 0, 0, 0);
         if (SPLIT) {
           const bf16x8 bl = load8(b + kStage + o);
-          part[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[ai][s2], bl, part[j], 0, 0, 0);
-          part[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[ai][s2], bh, part[j], 0, 0, 0);
+          acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[ai][s2], bl, acc[j], 0, 0, 0);
+          acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[ai][s2], bh, acc[j], 0, 0, 0);
         }
       }
     }
+    if constexpr (RES == 0) {
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < 2; ++j)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) tot[j][r] = c == 0 ? part[j][r] : tot[j][r] + part[j][r];
+        for (int r = 0; r < 16; ++r) tot[j][r] = c == 0 ? part[j][r] : tot[j][r] + part[j][r];
+    }
     if (c == nch - 1) epilogue(kt);
     if (i + 1 < steps) stash(std::integral_constant<int, 1 - SL>{}, i + 1);
     __syncthreads();
@@ -510,10 +523,13 @@ slk_status knn_mfma(const float* x, int64_t n, int32_t d, int32_t k, int32_t can
                      nrm);
   SLK_LAUNCHED("split_kernel");
   // error constant of the lower bound (see the file comment): split residual + FP32
-  // accumulation (32-term chunks, then dp/32 chunk sums) + final roundings, times 2
+  // accumulation + final roundings, times 2.  For d <= 128 the products of all coordinates go
+  // into one accumulator (3 d terms, d with bf16 points); above, 32-coordinate chunks (3 * 32
+  // terms) are summed in d / 32 more additions.
   const double u = std::ldexp(1.0, -24);
-  const double terms = bf16 ? kDK : 3 * kDK;
-  const double cG = (bf16 ? 0.0 : 3.05 * std::ldexp(1.0, -16)) + 1.01 * (terms + dp / kDK + 2) * u;
+  const int mul = bf16 ? 1 : 3;
+  const double terms = dp <= 4 * kDK ? (double)mul * dp : (double)mul * kDK + dp / kDK;
+  const double cG = (bf16 ? 0.0 : 3.05 * std::ldexp(1.0, -16)) + 1.01 * (terms + 2) * u;
   const double c = 2.0 * (cG + 8 * u);
   const float c1 = (float)(1.0 - c);
   const unsigned grid = (unsigned)((n + kQT - 1) / kQT);

@@ -1,0 +1,249 @@
+// Unary affinities and the initial assignment (Eq. (6a) with the Gaussian kernel of Section 4.2,
+// and the initialisation of Algorithm 1):
+//   a_pl = exp(-||x_p - m_l||^2 / (2 sigma^2)),   z^0_p = softmax(a_p).
+//
+// A work-group owns R = 64 rows (32 when L > 128) in the internal order, gathered from the
+// caller's order through the permutation.  Coordinates go through LDS 32 at a time, transposed
+// (coordinate-major), with 16-byte loads when d is a multiple of 4; each thread computes a 4 x 4
+// tile (4 rows x 4 modes) with FP32 direct differences, two 16-byte LDS reads and 16 multiply-adds
+// per coordinate.  The squared distance is summed chunk by chunk (32 terms, then the chunk
+// sums), which keeps the FP32 error small and avoids the cancellation of |x|^2 + |m|^2 - 2 x.m.
+// The row softmax runs on 16 lanes per row with butterfly reductions.
+#include "common.h"
+
+#include <float.h>
+#include <math.h>
+
+namespace slk {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kUT = 4;       // rows and modes per thread tile
+constexpr int kUTiles = 2;   // tiles per thread
+
+template <int DC, bool VEC>
+__device__ __forceinline__ void unary_block(const UnaryArgs& u, int64_t bid) {
+  const float* __restrict__ x = u.x;
+  const int64_t n = u.n;
+  const int d = u.d, L = u.L, ldz = u.ldz, R = u.R, bf16 = u.bf16;
+  const int32_t* __restrict__ perm = u.perm;
+  const int32_t* __restrict__ modes = u.modes;
+  const float inv2s2 = u.inv2s2;
+  float* __restrict__ A = u.A;
+  float* __restrict__ Z0 = u.Z0;
+  extern __shared__ float sm[];
+  const int MG = (L + kUT - 1) / kUT;
+  const int RS = R + 4, MS = MG * kUT + 4;  // padded strides (multiples of 4 floats)
+  float* xs = sm;                 // DC x RS, coordinate-major
+  float* ms = xs + DC * RS;       // DC x MS
+  float* as = ms + DC * MS;       // R x L
+  const int tid = threadIdx.x;
+  const int64_t row0 = bid * R;
+  const int nr = (int)min<int64_t>(R, n - row0);
+  const int ntiles = (R / kUT) * MG;
+  float acc[kUTiles][kUT][kUT];
+#pragma unroll
+  for (int t = 0; t < kUTiles; ++t)
+#pragma unroll
+    for (int i = 0; i < kUT; ++i)
+#pragma unroll
+      for (int k = 0; k < kUT; ++k) acc[t][i][k] = 0.f;
+
+  for (int c0 = 0; c0 < d; c0 += DC) {
+    const int dc = min(DC, d - c0);
+    if constexpr (VEC) {
+      // 16-byte pieces: row r, coordinates 4 q .. 4 q + 3 of the chunk (dc is a multiple of 4)
+      constexpr int Q = DC / 4;
+      for (int e = tid; e < R * Q; e += kBlock) {
+        const int r = e / Q, q = e % Q;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (r < nr && 4 * q < dc) {
+          const int64_t gr = perm ? perm[row0 + r] : row0 + r;
+          v = *reinterpret_cast<const float4*>(x + gr * d + c0 + 4 * q);
+        }
+        if (bf16) {
+          v.x = bf16_round(v.x);
+          v.y = bf16_round(v.y);
+          v.z = bf16_round(v.z);
+          v.w = bf16_round(v.w);
+        }
+        xs[(4 * q + 0) * RS + r] = v.x;
+        xs[(4 * q + 1) * RS + r] = v.y;
+        xs[(4 * q + 2) * RS + r] = v.z;
+        xs[(4 * q + 3) * RS + r] = v.w;
+      }
+      for (int e = tid; e < MG * kUT * Q; e += kBlock) {
+        const int l = e / Q, q = e % Q;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (l < L && 4 * q < dc) v = *reinterpret_cast<const float4*>(x + (int64_t)modes[l] * d + c0 + 4 * q);
+        if (bf16) {
+          v.x = bf16_round(v.x);
+          v.y = bf16_round(v.y);
+          v.z = bf16_round(v.z);
+          v.w = bf16_round(v.w);
+        }
+        ms[(4 * q + 0) * MS + l] = v.x;
+        ms[(4 * q + 1) * MS + l] = v.y;
+        ms[(4 * q + 2) * MS + l] = v.z;
+        ms[(4 * q + 3) * MS + l] = v.w;
+      }
+    } else {
+      for (int e = tid; e < R * DC; e += kBlock) {
+        const int r = e / DC, j = e % DC;
+        float v = 0.f;
+        if (r < nr && j < dc) {
+          const int64_t gr = perm ? perm[row0 + r] : row0 + r;
+          v = x[gr * d + c0 + j];
+          if (bf16) v = bf16_round(v);
+        }
+        xs[j * RS + r] = v;
+      }
+      for (int e = tid; e < MG * kUT * DC; e += kBlock) {
+        const int l = e / DC, j = e % DC;
+        float v = 0.f;
+        if (l < L && j < dc) {
+          v = x[(int64_t)modes[l] * d + c0 + j];
+          if (bf16) v = bf16_round(v);
+        }
+        ms[j * MS + l] = v;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < kUTiles; ++t) {
+      const int tile = tid + t * kBlock;
+      if (tile < ntiles) {
+        const int rg = tile / MG, mg = tile % MG;
+        float part[kUT][kUT];
+#pragma unroll
+        for (int i = 0; i < kUT; ++i)
+#pragma unroll
+          for (int k = 0; k < kUT; ++k) part[i][k] = 0.f;
+#pragma unroll 8
+        for (int j = 0; j < DC; ++j) {
+          const float4 xv = *reinterpret_cast<const float4*>(xs + j * RS + rg * kUT);
+          const float4 mv = *reinterpret_cast<const float4*>(ms + j * MS + mg * kUT);
+          const float xa[4] = {xv.x, xv.y, xv.z, xv.w};
+          const float ma[4] = {mv.x, mv.y, mv.z, mv.w};
+#pragma unroll
+          for (int i = 0; i < kUT; ++i)
+#pragma unroll
+            for (int k = 0; k < kUT; ++k) {
+              const float df = xa[i] - ma[k];
+              part[i][k] = fmaf(df, df, part[i][k]);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < kUT; ++i)
+#pragma unroll
+          for (int k = 0; k < kUT; ++k) acc[t][i][k] += part[i][k];
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int t = 0; t < kUTiles; ++t) {
+    const int tile = tid + t * kBlock;
+    if (tile < ntiles) {
+      const int rg = tile / MG, mg = tile % MG;
+#pragma unroll
+      for (int i = 0; i < kUT; ++i)
+#pragma unroll
+        for (int k = 0; k < kUT; ++k) {
+          const int l = mg * kUT + k;
+          if (l < L) as[(rg * kUT + i) * L + l] = expf(-acc[t][i][k] * inv2s2);
+        }
+    }
+  }
+  __syncthreads();
+  // row softmax of a_p gives z^0_p: 16 lanes per row, 16 rows per block pass
+  const int g = tid >> 4, j = tid & 15;
+  for (int r = g; r < nr; r += kBlock / 16) {
+    float m = -FLT_MAX;
+    for (int l = j; l < L; l += 16) m = fmaxf(m, as[r * L + l]);
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 16));
+    float s = 0.f;
+    for (int l = j; l < L; l += 16) s += expf(as[r * L + l] - m);
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) s += __shfl_xor(s, off, 16);
+    const int64_t row = row0 + r;
+    for (int l = j; l < ldz; l += 16) {
+      const float a = l < L ? as[r * L + l] : 0.f;
+      if (A) A[row * ldz + l] = a;
+      if (Z0) Z0[row * ldz + l] = l < L ? expf(a - m) / s : 0.f;
+    }
+  }
+}
+
+template <int DC, bool VEC>
+__global__ __launch_bounds__(kBlock) void unary_kernel(UnaryArgs u) {
+  unary_block<DC, VEC>(u, blockIdx.x);
+}
+
+__global__ __launch_bounds__(kBlock) void unary_packed(const UnaryArgs* __restrict__ jobs,
+                                                       const int32_t* __restrict__ start, int njobs) {
+  const int j = job_of(start, njobs, blockIdx.x);
+  const UnaryArgs& u = jobs[j];
+  // 16-byte staging when the job's rows allow it (d % 4 == 0, x 16-byte aligned)
+  if ((u.d & 3) == 0 && ((uintptr_t)u.x & 15) == 0) unary_block<32, true>(u, (int64_t)blockIdx.x - start[j]);
+  else unary_block<32, false>(u, (int64_t)blockIdx.x - start[j]);
+}
+
+}  // namespace
+
+UnaryArgs unary_args(const float* x, int64_t n, int32_t d, const int32_t* perm, const int32_t* modes_dev, int32_t L,
+                     int32_t ldz, double sigma2, int32_t bf16, float* A, float* Z0) {
+  UnaryArgs u{};
+  u.x = x;
+  u.n = n;
+  u.d = d;
+  u.L = L;
+  u.ldz = ldz;
+  u.R = L <= 128 ? 64 : 32;
+  u.perm = perm;
+  u.modes = modes_dev;
+  u.inv2s2 = (float)(1.0 / (2.0 * sigma2));
+  u.bf16 = bf16;
+  u.A = A;
+  u.Z0 = Z0;
+  return u;
+}
+
+int unary_grid(const UnaryArgs& u) { return (int)((u.n + u.R - 1) / u.R); }
+
+size_t unary_lds(const UnaryArgs& u) {
+  const int DC = u.L <= 128 ? 32 : 16;
+  const int MG = (u.L + kUT - 1) / kUT;
+  return sizeof(float) * ((size_t)DC * (u.R + 4) + (size_t)DC * (MG * kUT + 4) + (size_t)u.R * u.L);
+}
+
+// 16-byte loads need d % 4 == 0 (rows then start on 16-byte boundaries of a 16-byte aligned x).
+static bool vec_ok(const float* x, int d) { return (d & 3) == 0 && ((uintptr_t)x & 15) == 0; }
+
+slk_status launch_unary(const float* x, int64_t n, int32_t d, const int32_t* perm, const int32_t* modes_dev, int32_t L,
+                        int32_t ldz, double sigma2, int32_t bf16, float* A, float* Z0, hipStream_t s) {
+  const UnaryArgs u = unary_args(x, n, d, perm, modes_dev, L, ldz, sigma2, bf16, A, Z0);
+  const size_t lds = unary_lds(u);
+  const dim3 grid((unsigned)unary_grid(u));
+  const bool vec = vec_ok(x, d);
+  if (L <= 128) {
+    if (vec) hipLaunchKernelGGL((unary_kernel<32, true>), grid, dim3(kBlock), lds, s, u);
+    else hipLaunchKernelGGL((unary_kernel<32, false>), grid, dim3(kBlock), lds, s, u);
+  } else {
+    if (vec) hipLaunchKernelGGL((unary_kernel<16, true>), grid, dim3(kBlock), lds, s, u);
+    else hipLaunchKernelGGL((unary_kernel<16, false>), grid, dim3(kBlock), lds, s, u);
+  }
+  SLK_LAUNCHED("unary_kernel");
+  return SLK_OK;
+}
+
+// Packed jobs all have L <= 64, so DC = 32 and R = 64 for every one.
+slk_status launch_unary_packed(const UnaryArgs* jobs, const int32_t* start, int njobs, int blocks, size_t lds,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(unary_packed, dim3((unsigned)blocks), dim3(kBlock), lds, s, jobs, start, njobs);
+  SLK_LAUNCHED("unary_packed");
+  return SLK_OK;
+}
+
+}  // namespace slk
