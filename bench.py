@@ -183,6 +183,87 @@ def serving(slk, torch, n_jobs, rate, max_jobs, passes, prec="fp32"):
                         "k=10, lambda=1; Gaussian mixtures seeded per job (10000 + id)"}
 
 
+def _round_bf16(X):
+    """float32 -> nearest bfloat16 (ties to even), as float32 (input generation for the oracle)."""
+    b = np.ascontiguousarray(X, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+    return b.astype(np.uint32).view(np.float32)
+
+
+def precision(slk, torch, big_x, big_g, big_inst, r32):
+    """Error of the FP32 and BF16-X paths against the FP64 oracle at the 2,000-point mixture, and
+    of the BF16-X path against the FP32 path at the main workload (both evaluated on the FP32
+    problem: FP32-point graph, FP64 unary term)."""
+    import gen
+    from oracle import slk as orc
+    inst = gen.make("mixture-2k")
+    x = torch.from_numpy(inst.X).to("cuda")
+    idx, d2 = orc.knn(inst.X, inst.K, block=256)
+    rp, ci = orc.symmetrize(idx, inst.N)
+    ref = orc.fit(inst.X, rp, ci, inst.init_modes, orc.sigma2_from_knn(d2), inst.lam)
+    g32 = slk.Graph.build_knn(x, k=inst.K, method="exact")
+    out = {"small": {"workload": "mixture-2k (N=2000, D=16, L=5) against the FP64 oracle: lockstep = the oracle "
+                                 "runs the GPU's inner pass counts and continues from the GPU's modes wherever "
+                                 "they lie in its tie set; free = both run on their own"}}
+    for prec in ("fp32", "bf16"):
+        g = g32 if prec == "fp32" else slk.Graph.build_knn(x, k=inst.K, method="exact", prec="bf16")
+        Xp = inst.X if prec == "fp32" else _round_bf16(inst.X)
+        if prec == "fp32":
+            rpp, cip, s2p = rp, ci, orc.sigma2_from_knn(d2)
+        else:
+            ib, db = orc.knn(Xp, inst.K, block=256)
+            rpp, cip = orc.symmetrize(ib, inst.N)
+            s2p = orc.sigma2_from_knn(db)
+        # lock-step outer iterations (the parity contract)
+        modes = inst.init_modes.copy()
+        dz = 0.0
+        for t in range(20):
+            o = orc.assign(Xp, rpp, cip, modes, s2p, inst.lam)
+            r = slk.assign(x, g, modes, lam=inst.lam, fixed_inner=o["n_pass"], prec=prec)
+            dz = max(dz, float(np.abs(r["z"].cpu().numpy() - o["Z"]).max()))
+            nxt = r["modes_next"].astype(np.int64)
+            if np.array_equal(nxt, modes):
+                break
+            modes = nxt
+        lab = r["labels"].cpu().numpy()
+        srt = np.sort(o["S"], axis=1)
+        resolvable = (srt[:, -1] - srt[:, -2]) > 1e-6 + 64 * np.spacing(np.abs(srt[:, -1]).astype(np.float32)) \
+            + inst.lam * np.diff(rpp) * 1e-5
+        E_orc = orc.energy_of(inst.X, rpp, cip, lab, modes, s2p, inst.lam)[0]
+        E_orc_own = o["E"] if prec == "fp32" else orc.energy_of(inst.X, rpp, cip, o["labels"], modes, s2p, inst.lam)[0]
+        free = slk.fit(x, g, inst.init_modes, lam=inst.lam, prec=prec)
+        ef = slk.energy(x, g32, free["labels"], free["modes"], lam=inst.lam)
+        out["small"][prec] = {
+            "lockstep": {"outer": t + 1, "max_abs_dz": dz,
+                         "label_agreement": float(np.mean(lab == o["labels"])),
+                         "label_agreement_resolvable": float(np.mean(lab[resolvable] == o["labels"][resolvable])),
+                         "rows_resolvable": int(resolvable.sum()),
+                         "rel_energy_gap_fp64": float(abs(r["result"]["energy_fp64"] - E_orc_own) / abs(E_orc_own)),
+                         "rel_energy_gap_at_gpu_labels": float(abs(r["result"]["energy_fp64"] - E_orc) / abs(E_orc))},
+            "free": {"same_modes_as_oracle": bool(np.array_equal(free["modes"], ref["modes"])),
+                     "energy": float(ef["energy_fp64"]), "oracle_energy": float(ref["E"]),
+                     "label_agreement": float(np.mean(free["labels"].cpu().numpy() == ref["labels"]))}}
+    # main workload: BF16-X graph and fit against the FP32 ones
+    t0 = time.perf_counter()
+    gb = slk.Graph.build_knn(big_x, k=big_inst.K, method="mfma", reorder=True, prec="bf16")
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    rb = slk.fit(big_x, gb, big_inst.init_modes, lam=big_inst.lam, prec="bf16")
+    ea = slk.energy(big_x, big_g, r32["labels"], r32["modes"], lam=big_inst.lam)
+    eb = slk.energy(big_x, big_g, rb["labels"], rb["modes"], lam=big_inst.lam)
+    terms = (ea["energy_fp64"] - big_inst.lam * ea["cut"]) * -1.0 + big_inst.lam * ea["cut"]
+    out["large"] = {"workload": "the main workload, BF16-X against FP32 (both on the FP32 problem)",
+                    "energy_fp32": ea["energy_fp64"], "energy_bf16": eb["energy_fp64"],
+                    "cut_fp32": ea["cut"], "cut_bf16": eb["cut"],
+                    "same_modes": bool(np.array_equal(rb["modes"], r32["modes"])),
+                    "rel_energy_gap": float(abs(eb["energy_fp64"] - ea["energy_fp64"]) / abs(ea["energy_fp64"])),
+                    "rel_energy_gap_of_terms": float(abs(eb["energy_fp64"] - ea["energy_fp64"]) / terms),
+                    "label_agreement": float((rb["labels"] == r32["labels"]).float().mean().item()),
+                    "bf16_graph_s": round(tb, 3), "bf16_outer": rb["result"]["outer_iters"],
+                    "bf16_inner_total": rb["result"]["inner_iters_total"]}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -192,6 +273,7 @@ def main():
     ap.add_argument("--n", type=int, default=0, help="override N (testing only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--reorder", type=int, default=1)
+    ap.add_argument("--precision", type=int, default=1, help="report FP32/BF16-X errors (0 = skip)")
     ap.add_argument("--serve-jobs", type=int, default=300, help="jobs in the served-form run (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-slots", type=int, default=64)
@@ -265,6 +347,12 @@ def main():
     log(f"[bench] {args.steps} fits in {wall:.3f}s ({ms_step:.2f} ms/fit); iter_kernel avg {iter_avg_ms * 1e3:.1f} us "
         f"over {n_iter} launches -> {achieved:.0f} GB/s; kernels {kern}")
 
+    prec = None
+    if args.precision:
+        r32 = slk.fit(x, g, inst.init_modes, lam=lam)
+        prec = precision(slk, torch, x, g, inst, r32)
+        log(f"[bench] precision {prec}")
+
     serve = None
     if args.serve_jobs > 0:
         serve = serving(slk, torch, args.serve_jobs, args.serve_rate, args.serve_slots, 2)
@@ -320,6 +408,7 @@ def main():
             "rows_certified": info["rows_certified"],
             "rows_fallback": info["rows_fallback"],
         },
+        "precision": prec,
         "serving": serve,
         "fit": {k: r0[k] for k in ("energy", "energy_fp64", "bound", "cut", "n_distinct_modes", "converged")},
         "kernels_ms": {k: {"launches": v[0], "total_ms": round(v[1], 3)} for k, v in kern.items()},
