@@ -240,6 +240,30 @@ slk_status slk_inner_step(const slk_graph* g, int32_t L, const float* a, const f
                           double* bound_host);
 
 /*
+ * Out-of-sample assignment (Section 1: the explicit assignment variables give a direct
+ * out-of-sample extension).  Each query y takes the z-update of Eq. (8) once with the fit
+ * held fixed:
+ *   a_yl = k(y, m_l)  (Eq. (6a), Gaussian kernel with sigma2),
+ *   b_y  = sum over the k nearest points q of y in x (binary kNN affinity, Section 4.2,
+ *          ordered by (squared distance, index); the query is not excluded, it is not in x),
+ *   z_y  = softmax(a_y + lambda b_y),  label_y = argmax_l (a_y + lambda b_y)_l (ties to the
+ *          smaller l).
+ *  x, n, d     : the fitted points (device, n x d float32).
+ *  z, L        : their assignment Z (device, n x L float32, caller order), e.g. slk_fit's z_out.
+ *  modes_host  : L mode indices into x (host).
+ *  y, m        : queries (device, m x d float32).
+ *  k           : neighbours per query, 1 <= k <= min(64, n).
+ *  sigma2 > 0  : the kernel bandwidth (e.g. the graph's estimate from slk_graph_info).
+ *  method, prec: kNN search and point precision, as in slk_build_knn.
+ *  z_out       : m x L float32 (device); labels_out: m int32 (device, may be NULL);
+ *  knn_idx_out : m x k int32 (device, may be NULL) receives the neighbours.
+ *  Synchronises `stream`.
+ */
+slk_status slk_predict(const float* x, int64_t n, int32_t d, const float* z, int32_t L, const int32_t* modes_host,
+                       const float* y, int64_t m, int32_t k, double lambda, double sigma2, slk_knn_method method,
+                       slk_precision prec, void* stream, float* z_out, int32_t* labels_out, int32_t* knn_idx_out);
+
+/*
  * Served and batched form (an extension; the paper fits one problem at a time).
  *
  * A job is one whole problem: its graph is built from its points (slk_build_knn with

@@ -235,6 +235,30 @@ def inner_step(graph: Graph, a, z_in, lam=1.0, delta=0.0, scale=1):
     return z_out, b.value
 
 
+def predict(x, z, modes, y, k=10, lam=1.0, sigma2=0.0, graph=None, method="auto", prec="fp32"):
+    """Out-of-sample assignment of the queries y (m x d) against a fit (x, z, modes).
+    sigma2 <= 0 takes the estimate of `graph`.  Returns (z_y, labels_y, knn_idx)."""
+    torch = _torch()
+    lib = _lib.load()
+    n, d = x.shape
+    m = y.shape[0]
+    mo = _lib.host_i32(modes)
+    L = len(mo)
+    if sigma2 <= 0:
+        if graph is None:
+            raise ValueError("pass sigma2 > 0 or the fit's graph")
+        sigma2 = graph.info()["sigma2"]
+    zy = torch.empty((m, L), dtype=torch.float32, device="cuda")
+    lab = torch.empty(m, dtype=torch.int32, device="cuda")
+    nn = torch.empty((m, k), dtype=torch.int32, device="cuda")
+    _lib.check(lib.slk_predict(_dev(x, torch.float32, "x"), n, d, _dev(z, torch.float32, "z"), L, _lib.ptr_i32(mo),
+                               _dev(y, torch.float32, "y"), m, int(k), float(lam), float(sigma2),
+                               {"auto": 0, "exact": 1, "mfma": 2}[method], _prec(prec), _stream(),
+                               _dev(zy, torch.float32, "z_out"), _dev(lab, torch.int32, "labels"),
+                               _dev(nn, torch.int32, "knn_idx")))
+    return zy, lab, nn
+
+
 # ----------------------------------------------------------------------------- served form
 
 def knn_opts(k=10, method="auto", reorder=False, prec="fp32", candidates=0):

@@ -93,6 +93,7 @@ def load(path: str = LIB_PATH):
         "slk_energy": [P, I64, I32, P, I32, P, P, P, D, D, D, P, C.POINTER(EnergyOut)],
         "slk_unary": [P, I64, I32, I32, P, D, I32, P, P, P],
         "slk_inner_step": [P, I32, P, P, D, D, I32, P, P, P],
+        "slk_predict": [P, I64, I32, P, I32, P, P, I64, I32, D, D, I32, I32, P, P, P, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)

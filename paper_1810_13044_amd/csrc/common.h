@@ -205,6 +205,7 @@ struct UnaryArgs {
   int32_t bf16;
   float* A;              // n x ldz, internal order (may be null)
   float* Z0;             // n x ldz (may be null)
+  const float* xm;       // points the mode indices refer to (null = x)
 };
 
 // One job of a packed pass reduction (one work-group per job).
@@ -224,8 +225,10 @@ struct ModeJob {
   int32_t* modes;
 };
 
+// xm: the points the mode indices refer to (null = x; the out-of-sample queries use the fit's x)
 slk_status launch_unary(const float* x, int64_t n, int32_t d, const int32_t* perm, const int32_t* modes_dev,
-                        int32_t L, int32_t ldz, double sigma2, int32_t bf16, float* A, float* Z0, hipStream_t s);
+                        int32_t L, int32_t ldz, double sigma2, int32_t bf16, float* A, float* Z0, hipStream_t s,
+                        const float* xm = nullptr);
 UnaryArgs unary_args(const float* x, int64_t n, int32_t d, const int32_t* perm, const int32_t* modes_dev, int32_t L,
                      int32_t ldz, double sigma2, int32_t bf16, float* A, float* Z0);
 int unary_grid(const UnaryArgs& u);
@@ -302,10 +305,13 @@ slk_status launch_to_internal_labels(const int32_t* labels_user, const int32_t* 
                                      hipStream_t s);
 
 // graph construction
+// k nearest points of x for each query: rows of x (rows[] or all n_rows, the point itself
+// excluded) or, if y is given, the n_rows rows of y (nothing excluded).
 slk_status knn_exact(const float* x, int64_t n, int32_t d, int32_t k, int32_t bf16, const int32_t* rows,
-                     int64_t n_rows, int32_t* out_idx, double* out_d2, hipStream_t s);
+                     int64_t n_rows, int32_t* out_idx, double* out_d2, hipStream_t s, const float* y = nullptr);
 slk_status knn_mfma(const float* x, int64_t n, int32_t d, int32_t k, int32_t cand, int32_t bf16,
-                    int32_t* out_idx, double* out_d2, int64_t* n_certified, int64_t* n_fallback, hipStream_t s);
+                    int32_t* out_idx, double* out_d2, int64_t* n_certified, int64_t* n_fallback, hipStream_t s,
+                    const float* y = nullptr, int64_t m = 0);
 slk_status build_csr(int64_t n, int32_t k, const int32_t* knn_idx, int32_t** row_ptr, int32_t** col_idx,
                      int64_t* nnz, hipStream_t s);
 slk_status sum_f64(const double* v, int64_t count, double* out_dev, hipStream_t s);

@@ -65,10 +65,13 @@ __device__ void block_bitonic(double* kd, int* kq, int P) {
   }
 }
 
+// Queries are rows of x (rows[] or all, the point itself excluded) or, with y, the rows of y
+// (nothing excluded).
 __global__ __launch_bounds__(kBlock) void knn_exact_kernel(const float* __restrict__ x, int64_t n, int d, int k,
                                                            int bf16, const int32_t* __restrict__ rows,
                                                            int64_t n_rows, int32_t* __restrict__ out_idx,
-                                                           double* __restrict__ out_d2) {
+                                                           double* __restrict__ out_d2, const float* __restrict__ y) {
+  const float* __restrict__ qsrc = y ? y : x;
   __shared__ double qs[kQB][kQDc];
   __shared__ double ld[kQB][64];
   __shared__ int lq[kQB][64];
@@ -101,7 +104,7 @@ __global__ __launch_bounds__(kBlock) void knn_exact_kernel(const float* __restri
         const int i = e / kQDc, j = e % kQDc;
         double v = 0.0;
         if (i < nq && j < dc) {
-          float f = x[qrow[i] * d + c0 + j];
+          float f = qsrc[qrow[i] * d + c0 + j];
           if (bf16) f = bf16_round(f);
           v = (double)f;
         }
@@ -124,7 +127,7 @@ __global__ __launch_bounds__(kBlock) void knn_exact_kernel(const float* __restri
     // filter against the current k-th best of each query
 #pragma unroll
     for (int i = 0; i < kQB; ++i) {
-      if (i < nq && q < n && q != qrow[i] && key_less(acc[i], (int)q, ld[i][k - 1], lq[i][k - 1])) {
+      if (i < nq && q < n && (y || q != qrow[i]) && key_less(acc[i], (int)q, ld[i][k - 1], lq[i][k - 1])) {
         const int pos = atomicAdd(&bcnt[i], 1);
         bd[i][pos] = acc[i];
         bq[i][pos] = (int)q;
@@ -448,12 +451,12 @@ __global__ void set_last_kernel(int32_t* arr, int64_t pos, const int32_t* total)
 // host launchers
 // ------------------------------------------------------------------------------------------
 slk_status knn_exact(const float* x, int64_t n, int32_t d, int32_t k, int32_t bf16, const int32_t* rows,
-                     int64_t n_rows, int32_t* out_idx, double* out_d2, hipStream_t s) {
+                     int64_t n_rows, int32_t* out_idx, double* out_d2, hipStream_t s, const float* y) {
   if (n_rows <= 0) return SLK_OK;
   if (k > 64) return fail(SLK_ERR_INVALID_ARG, "k > 64");
   const int64_t grid = (n_rows + kQB - 1) / kQB;
   hipLaunchKernelGGL(knn_exact_kernel, dim3((unsigned)grid), dim3(kBlock), 0, s, x, n, d, k, bf16, rows, n_rows,
-                     out_idx, out_d2);
+                     out_idx, out_d2, y);
   SLK_LAUNCHED("knn_exact_kernel");
   return SLK_OK;
 }

@@ -211,9 +211,10 @@ __device__ __forceinline__ float list_insert(float* lv, int* li, int C, float v,
 
 // Two waves per SIMD (at most 256 registers per lane): the scan is latency-bound below that.
 template <bool SPLIT, int RES>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void cand_kernel(const uint16_t* __restrict__ xh, const uint16_t* __restrict__ xl,
-                                                      const float* __restrict__ nrm, int64_t n, int dp, int C,
-                                                      float c1, int32_t* __restrict__ cand, float* __restrict__ tau_out) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void cand_kernel(
+    const uint16_t* __restrict__ xh, const uint16_t* __restrict__ xl, const float* __restrict__ nrm, int64_t n, int dp,
+    int C, float c1, int32_t* __restrict__ cand, float* __restrict__ tau_out, const uint16_t* __restrict__ qh,
+    const uint16_t* __restrict__ ql, const float* __restrict__ qn, int64_t nq, int self) {
   extern __shared__ unsigned char smraw[];
   // key stage ring: [3 buffers][hi/lo][key][kRow] bf16, then the candidate lists [wave][row][C]
   uint16_t* kst = reinterpret_cast<uint16_t*>(smraw);
@@ -233,13 +234,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int64_t q = q0 + 8 * (r >> 2) + 4 * half + (r & 3);
-    qv[r] = q < n ? c1 * nrm[q] : 0.f;
+    qv[r] = q < nq ? c1 * qn[q] : 0.f;
     tau[r] = INFINITY;
   }
   // query operands: row q0 + col, coordinates 16 s + 8 half .. + 7 of each chunk
-  const int64_t arow = min<int64_t>(q0 + col, n - 1);
-  const uint16_t* aph = xh + arow * dp + 8 * half;
-  const uint16_t* apl = xl + arow * dp + 8 * half;
+  const int64_t arow = min<int64_t>(q0 + col, nq - 1);
+  const uint16_t* aph = qh + arow * dp + 8 * half;
+  const uint16_t* apl = ql + arow * dp + 8 * half;
   constexpr int NA = RES > 0 ? RES : 1;
   bf16x8 ah[NA][2], al[NA][2];
   if constexpr (RES > 0) {
@@ -296,7 +297,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     const int64_t k0 = kt * kKT;
     // only the last tile has keys past n, only the tiles holding this wave's rows hold a self
     // pair, only the last work-group has rows past n: other tiles need no masking
-    const bool clean = k0 + kKT <= n && (k0 >= q0 + 32 || k0 + kKT <= q0) && q0 + 32 <= n;
+    const bool clean = k0 + kKT <= n && (!self || k0 >= q0 + 32 || k0 + kKT <= q0) && q0 + 32 <= nq;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int64_t q = q0 + 8 * (r >> 2) + 4 * half + (r & 3);
@@ -306,7 +307,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
         lb[j] = qv[r] + nk[j] - 2.0f * tot[j][r];
         if (!clean) {
           const int64_t key = k0 + 32 * j + col;
-          if (key >= n || key == q || q >= n) lb[j] = INFINITY;
+          if (key >= n || (self && key == q) || q >= nq) lb[j] = INFINITY;
         }
       }
       const uint64_t m0 = __ballot(lb[0] < tau[r]), m1 = __ballot(lb[1] < tau[r]);
@@ -425,9 +426,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   for (int e = lane; e < 32 * C; e += 64) {
     const int rho = e / C, j = e % C;
     const int64_t q = q0 + rho;
-    if (q < n) cand[q * C + j] = liw[e];
+    if (q < nq) cand[q * C + j] = liw[e];
   }
-  if (lane < 32 && q0 + lane < n) tau_out[q0 + lane] = lvw[lane * C + C - 1];
+  if (lane < 32 && q0 + lane < nq) tau_out[q0 + lane] = lvw[lane * C + C - 1];
 }
 
 // ------------------------------------------------------------------------------------------
@@ -438,14 +439,15 @@ __global__ __launch_bounds__(kBlock) void rerank_kernel(const float* __restrict_
                                                         const float* __restrict__ tau, int32_t* __restrict__ out_idx,
                                                         double* __restrict__ out_d2, int32_t* __restrict__ fb_rows,
                                                         int32_t* __restrict__ fb_count,
-                                                        unsigned long long* __restrict__ certified) {
+                                                        unsigned long long* __restrict__ certified,
+                                                        const float* __restrict__ yq, int64_t nq) {
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row >= n) return;
+  if (row >= nq) return;
   int q = lane < C ? cand[row * C + lane] : INT32_MAX;
   double dist = INFINITY;
   if (q >= 0 && q < n) {
-    const float* xp = x + row * d;
+    const float* xp = yq + row * d;
     const float* xq = x + (int64_t)q * d;
     double acc = 0.0;
     for (int j = 0; j < d; ++j) {
@@ -491,12 +493,17 @@ __global__ __launch_bounds__(kBlock) void rerank_kernel(const float* __restrict_
 }  // namespace
 
 slk_status knn_mfma(const float* x, int64_t n, int32_t d, int32_t k, int32_t cand, int32_t bf16, int32_t* out_idx,
-                    double* out_d2, int64_t* n_certified, int64_t* n_fallback, hipStream_t s) {
+                    double* out_d2, int64_t* n_certified, int64_t* n_fallback, hipStream_t s, const float* y,
+                    int64_t m) {
+  // queries: the points themselves (each excluded from its own list) or the m rows of y
+  const bool self = y == nullptr;
+  const float* qx = self ? x : y;
+  const int64_t nq = self ? n : m;
   const int C = std::min(std::max(cand, k), kMaxCand);
   const int dp = ((d + kDK - 1) / kDK) * kDK;
   Scratch sc(s);
-  uint16_t *xh, *xl;
-  float *nrm, *tau;
+  uint16_t *xh, *xl, *qh, *ql;
+  float *nrm, *qn, *tau;
   double *mean, *part;
   int32_t *cidx, *fb_rows, *fb_count;
   unsigned long long* certified;
@@ -504,11 +511,20 @@ slk_status knn_mfma(const float* x, int64_t n, int32_t d, int32_t k, int32_t can
   SLK_TRY(sc.get(&xh, (size_t)n * dp));
   SLK_TRY(sc.get(&xl, (size_t)n * dp));
   SLK_TRY(sc.get(&nrm, n));
-  SLK_TRY(sc.get(&tau, n));
+  if (self) {
+    qh = xh;
+    ql = xl;
+    qn = nrm;
+  } else {
+    SLK_TRY(sc.get(&qh, (size_t)nq * dp));
+    SLK_TRY(sc.get(&ql, (size_t)nq * dp));
+    SLK_TRY(sc.get(&qn, nq));
+  }
+  SLK_TRY(sc.get(&tau, nq));
   SLK_TRY(sc.get(&mean, d));
   SLK_TRY(sc.get(&part, (size_t)nparts * d));
-  SLK_TRY(sc.get(&cidx, (size_t)n * C));
-  SLK_TRY(sc.get(&fb_rows, n));
+  SLK_TRY(sc.get(&cidx, (size_t)nq * C));
+  SLK_TRY(sc.get(&fb_rows, nq));
   SLK_TRY(sc.get(&fb_count, 1));
   SLK_TRY(sc.get(&certified, 1));
   SLK_HIP(hipMemsetAsync(fb_count, 0, sizeof(int32_t), s));
@@ -519,9 +535,15 @@ slk_status knn_mfma(const float* x, int64_t n, int32_t d, int32_t k, int32_t can
     hipLaunchKernelGGL(colmean_kernel, dim3((d + kBlock - 1) / kBlock), dim3(kBlock), 0, s, part, nparts, n, d, mean);
     SLK_LAUNCHED("colmean_kernel");
   }
+  // the queries are centred with the points' mean (distances do not depend on the centre)
   hipLaunchKernelGGL(split_kernel, dim3((unsigned)((n + 3) / 4)), dim3(kBlock), 0, s, x, n, d, dp, mean, bf16, xh, xl,
                      nrm);
   SLK_LAUNCHED("split_kernel");
+  if (!self) {
+    hipLaunchKernelGGL(split_kernel, dim3((unsigned)((nq + 3) / 4)), dim3(kBlock), 0, s, qx, nq, d, dp, mean, bf16, qh,
+                       ql, qn);
+    SLK_LAUNCHED("split_kernel");
+  }
   // error constant of the lower bound (see the file comment): split residual + FP32
   // accumulation + final roundings, times 2.  For d <= 128 the products of all coordinates go
   // into one accumulator (3 d terms, d with bf16 points); above, 32-coordinate chunks (3 * 32
@@ -532,12 +554,15 @@ slk_status knn_mfma(const float* x, int64_t n, int32_t d, int32_t k, int32_t can
   const double cG = (bf16 ? 0.0 : 3.05 * std::ldexp(1.0, -16)) + 1.01 * (terms + 2) * u;
   const double c = 2.0 * (cG + 8 * u);
   const float c1 = (float)(1.0 - c);
-  const unsigned grid = (unsigned)((n + kQT - 1) / kQT);
+  const unsigned grid = (unsigned)((nq + kQT - 1) / kQT);
   const size_t lds = sizeof(uint16_t) * 6 * kKT * kRow + (sizeof(float) + sizeof(int)) * (size_t)kQT * C;
   const int res = dp <= 4 * kDK ? dp / kDK : 0;
+  const int selfi = self ? 1 : 0;
   {
     KernelTimer kt("cand_kernel", s);
-#define SLK_CAND(SPL, R) hipLaunchKernelGGL((cand_kernel<SPL, R>), dim3(grid), dim3(kBlock), lds, s, xh, xl, nrm, n, dp, C, c1, cidx, tau)
+#define SLK_CAND(SPL, R)                                                                                          \
+  hipLaunchKernelGGL((cand_kernel<SPL, R>), dim3(grid), dim3(kBlock), lds, s, xh, xl, nrm, n, dp, C, c1, cidx, tau, \
+                     qh, ql, qn, nq, selfi)
 #define SLK_CAND_RES(SPL)                  \
     switch (res) {                         \
       case 1: SLK_CAND(SPL, 1); break;     \
@@ -557,8 +582,8 @@ slk_status knn_mfma(const float* x, int64_t n, int32_t d, int32_t k, int32_t can
   }
   {
     KernelTimer kt("rerank_kernel", s);
-    hipLaunchKernelGGL(rerank_kernel, dim3((unsigned)((n + 3) / 4)), dim3(kBlock), 0, s, x, n, d, k, C, bf16, cidx,
-                       tau, out_idx, out_d2, fb_rows, fb_count, certified);
+    hipLaunchKernelGGL(rerank_kernel, dim3((unsigned)((nq + 3) / 4)), dim3(kBlock), 0, s, x, n, d, k, C, bf16, cidx,
+                       tau, out_idx, out_d2, fb_rows, fb_count, certified, qx, nq);
     SLK_LAUNCHED("rerank_kernel");
   }
   int32_t h_fb = 0;
@@ -567,7 +592,7 @@ slk_status knn_mfma(const float* x, int64_t n, int32_t d, int32_t k, int32_t can
   SLK_HIP(hipMemcpyAsync(&h_cert, certified, sizeof(h_cert), hipMemcpyDeviceToHost, s));
   SLK_HIP(hipStreamSynchronize(s));
   if (timing_on()) timing_flush();
-  if (h_fb > 0) SLK_TRY(knn_exact(x, n, d, k, bf16, fb_rows, h_fb, out_idx, out_d2, s));
+  if (h_fb > 0) SLK_TRY(knn_exact(x, n, d, k, bf16, fb_rows, h_fb, out_idx, out_d2, s, self ? nullptr : qx));
   SLK_HIP(hipStreamSynchronize(s));
   *n_certified = (int64_t)h_cert;
   *n_fallback = h_fb;
