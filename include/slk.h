@@ -264,6 +264,42 @@ slk_status slk_predict(const float* x, int64_t n, int32_t d, const float* z, int
                        slk_precision prec, void* stream, float* z_out, int32_t* labels_out, int32_t* knn_idx_out);
 
 /*
+ * SLK-MS mode update (Eq. (9)): with the assignment Z fixed, every mode is moved to the
+ * weighted mean of the points, weights w_pl = z_pl k(x_p, m_l), and the step is repeated
+ * until no mode moves by more than tol * sqrt(sigma2) in one step, or max_iter steps.
+ * A cluster whose weights sum to zero keeps its mode.
+ *  x, n, d     : points (device, n x d float32).
+ *  z, L        : assignment (device, n x L float32), 1 <= L <= min(64, n).
+ *  modes_in    : L x d float32 start vectors (device).
+ *  sigma2 > 0  : the kernel bandwidth; prec: BF16 rounds the points (not the modes).
+ *  modes_out   : L x d float32 (device; may equal modes_in).
+ *  iters_host  : steps taken (host, may be NULL).  Sums are FP32 per 1,024-point block and
+ *                FP64 across blocks.  Synchronises `stream`.
+ */
+slk_status slk_mean_shift(const float* x, int64_t n, int32_t d, const float* z, int32_t L, const float* modes_in,
+                          double sigma2, double tol, int32_t max_iter, slk_precision prec, void* stream,
+                          float* modes_out, int32_t* iters_host);
+
+/*
+ * SLK-MS (Algorithm 1 with the mean-shift mode update).  Each outer iteration runs the
+ * z-update block of slk_assign with the unary term at the current mode vectors,
+ * a_pl = k(x_p, m_l), then slk_mean_shift on the last z-update's Z (ms_tol, ms_max_iter).
+ * The outer loop stops when no mode moved by more than ms_tol * sqrt(sigma2) over a whole
+ * mode update (converged), or after params.max_outer.
+ *  init_modes   : L x d float32 start vectors (device), e.g. L seeded points.
+ *  z_out, labels_out : as in slk_assign, for the last outer iteration.
+ *  modes_out    : L x d float32 (device), the modes after the last mean-shift.
+ *  modes_used_out : L x d float32 (device, may be NULL), the modes the last z-updates used.
+ *  ms_steps_host : total mean-shift steps (host, may be NULL).
+ *  res_host     : as in slk_fit; energy at the last labels and modes_used_out.
+ *  1 <= L <= 64.  Synchronises `stream`.
+ */
+slk_status slk_fit_ms(const float* x, int64_t n, int32_t d, const slk_graph* g, int32_t L, const float* init_modes,
+                      const slk_params* p, double ms_tol, int32_t ms_max_iter, void* stream, float* z_out,
+                      int32_t* labels_out, float* modes_out, float* modes_used_out, int32_t* ms_steps_host,
+                      slk_result* res_host);
+
+/*
  * Served and batched form (an extension; the paper fits one problem at a time).
  *
  * A job is one whole problem: its graph is built from its points (slk_build_knn with

@@ -259,6 +259,44 @@ def predict(x, z, modes, y, k=10, lam=1.0, sigma2=0.0, graph=None, method="auto"
     return zy, lab, nn
 
 
+def mean_shift(x, z, modes, sigma2, tol=1e-6, max_iter=100, prec="fp32"):
+    """SLK-MS mode update (Eq. (9)) from the L x d start vectors `modes` with Z fixed.
+    Returns (modes L x d float32 device tensor, steps taken)."""
+    torch = _torch()
+    lib = _lib.load()
+    n, d = x.shape
+    L = z.shape[1]
+    out = torch.empty((L, d), dtype=torch.float32, device="cuda")
+    it = C.c_int32(0)
+    _lib.check(lib.slk_mean_shift(_dev(x, torch.float32, "x"), n, d, _dev(z, torch.float32, "z"), L,
+                                  _dev(modes, torch.float32, "modes", (L, d)), float(sigma2), float(tol),
+                                  int(max_iter), _prec(prec), _stream(), _dev(out, torch.float32, "modes_out"),
+                                  C.byref(it)))
+    return out, it.value
+
+
+def fit_ms(x, graph: Graph, init_modes, lam=1.0, ms_tol=1e-6, ms_max_iter=100, **kw):
+    """SLK-MS (Algorithm 1 with the mean-shift mode update) from L x d start vectors.
+    Returns dict with z, labels, modes (after the last mean-shift), modes_used (of the last
+    z-updates), ms_steps and the summary."""
+    torch = _torch()
+    lib = _lib.load()
+    n, d = x.shape
+    L = init_modes.shape[0]
+    p = params(lam=lam, **kw)
+    z, lab = _outputs(n, L, True)
+    mo = torch.empty((L, d), dtype=torch.float32, device="cuda")
+    mu = torch.empty((L, d), dtype=torch.float32, device="cuda")
+    st = C.c_int32(0)
+    r = _lib.Result()
+    _lib.check(lib.slk_fit_ms(_dev(x, torch.float32, "x"), n, d, graph.handle, L,
+                              _dev(init_modes, torch.float32, "init_modes", (L, d)), C.byref(p), float(ms_tol),
+                              int(ms_max_iter), _stream(), _dev(z, torch.float32, "z"),
+                              _dev(lab, torch.int32, "labels"), _dev(mo, torch.float32, "modes_out"),
+                              _dev(mu, torch.float32, "modes_used"), C.byref(st), C.byref(r)))
+    return dict(z=z, labels=lab, modes=mo, modes_used=mu, ms_steps=st.value, result=r.as_dict())
+
+
 # ----------------------------------------------------------------------------- served form
 
 def knn_opts(k=10, method="auto", reorder=False, prec="fp32", candidates=0):

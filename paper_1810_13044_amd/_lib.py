@@ -94,6 +94,8 @@ def load(path: str = LIB_PATH):
         "slk_unary": [P, I64, I32, I32, P, D, I32, P, P, P],
         "slk_inner_step": [P, I32, P, P, D, D, I32, P, P, P],
         "slk_predict": [P, I64, I32, P, I32, P, P, I64, I32, D, D, I32, I32, P, P, P, P],
+        "slk_mean_shift": [P, I64, I32, P, I32, P, D, D, I32, I32, P, P, P],
+        "slk_fit_ms": [P, I64, I32, P, I32, P, C.POINTER(Params), D, I32, P, P, P, P, P, P, C.POINTER(Result)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)

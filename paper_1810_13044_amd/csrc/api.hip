@@ -418,6 +418,7 @@ struct Work {
   double* bound = nullptr;
   int32_t* modes = nullptr;
   int32_t* modes_next = nullptr;
+  const float* mvec = nullptr;  // SLK-MS: L x d mode vectors used in place of the points at `modes`
   double* epart_un = nullptr;
   double* epart_un64 = nullptr;
   long long* epart_cut = nullptr;
@@ -500,7 +501,8 @@ slk_status run_outer(const float* x, int64_t n, int32_t d, const slk_graph* g, i
                      int32_t* labels_user, OuterOut* o) {
   {
     KernelTimer kt("unary_kernel", s);
-    SLK_TRY(launch_unary(x, n, d, g->perm, w.modes, L, ldz_for(L), sigma2, p.prec == SLK_PREC_BF16, w.A, w.Z[0], s));
+    SLK_TRY(launch_unary(x, n, d, g->perm, w.modes, L, ldz_for(L), sigma2, p.prec == SLK_PREC_BF16, w.A, w.Z[0], s,
+                         nullptr, w.mvec));
   }
   const int check = p.fixed_inner > 0 ? 0 : 1;
   hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(1), 0, s, w.state, p.bound_tol, check, trace_cap);
@@ -587,6 +589,7 @@ slk_status run_outer(const float* x, int64_t n, int32_t d, const slk_graph* g, i
   e.x = want_fp64 ? x : nullptr;
   e.perm = g->perm;
   e.modes = w.modes;
+  e.mvec = w.mvec;
   e.n = n;
   e.d = d;
   e.L = L;
@@ -1064,6 +1067,113 @@ slk_status slk_fit(const float* x, int64_t n, int32_t d, const slk_graph* g, int
   if (!modes_out_host) return fail(SLK_ERR_INVALID_ARG, "modes_out_host is NULL");
   return assign_or_fit(true, x, n, d, g, L, init_modes_host, p, stream, z_out, labels_out, modes_out_host, nullptr, 0,
                        res_host);
+}
+
+slk_status slk_fit_ms(const float* x, int64_t n, int32_t d, const slk_graph* g, int32_t L, const float* init_modes,
+                      const slk_params* pp, double ms_tol, int32_t ms_max_iter, void* stream, float* z_out,
+                      int32_t* labels_out, float* modes_out, float* modes_used_out, int32_t* ms_steps_host,
+                      slk_result* res) {
+  SLK_TRY(check_points(x, n, d));
+  if (!g) return fail(SLK_ERR_INVALID_ARG, "graph is NULL");
+  if (g->n != n) return fail(SLK_ERR_INVALID_ARG, "graph was built for a different n");
+  if (L < 1 || L > 64 || L > n) return fail(SLK_ERR_INVALID_ARG, "L must satisfy 1 <= L <= min(64, n)");
+  if (!init_modes || !z_out || !modes_out) return fail(SLK_ERR_INVALID_ARG, "NULL argument");
+  if (!(ms_tol >= 0.0) || ms_max_iter < 1) return fail(SLK_ERR_INVALID_ARG, "need ms_tol >= 0 and ms_max_iter >= 1");
+  SLK_TRY(check_params(pp));
+  const slk_params p = *pp;
+  const double sigma2 = pick_sigma2(p, g);
+  if (!(sigma2 > 0.0)) return fail(SLK_ERR_INVALID_ARG, "sigma2 unknown: pass params.sigma2 > 0");
+  hipStream_t s = (hipStream_t)stream;
+  const int cap = std::max(p.max_inner, p.fixed_inner);
+  Scratch sc(s);
+  Work w;
+  SLK_TRY(alloc_work(sc, g, L, cap, w));
+  SLK_TRY(prepare_col_off(g, L, sc, &w.col_off));
+  // mode vectors: cur (used by the outer iteration) and nxt (after its mean-shift)
+  float *cur, *nxt;
+  SLK_TRY(sc.get(&cur, (size_t)L * d));
+  SLK_TRY(sc.get(&nxt, (size_t)L * d));
+  SLK_HIP(hipMemcpyAsync(cur, init_modes, sizeof(float) * L * d, hipMemcpyDeviceToDevice, s));
+  slk_result r{};
+  OuterOut o;
+  const int bf16 = p.prec == SLK_PREC_BF16;
+  const double lim = ms_tol * std::sqrt(sigma2);
+  int32_t ms_steps = 0;
+  SLK_HIP(hipMemsetAsync(w.modes, 0, sizeof(int32_t) * L, s));  // unused: the modes are the vectors
+  for (int t = 0; t < p.max_outer; ++t) {
+    w.mvec = cur;
+    SLK_TRY(run_outer(x, n, d, g, L, p, sigma2, cap, 0, s, w, z_out, labels_out, &o));
+    r.outer_iters = t + 1;
+    r.inner_iters_total += o.passes;
+    r.inner_iters_last = o.passes;
+    r.energy = o.energy;
+    r.energy_fp64 = o.energy64;
+    r.bound = o.bound;
+    r.cut = o.cut;
+    // Eq. (9) with the relaxed assignment of the last z-update (internal order)
+    SLK_HIP(hipMemcpyAsync(nxt, cur, sizeof(float) * L * d, hipMemcpyDeviceToDevice, s));
+    int32_t its = 0;
+    SLK_TRY(mean_shift_loop(x, n, d, g->perm, w.Z[o.passes & 1], L, ldz_for(L), nxt, sigma2, ms_tol, ms_max_iter, bf16,
+                            s, &its, nullptr));
+    ms_steps += its;
+    // how far the modes moved over the whole update
+    double move = 0.0;
+    {
+      std::vector<float> a((size_t)L * d), b((size_t)L * d);
+      SLK_HIP(hipMemcpyAsync(a.data(), cur, sizeof(float) * L * d, hipMemcpyDeviceToHost, s));
+      SLK_HIP(hipMemcpyAsync(b.data(), nxt, sizeof(float) * L * d, hipMemcpyDeviceToHost, s));
+      SLK_HIP(hipStreamSynchronize(s));
+      for (int l = 0; l < L; ++l) {
+        double m2 = 0.0;
+        for (int c = 0; c < d; ++c) {
+          const double t2 = (double)b[(size_t)l * d + c] - (double)a[(size_t)l * d + c];
+          m2 += t2 * t2;
+        }
+        move = std::max(move, std::sqrt(m2));
+      }
+    }
+    if (move <= lim) {
+      r.converged = 1;
+      break;
+    }
+    if (t + 1 == p.max_outer) break;
+    std::swap(cur, nxt);
+  }
+  // FP64 recheck of the final energy at the last labels and the modes that produced them
+  {
+    EnergyArgs e{};
+    set_heavy(e, g);
+    e.row_ptr = g->row_ptr;
+    e.col_idx = g->col_idx;
+    e.labels_int = w.labels_int;
+    e.A = w.A;
+    e.x = x;
+    e.perm = g->perm;
+    e.modes = w.modes;
+    e.mvec = cur;
+    e.n = n;
+    e.d = d;
+    e.L = L;
+    e.ldz = ldz_for(L);
+    e.inv2s2 = 1.0 / (2.0 * sigma2);
+    e.part_un = w.epart_un;
+    e.part_un64 = w.epart_un64;
+    e.part_cut = w.epart_cut;
+    e.out = w.eout;
+    e.out_cut = w.eout_cut;
+    SLK_TRY(launch_energy(e, w.egrid, s));
+    double eo[2];
+    SLK_HIP(hipMemcpyAsync(eo, w.eout, sizeof(eo), hipMemcpyDeviceToHost, s));
+    SLK_HIP(hipStreamSynchronize(s));
+    r.energy_fp64 = -eo[1] + p.lambda * (double)r.cut;
+  }
+  SLK_HIP(hipMemcpyAsync(modes_out, nxt, sizeof(float) * L * d, hipMemcpyDeviceToDevice, s));
+  if (modes_used_out) SLK_HIP(hipMemcpyAsync(modes_used_out, cur, sizeof(float) * L * d, hipMemcpyDeviceToDevice, s));
+  SLK_HIP(hipStreamSynchronize(s));
+  r.n_distinct_modes = L;
+  if (ms_steps_host) *ms_steps_host = ms_steps;
+  if (res) *res = r;
+  return SLK_OK;
 }
 
 slk_status slk_energy(const float* x, int64_t n, int32_t d, const slk_graph* g, int32_t L, const int32_t* labels,

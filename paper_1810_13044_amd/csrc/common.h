@@ -206,6 +206,7 @@ struct UnaryArgs {
   float* A;              // n x ldz, internal order (may be null)
   float* Z0;             // n x ldz (may be null)
   const float* xm;       // points the mode indices refer to (null = x)
+  const float* mvec;     // L x d mode vectors (SLK-MS; null = the points at `modes`)
 };
 
 // One job of a packed pass reduction (one work-group per job).
@@ -228,7 +229,7 @@ struct ModeJob {
 // xm: the points the mode indices refer to (null = x; the out-of-sample queries use the fit's x)
 slk_status launch_unary(const float* x, int64_t n, int32_t d, const int32_t* perm, const int32_t* modes_dev,
                         int32_t L, int32_t ldz, double sigma2, int32_t bf16, float* A, float* Z0, hipStream_t s,
-                        const float* xm = nullptr);
+                        const float* xm = nullptr, const float* mvec = nullptr);
 UnaryArgs unary_args(const float* x, int64_t n, int32_t d, const int32_t* perm, const int32_t* modes_dev, int32_t L,
                      int32_t ldz, double sigma2, int32_t bf16, float* A, float* Z0);
 int unary_grid(const UnaryArgs& u);
@@ -270,6 +271,7 @@ struct EnergyArgs {
   const float* x;             // original order points (for the FP64 recheck), may be null
   const int32_t* perm;        // internal -> original
   const int32_t* modes;       // L original indices (device)
+  const float* mvec;          // L x d mode vectors (SLK-MS; null = the points at `modes`)
   int64_t n;
   int32_t d, L, ldz;
   double inv2s2;
@@ -287,6 +289,12 @@ struct EnergyArgs {
 int energy_grid(int64_t n, int64_t n_heavy);
 slk_status launch_energy(const EnergyArgs& a, int grid, hipStream_t s);
 slk_status launch_energy_packed(const EnergyArgs* jobs, const int32_t* start, int njobs, int blocks, hipStream_t s);
+// SLK-MS: mean-shift of the modes m (L x d, in place) for the assignment Z (internal order,
+// stride ldz) until no mode moves by more than tol * sigma or max_iter steps (meanshift.hip).
+slk_status mean_shift_loop(const float* x, int64_t n, int32_t d, const int32_t* perm, const float* Z, int32_t L,
+                           int32_t ldz, float* m, double sigma2, double tol, int32_t max_iter, int32_t bf16,
+                           hipStream_t s, int32_t* iters, double* last_shift);
+
 // argument checks and per-graph settings shared by the C ABI and the served form (api.hip)
 slk_status check_points(const float* x, int64_t n, int32_t d);
 slk_status check_params(const slk_params* p);

@@ -931,7 +931,7 @@ __device__ __forceinline__ int gsum16i(int v) {
 __device__ __forceinline__ double unary64_part(const EnergyArgs& e, int64_t rowc, int lab, int j) {
   const int64_t orow = e.perm ? e.perm[rowc] : rowc;
   const float* xp = e.x + orow * e.d;
-  const float* mp = e.x + (int64_t)e.modes[lab] * e.d;
+  const float* mp = e.mvec ? e.mvec + (int64_t)lab * e.d : e.x + (int64_t)e.modes[lab] * e.d;
   double d64 = 0.0;
   for (int k = j; k < e.d; k += 16) {
     const double t = (double)xp[k] - (double)mp[k];

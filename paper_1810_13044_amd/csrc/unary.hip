@@ -32,6 +32,7 @@ __device__ __forceinline__ void unary_block(const UnaryArgs& u, int64_t bid) {
   float* __restrict__ A = u.A;
   float* __restrict__ Z0 = u.Z0;
   const float* __restrict__ xm = u.xm ? u.xm : u.x;
+  const float* __restrict__ mvec = u.mvec;
   extern __shared__ float sm[];
   const int MG = (L + kUT - 1) / kUT;
   const int RS = R + 4, MS = MG * kUT + 4;  // padded strides (multiples of 4 floats)
@@ -76,8 +77,9 @@ __device__ __forceinline__ void unary_block(const UnaryArgs& u, int64_t bid) {
       for (int e = tid; e < MG * kUT * Q; e += kBlock) {
         const int l = e / Q, q = e % Q;
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (l < L && 4 * q < dc) v = *reinterpret_cast<const float4*>(xm + (int64_t)modes[l] * d + c0 + 4 * q);
-        if (bf16) {
+        if (l < L && 4 * q < dc)
+          v = *reinterpret_cast<const float4*>((mvec ? mvec + (int64_t)l * d : xm + (int64_t)modes[l] * d) + c0 + 4 * q);
+        if (bf16 && !mvec) {  // mode vectors are computed in FP32 and used as they are
           v.x = bf16_round(v.x);
           v.y = bf16_round(v.y);
           v.z = bf16_round(v.z);
@@ -103,8 +105,8 @@ __device__ __forceinline__ void unary_block(const UnaryArgs& u, int64_t bid) {
         const int l = e / DC, j = e % DC;
         float v = 0.f;
         if (l < L && j < dc) {
-          v = xm[(int64_t)modes[l] * d + c0 + j];
-          if (bf16) v = bf16_round(v);
+          v = mvec ? mvec[(int64_t)l * d + c0 + j] : xm[(int64_t)modes[l] * d + c0 + j];
+          if (bf16 && !mvec) v = bf16_round(v);
         }
         ms[j * MS + l] = v;
       }
@@ -187,7 +189,8 @@ __global__ __launch_bounds__(kBlock) void unary_packed(const UnaryArgs* __restri
   const int j = job_of(start, njobs, blockIdx.x);
   const UnaryArgs& u = jobs[j];
   // 16-byte staging when the job's rows allow it (d % 4 == 0, x 16-byte aligned)
-  if ((u.d & 3) == 0 && ((uintptr_t)u.x & 15) == 0 && ((uintptr_t)(u.xm ? u.xm : u.x) & 15) == 0)
+  if ((u.d & 3) == 0 && ((uintptr_t)u.x & 15) == 0 && ((uintptr_t)(u.xm ? u.xm : u.x) & 15) == 0 &&
+      ((uintptr_t)u.mvec & 15) == 0)
     unary_block<32, true>(u, (int64_t)blockIdx.x - start[j]);
   else unary_block<32, false>(u, (int64_t)blockIdx.x - start[j]);
 }
@@ -222,14 +225,16 @@ size_t unary_lds(const UnaryArgs& u) {
 
 // 16-byte loads need d % 4 == 0 (rows then start on 16-byte boundaries of a 16-byte aligned x).
 static bool vec_ok(const UnaryArgs& u) {
-  return (u.d & 3) == 0 && ((uintptr_t)u.x & 15) == 0 && ((uintptr_t)(u.xm ? u.xm : u.x) & 15) == 0;
+  return (u.d & 3) == 0 && ((uintptr_t)u.x & 15) == 0 && ((uintptr_t)(u.xm ? u.xm : u.x) & 15) == 0 &&
+         ((uintptr_t)u.mvec & 15) == 0;
 }
 
 slk_status launch_unary(const float* x, int64_t n, int32_t d, const int32_t* perm, const int32_t* modes_dev, int32_t L,
                         int32_t ldz, double sigma2, int32_t bf16, float* A, float* Z0, hipStream_t s,
-                        const float* xm) {
+                        const float* xm, const float* mvec) {
   UnaryArgs u = unary_args(x, n, d, perm, modes_dev, L, ldz, sigma2, bf16, A, Z0);
   u.xm = xm;
+  u.mvec = mvec;
   const size_t lds = unary_lds(u);
   const dim3 grid((unsigned)unary_grid(u));
   const bool vec = vec_ok(u);
