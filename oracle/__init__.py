@@ -10,5 +10,8 @@ Modules:
             discrete energy and the outer/inner driver (SLK-BO).
   brute  -- brute-force minimisation of the discrete objective over all labelings
             with modes taken by their definition (small N only).
+  extend -- out-of-sample assignment and the SLK-MS mean-shift mode update.
+  seeding -- K-means++ seeding, the nearest-seed assignment and the exact modes of
+            Eqs. (1) and (10).
 """
-from . import slk, brute  # noqa: F401
+from . import slk, brute, extend, seeding  # noqa: F401
