@@ -264,6 +264,100 @@ def precision(slk, torch, big_x, big_g, big_inst, r32):
     return out
 
 
+def extensions(slk, torch, x, g, inst, fit_z, fit_modes):
+    """The rows after the hot path, on the same resident points, each kernel timed with HIP
+    events on its launch stream:
+      K-means++ seeding (L rounds; kpp_dist_kernel reads X and D^2 once per round: HBM roofline),
+      exact modes by Eq. (1) from the seeds' nearest-seed assignment (dmode_kernel: MFMA roofline
+        over the issued bf16 products; 3 for the split Gram, 2 per 32 clusters for K Z),
+      one SLK-MS mean-shift step from the fit's assignment (ms_partial_kernel: HBM roofline),
+      out-of-sample assignment of 100,000 queries (k = 10, MFMA kNN into the N points)."""
+    N, D = x.shape
+    L = inst.L
+    s2 = g.info()["sigma2"]
+    out = {}
+    # ---- K-means++
+    u = np.random.default_rng(7).random(L)
+    slk.kmeanspp(x, L, u)
+    torch.cuda.synchronize()
+    slk.timing_enable(True)
+    t0 = time.perf_counter()
+    seeds, lab, _ = slk.kmeanspp(x, L, u)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    nk, kms = slk.timing_read("kpp_dist_kernel")
+    ns, sms = slk.timing_read("kpp_select_kernel")
+    slk.timing_enable(False)
+    per = kms / max(nk, 1)
+    alg = 4 * N * D + 16 * N
+    ach = alg / (per / 1e3) / 1e9
+    out["kmeanspp"] = {"L": L, "wall_ms": round(wall * 1e3, 3), "rounds": nk,
+                       "dist_kernel_avg_us": round(per * 1e3, 2),
+                       "select_kernel_avg_us": round(sms / max(ns, 1) * 1e3, 2),
+                       "roofline": {"kernel": "kpp_dist_kernel", "bound": "hbm", "achieved": round(ach, 1),
+                                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                                    "alg_bytes_per_launch": alg}}
+    log(f"[ext] kmeans++ {out['kmeanspp']}")
+    # ---- exact modes by Eq. (1) from the nearest-seed assignment
+    xs = x[:4096].contiguous()
+    slk.dense_modes(xs, L, s2, labels=lab[:4096].contiguous(), keep=np.arange(L))
+    torch.cuda.synchronize()
+    slk.timing_enable(True)
+    t0 = time.perf_counter()
+    modes, best, _ = slk.dense_modes(x, L, s2, labels=lab, keep=seeds)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    nd, dms = slk.timing_read("dmode_kernel")
+    slk.timing_enable(False)
+    dp = max(64, (D + 31) // 32 * 32)
+    lb = 2 if L > 32 else 1
+    issued = 2.0 * N * N * (3 * dp + 2 * 32 * lb)
+    algf = 2.0 * N * N * (D + L)
+    ach = issued / (dms / 1e3) / 1e12
+    out["dense_modes"] = {"L": L, "wall_ms": round(wall * 1e3, 2), "kernel_ms": round(dms, 2),
+                          "alg_tflops": round(algf / (dms / 1e3) / 1e12, 1),
+                          "roofline": {"kernel": "dmode_kernel", "bound": "mfma", "achieved": round(ach, 1),
+                                       "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                       "frac": round(ach / BF16_PEAK_TFLOPS, 4), "issued_flops": issued}}
+    log(f"[ext] dense modes {out['dense_modes']}")
+    # ---- one SLK-MS mean-shift step (three steps timed) from the fit's assignment
+    m0 = x[torch.as_tensor(np.asarray(fit_modes, dtype=np.int64), device="cuda")].contiguous()
+    slk.mean_shift(x, fit_z, m0, s2, tol=0.0, max_iter=1)
+    torch.cuda.synchronize()
+    slk.timing_enable(True)
+    t0 = time.perf_counter()
+    slk.mean_shift(x, fit_z, m0, s2, tol=0.0, max_iter=3)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    nm, mms = slk.timing_read("ms_partial_kernel")
+    slk.timing_enable(False)
+    per = mms / max(nm, 1)
+    alg = 4 * N * D + 8 * N * L + 4 * ((N + 1023) // 1024) * L * (D + 1)
+    ach = alg / (per / 1e3) / 1e9
+    out["mean_shift"] = {"steps": nm, "wall_ms_per_step": round(wall / 3 * 1e3, 3),
+                         "partial_kernel_avg_us": round(per * 1e3, 2),
+                         "roofline": {"kernel": "ms_partial_kernel", "bound": "hbm", "achieved": round(ach, 1),
+                                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                                      "alg_bytes_per_launch": alg}}
+    log(f"[ext] mean shift {out['mean_shift']}")
+    # ---- out-of-sample assignment
+    m = 100_000
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(11)
+    rows = torch.randint(0, N, (m,), device="cuda", generator=gen)
+    y = (x[rows] + 0.1 * torch.randn((m, D), device="cuda", generator=gen)).contiguous()
+    slk.predict(x, fit_z, fit_modes, y[:1000].contiguous(), k=10, lam=inst.lam, sigma2=s2, method="mfma")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    slk.predict(x, fit_z, fit_modes, y, k=10, lam=inst.lam, sigma2=s2, method="mfma")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    out["predict"] = {"queries": m, "k": 10, "wall_ms": round(wall * 1e3, 2),
+                      "queries_per_s": round(m / wall, 1)}
+    log(f"[ext] predict {out['predict']}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -277,6 +371,8 @@ def main():
     ap.add_argument("--serve-jobs", type=int, default=300, help="jobs in the served-form run (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--extensions", type=int, default=1,
+                    help="time seeding, exact modes, mean-shift and out-of-sample assignment (0 = skip)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -353,6 +449,12 @@ def main():
         prec = precision(slk, torch, x, g, inst, r32)
         log(f"[bench] precision {prec}")
 
+    ext = None
+    if args.extensions:
+        fr = slk.fit(x, g, inst.init_modes, lam=lam)
+        ext = extensions(slk, torch, x, g, inst, fr["z"], fr["modes"])
+        del fr
+
     serve = None
     if args.serve_jobs > 0:
         serve = serving(slk, torch, args.serve_jobs, args.serve_rate, args.serve_slots, 2)
@@ -410,6 +512,7 @@ def main():
         },
         "precision": prec,
         "serving": serve,
+        "extensions": ext,
         "fit": {k: r0[k] for k in ("energy", "energy_fp64", "bound", "cut", "n_distinct_modes", "converged")},
         "kernels_ms": {k: {"launches": v[0], "total_ms": round(v[1], 3)} for k, v in kern.items()},
     }

@@ -300,6 +300,46 @@ slk_status slk_fit_ms(const float* x, int64_t n, int32_t d, const slk_graph* g, 
                       slk_result* res_host);
 
 /*
+ * K-means++ seeding (Section 4.2 starts from K-means++ centres; the sampling rule is that of
+ * Arthur and Vassilvitskii, 2007) and the nearest-seed assignment.
+ *  u_host      : L uniforms in [0, 1) (host); the caller owns the random numbers.
+ *  Centre 0 is the point floor(u_0 n).  Centre r >= 1 is the smallest p whose prefix sum of
+ *  D^2 (in point order) exceeds u_r * sum D^2, where D^2(p) is the squared distance from x_p to
+ *  the nearest centre chosen so far (FP64, coordinates summed in order, no FMA); if sum D^2 = 0
+ *  it is floor(u_r n).  The prefix sums are formed per 256-point block and then across blocks;
+ *  a choice can differ from that of a left-to-right sum only when the target lies within a few
+ *  ulps of a prefix boundary.
+ *  prec        : BF16 rounds the points before the distances.
+ *  centres_out_host : L int32 (host).
+ *  labels_out  : n int32 (device, may be NULL): index of the nearest centre (ties to the
+ *                smaller index), the initial assignment.
+ *  d2_out      : n double (device, may be NULL): D^2 after the last centre.
+ *  Synchronises `stream`.
+ */
+slk_status slk_kmeanspp(const float* x, int64_t n, int32_t d, int32_t L, const double* u_host, slk_precision prec,
+                        void* stream, int32_t* centres_out_host, int32_t* labels_out, double* d2_out);
+
+/*
+ * Exact modes by definition: Eq. (1), m_l = argmax over the points y of
+ * P[y, l] = sum_p z_pl k(x_p, x_y) (the start modes of Section 4.2, from the initial
+ * assignment), or with prev_host the proximal hard-max of Eq. (10), which adds k(x_y, x_prev_l).
+ * Gaussian k with sigma2; ties to the smaller index.  Dense: 2 n^2 d + 2 n^2 L multiply-adds
+ * on MFMA (centred points split into bf16 hi + lo; kernel values and Z split likewise; FP32
+ * accumulation), so P carries a relative error of about 1e-5.
+ *  z / labels  : exactly one: n x L float32 assignment (device) or n int32 hard labels (device;
+ *                a label outside [0, L) adds nothing).
+ *  prev_host   : L int32 (host, may be NULL): previous modes for Eq. (10).
+ *  keep_host   : L int32 (host, may be NULL): the mode of a cluster with no weight (default
+ *                prev_host; with neither, such a cluster is an SLK_ERR_INVALID_ARG).
+ *  modes_out_host : L int32 (host); best_out_host : L float (host, may be NULL), the largest P.
+ *  dens_out    : n x L float32 (device, may be NULL) receives P.
+ *  1 <= L <= min(64, n).  Synchronises `stream`.
+ */
+slk_status slk_dense_modes(const float* x, int64_t n, int32_t d, int32_t L, const float* z, const int32_t* labels,
+                           double sigma2, const int32_t* prev_host, const int32_t* keep_host, slk_precision prec,
+                           void* stream, int32_t* modes_out_host, float* best_out_host, float* dens_out);
+
+/*
  * Served and batched form (an extension; the paper fits one problem at a time).
  *
  * A job is one whole problem: its graph is built from its points (slk_build_knn with
@@ -375,13 +415,15 @@ void slk_server_destroy(slk_server* sv);
 slk_status slk_fit_batched(const slk_job* jobs, int32_t n_jobs, const slk_server_opts* opts, void* stream);
 
 /*
- * Per-kernel timing for measurement: with timing on, every launch of the iteration kernels
- * ("unary_kernel", "iter_kernel", "final_kernel", "mode_reduce_kernel", "energy_kernel") made
- * by slk_assign / slk_fit is bracketed by two HIP events recorded on the call's stream, and
- * the elapsed times are accumulated per kernel name.  slk_timing_enable(on) clears the totals
- * and switches timing on (1) or off (0); slk_timing_read returns the number of timed launches
- * and their total milliseconds for one kernel name (0 and 0.0 if none).  Process-wide state;
- * timing adds one event pair per launch and should stay off in production.
+ * Per-kernel timing for measurement: with timing on, every launch of the timed kernels
+ * ("unary_kernel", "iter_kernel", "final_kernel", "mode_reduce_kernel", "energy_kernel" of
+ * slk_assign / slk_fit; "cand_kernel", "rerank_kernel" of the MFMA kNN; "kpp_dist_kernel",
+ * "kpp_select_kernel", "dmode_kernel", "ms_partial_kernel" of the extensions) is bracketed by
+ * two HIP events recorded on the call's stream, and the elapsed times are accumulated per
+ * kernel name.  slk_timing_enable(on) clears the totals and switches timing on (1) or off (0);
+ * slk_timing_read first waits for the launches still pending, then returns the number of timed
+ * launches and their total milliseconds for one kernel name (0 and 0.0 if none).  Process-wide
+ * state; timing adds one event pair per launch and should stay off in production.
  */
 slk_status slk_timing_enable(int32_t on);
 slk_status slk_timing_read(const char* kernel, int64_t* launches_host, double* total_ms_host);

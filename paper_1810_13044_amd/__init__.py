@@ -297,6 +297,54 @@ def fit_ms(x, graph: Graph, init_modes, lam=1.0, ms_tol=1e-6, ms_max_iter=100, *
     return dict(z=z, labels=lab, modes=mo, modes_used=mu, ms_steps=st.value, result=r.as_dict())
 
 
+def kmeanspp(x, L, u, prec="fp32"):
+    """K-means++ centres for the caller's uniforms u (L values in [0, 1)).  Returns
+    (centres numpy int32 [L], labels = nearest centre (device int32 [n]), D^2 (device float64 [n]))."""
+    torch = _torch()
+    lib = _lib.load()
+    n, d = x.shape
+    uh = np.ascontiguousarray(np.asarray(u, dtype=np.float64))
+    if uh.shape != (L,):
+        raise ValueError("u must hold L uniforms")
+    cent = np.empty(L, dtype=np.int32)
+    lab = torch.empty(n, dtype=torch.int32, device="cuda")
+    d2 = torch.empty(n, dtype=torch.float64, device="cuda")
+    _lib.check(lib.slk_kmeanspp(_dev(x, torch.float32, "x"), n, d, int(L), uh.ctypes.data_as(C.c_void_p),
+                                _prec(prec), _stream(), _lib.ptr_i32(cent), _dev(lab, torch.int32, "labels"),
+                                _dev(d2, torch.float64, "d2")))
+    return cent, lab, d2
+
+
+def dense_modes(x, L, sigma2, z=None, labels=None, prev=None, keep=None, prec="fp32", density=False):
+    """Modes by Eq. (1) (or Eq. (10) with prev): per cluster the point of largest z-weighted
+    kernel density.  Pass exactly one of z (n x L) and labels (n).  Returns (modes numpy int32,
+    best density numpy float32, density n x L device tensor or None)."""
+    torch = _torch()
+    lib = _lib.load()
+    n, d = x.shape
+    modes = np.empty(L, dtype=np.int32)
+    best = np.empty(L, dtype=np.float32)
+    dens = torch.empty((n, L), dtype=torch.float32, device="cuda") if density else None
+    pv = _lib.host_i32(prev) if prev is not None else None
+    kp = _lib.host_i32(keep) if keep is not None else None
+    _lib.check(lib.slk_dense_modes(_dev(x, torch.float32, "x"), n, d, int(L),
+                                   _dev(z, torch.float32, "z", (n, L)) if z is not None else None,
+                                   _dev(labels, torch.int32, "labels", (n,)) if labels is not None else None,
+                                   float(sigma2), _lib.ptr_i32(pv) if pv is not None else None,
+                                   _lib.ptr_i32(kp) if kp is not None else None, _prec(prec), _stream(),
+                                   _lib.ptr_i32(modes), best.ctypes.data_as(C.c_void_p),
+                                   _dev(dens, torch.float32, "density") if density else None))
+    return modes, best, dens
+
+
+def initial_modes(x, L, u, sigma2, prec="fp32"):
+    """The start of Section 4.2: K-means++ seeds, the nearest-seed assignment and the start
+    modes by Eq. (1).  Returns dict(seeds, labels (device), modes)."""
+    seeds, lab, _ = kmeanspp(x, L, u, prec)
+    modes, _, _ = dense_modes(x, L, sigma2, labels=lab, keep=seeds, prec=prec)
+    return dict(seeds=seeds, labels=lab, modes=modes)
+
+
 # ----------------------------------------------------------------------------- served form
 
 def knn_opts(k=10, method="auto", reorder=False, prec="fp32", candidates=0):

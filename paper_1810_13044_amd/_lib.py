@@ -96,6 +96,8 @@ def load(path: str = LIB_PATH):
         "slk_predict": [P, I64, I32, P, I32, P, P, I64, I32, D, D, I32, I32, P, P, P, P],
         "slk_mean_shift": [P, I64, I32, P, I32, P, D, D, I32, I32, P, P, P],
         "slk_fit_ms": [P, I64, I32, P, I32, P, C.POINTER(Params), D, I32, P, P, P, P, P, P, C.POINTER(Result)],
+        "slk_kmeanspp": [P, I64, I32, I32, P, I32, P, P, P, P],
+        "slk_dense_modes": [P, I64, I32, I32, P, P, D, P, P, I32, P, P, P, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)

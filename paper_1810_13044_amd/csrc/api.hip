@@ -701,6 +701,7 @@ slk_status slk_timing_enable(int32_t on) {
 
 slk_status slk_timing_read(const char* kernel, int64_t* launches_host, double* total_ms_host) {
   if (!kernel || !launches_host || !total_ms_host) return fail(SLK_ERR_INVALID_ARG, "NULL argument");
+  timing_flush();  // launches still pending are waited for and counted
   std::lock_guard<std::mutex> lk(g_tmu);
   auto it = g_tacc.find(kernel);
   *launches_host = it == g_tacc.end() ? 0 : it->second.first;

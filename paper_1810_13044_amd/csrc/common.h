@@ -320,6 +320,11 @@ slk_status knn_exact(const float* x, int64_t n, int32_t d, int32_t k, int32_t bf
 slk_status knn_mfma(const float* x, int64_t n, int32_t d, int32_t k, int32_t cand, int32_t bf16,
                     int32_t* out_idx, double* out_d2, int64_t* n_certified, int64_t* n_fallback, hipStream_t s,
                     const float* y = nullptr, int64_t m = 0);
+// Centred bf16 split of the points for MFMA Gram products (knn_mfma.hip): y = x - mean (FP64;
+// bf16 points: y = bf16(x), no centring), xh = bf16(y), xl = bf16(y - xh), dp columns (zero
+// padded), nrm = ||y||^2; mean receives the d column means (unused with bf16 points).
+slk_status split_points(const float* x, int64_t n, int32_t d, int32_t dp, int32_t bf16, double* mean, uint16_t* xh,
+                        uint16_t* xl, float* nrm, hipStream_t s);
 slk_status build_csr(int64_t n, int32_t k, const int32_t* knn_idx, int32_t** row_ptr, int32_t** col_idx,
                      int64_t* nnz, hipStream_t s);
 slk_status sum_f64(const double* v, int64_t count, double* out_dev, hipStream_t s);

@@ -492,6 +492,24 @@ __global__ __launch_bounds__(kBlock) void rerank_kernel(const float* __restrict_
 
 }  // namespace
 
+slk_status split_points(const float* x, int64_t n, int32_t d, int32_t dp, int32_t bf16, double* mean, uint16_t* xh,
+                        uint16_t* xl, float* nrm, hipStream_t s) {
+  if (!bf16) {
+    Scratch sc(s);
+    double* part;
+    const int nparts = (int)((n + kMeanRows - 1) / kMeanRows);
+    SLK_TRY(sc.get(&part, (size_t)nparts * d));
+    hipLaunchKernelGGL(colsum_kernel, dim3((d + kBlock - 1) / kBlock, nparts), dim3(kBlock), 0, s, x, n, d, part);
+    SLK_LAUNCHED("colsum_kernel");
+    hipLaunchKernelGGL(colmean_kernel, dim3((d + kBlock - 1) / kBlock), dim3(kBlock), 0, s, part, nparts, n, d, mean);
+    SLK_LAUNCHED("colmean_kernel");
+  }
+  hipLaunchKernelGGL(split_kernel, dim3((unsigned)((n + 3) / 4)), dim3(kBlock), 0, s, x, n, d, dp, mean, bf16, xh, xl,
+                     nrm);
+  SLK_LAUNCHED("split_kernel");
+  return SLK_OK;
+}
+
 slk_status knn_mfma(const float* x, int64_t n, int32_t d, int32_t k, int32_t cand, int32_t bf16, int32_t* out_idx,
                     double* out_d2, int64_t* n_certified, int64_t* n_fallback, hipStream_t s, const float* y,
                     int64_t m) {

@@ -41,38 +41,53 @@ __global__ __launch_bounds__(kBlock) void ms_partial_kernel(const float* __restr
 #pragma unroll
     for (int j = 0; j < 8; ++j) acc[i][j] = 0.f;
   float den = 0.f;
+  // the next round's weights and coordinates are loaded into registers while this round
+  // computes: thread tid moves weights (tid / 64 + 4 k, tid % 64) and coordinates
+  // (tid / 128 + 2 k, tid % 128)
+  constexpr int kWk = kSub * kLmax / kBlock, kXk = kSub * kCw / kBlock;
+  float wv[kWk], xv[kXk];
+  const int wl = tid % kLmax, wr = tid / kLmax;
+  const int xc = tid % kCw, xr = tid / kCw;
+  auto load = [&](int s0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int k = 0; k < kWk; ++k) {
+      const int64_t row = r0 + s0 + wr + (kBlock / kLmax) * k;
+      wv[k] = (row < n && wl < L) ? Z[row * ldz + wl] * A[row * ldz + wl] : 0.f;
+    }
+#pragma unroll
+    for (int k = 0; k < kXk; ++k) {
+      const int64_t row = r0 + s0 + xr + (kBlock / kCw) * k;
+      float v = 0.f;
+      if (row < n && c0 + xc < d) {
+        const int64_t g = perm ? perm[row] : row;
+        v = x[g * d + c0 + xc];
+      }
+      xv[k] = v;
+    }
+  };
+  load(0);
   for (int s0 = 0; s0 < kRowsPer; s0 += kSub) {
     __syncthreads();
-    for (int e = tid; e < kSub * kLmax; e += kBlock) {
-      const int r = e / kLmax, l = e % kLmax;
-      const int64_t row = r0 + s0 + r;
-      ws[r][l] = (row < n && l < L) ? Z[row * ldz + l] * A[row * ldz + l] : 0.f;
-    }
-    for (int e = tid; e < kSub * kCw; e += kBlock) {
-      const int r = e / kCw, c = e % kCw;
-      const int64_t row = r0 + s0 + r;
-      float v = 0.f;
-      if (row < n && c0 + c < d) {
-        const int64_t g = perm ? perm[row] : row;
-        v = x[g * d + c0 + c];
-        if (bf16) v = bf16_round(v);
-      }
-      xs[r][c] = v;
-    }
+#pragma unroll
+    for (int k = 0; k < kWk; ++k) ws[wr + (kBlock / kLmax) * k][wl] = wv[k];
+#pragma unroll
+    for (int k = 0; k < kXk; ++k) xs[xr + (kBlock / kCw) * k][xc] = bf16 ? bf16_round(xv[k]) : xv[k];
     __syncthreads();
+    if (s0 + kSub < kRowsPer && r0 + s0 + kSub < n) load(s0 + kSub);
 #pragma unroll 4
     for (int r = 0; r < kSub; ++r) {
       const float4 w = *reinterpret_cast<const float4*>(&ws[r][4 * lg]);
       const float4 xa = *reinterpret_cast<const float4*>(&xs[r][8 * cg]);
       const float4 xb = *reinterpret_cast<const float4*>(&xs[r][8 * cg + 4]);
-      const float wv[4] = {w.x, w.y, w.z, w.w};
-      const float xv[8] = {xa.x, xa.y, xa.z, xa.w, xb.x, xb.y, xb.z, xb.w};
+      const float wv4[4] = {w.x, w.y, w.z, w.w};
+      const float xv8[8] = {xa.x, xa.y, xa.z, xa.w, xb.x, xb.y, xb.z, xb.w};
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 8; ++j) acc[i][j] = fmaf(wv[i], xv[j], acc[i][j]);
+        for (int j = 0; j < 8; ++j) acc[i][j] = fmaf(wv4[i], xv8[j], acc[i][j]);
       if (tid < kLmax) den += ws[r][tid];
     }
+    if (r0 + s0 + kSub >= n) break;
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
@@ -155,9 +170,12 @@ slk_status launch_ms_step(const float* x, int64_t n, int32_t d, const int32_t* p
   if (L > kLmax) return fail(SLK_ERR_UNSUPPORTED, "mean-shift modes take L <= 64");
   const int nrb = (int)((n + kRowsPer - 1) / kRowsPer);
   const int ncw = (d + kCw - 1) / kCw;
-  hipLaunchKernelGGL(ms_partial_kernel, dim3((unsigned)nrb, (unsigned)ncw), dim3(kBlock), 0, s, x, n, d, perm, Z, A,
-                     L, ldz, bf16, pn, pd);
-  SLK_LAUNCHED("ms_partial_kernel");
+  {
+    KernelTimer kt("ms_partial_kernel", s);
+    hipLaunchKernelGGL(ms_partial_kernel, dim3((unsigned)nrb, (unsigned)ncw), dim3(kBlock), 0, s, x, n, d, perm, Z,
+                       A, L, ldz, bf16, pn, pd);
+    SLK_LAUNCHED("ms_partial_kernel");
+  }
   hipLaunchKernelGGL(ms_den_kernel, dim3((unsigned)L), dim3(kBlock), 0, s, pd, nrb, L, den);
   SLK_LAUNCHED("ms_den_kernel");
   hipLaunchKernelGGL(ms_num_kernel, dim3((unsigned)L, (unsigned)((d + 63) / 64)), dim3(kBlock), 0, s, pn, nrb, L, d,
