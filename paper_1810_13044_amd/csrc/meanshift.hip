@@ -4,9 +4,11 @@
 //
 // One step: the kernel values k(x_p, m_l) come from the unary kernel (with mode vectors);
 // ms_partial_kernel forms w = z * k and, per work-group of 1,024 rows and 128 coordinates, the
-// partial sums sum_p w_pl x_pc (a 64 x 128 register tile over 256 threads, rows staged through
-// LDS 32 at a time) and sum_p w_pl in FP32; ms_num_kernel and ms_den_kernel add the partials in
-// FP64 in a fixed order, divide, and give each mode's squared displacement.
+// partial sums sum_p w_pl x_pc and sum_p w_pl in FP32.  The first is the contraction W^T X of a
+// 64 x 1,024 by 1,024 x 128 block, done on v_mfma_f32_32x32x2_f32 (FP32 products and
+// accumulation; each wave owns two 32 x 32 cluster-by-coordinate tiles), rows staged through LDS
+// 32 at a time with the next 32 loaded into registers meanwhile.  ms_num_kernel and ms_den_kernel
+// add the partials in FP64 in a fixed order, divide, and give each mode's squared displacement.
 #include "common.h"
 
 #include <math.h>
@@ -23,23 +25,26 @@ constexpr int kSub = 32;         // rows staged per LDS round
 constexpr int kCw = 128;         // coordinates per work-group
 constexpr int kLmax = 64;
 
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+
 __global__ __launch_bounds__(kBlock) void ms_partial_kernel(const float* __restrict__ x, int64_t n, int d,
                                                             const int32_t* __restrict__ perm,
                                                             const float* __restrict__ Z, const float* __restrict__ A,
                                                             int L, int ldz, int bf16, float* __restrict__ part_num,
                                                             float* __restrict__ part_den) {
-  __shared__ float ws[kSub][kLmax];
-  __shared__ float xs[kSub][kCw + 4];
-  const int tid = threadIdx.x;
-  const int lg = tid >> 4, cg = tid & 15;   // clusters 4 lg .. +3, coordinates 8 cg .. +7
+  // rows padded by 32 floats: the two half-waves read consecutive rows in different banks
+  __shared__ float ws[kSub][kLmax + 32];
+  __shared__ float xs[kSub][kCw + 32];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 5, col = lane & 31;
+  // wave w: clusters 32 (w / 2) .. +31, coordinates 64 (w % 2) .. +63 as two 32-wide tiles
+  const int lb = wave >> 1, cb = (wave & 1) * 64;
   const int64_t rb = blockIdx.x;
   const int c0 = blockIdx.y * kCw;
   const int64_t r0 = rb * kRowsPer;
-  float acc[4][8];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 8; ++j) acc[i][j] = 0.f;
+  f32x16 acc[2];
+  acc[0] = f32x16{};
+  acc[1] = f32x16{};
   float den = 0.f;
   // the next round's weights and coordinates are loaded into registers while this round
   // computes: thread tid moves weights (tid / 64 + 4 k, tid % 64) and coordinates
@@ -59,8 +64,8 @@ __global__ __launch_bounds__(kBlock) void ms_partial_kernel(const float* __restr
       const int64_t row = r0 + s0 + xr + (kBlock / kCw) * k;
       float v = 0.f;
       if (row < n && c0 + xc < d) {
-        const int64_t g = perm ? perm[row] : row;
-        v = x[g * d + c0 + xc];
+        const int64_t gr = perm ? perm[row] : row;
+        v = x[gr * d + c0 + xc];
       }
       xv[k] = v;
     }
@@ -74,29 +79,26 @@ __global__ __launch_bounds__(kBlock) void ms_partial_kernel(const float* __restr
     for (int k = 0; k < kXk; ++k) xs[xr + (kBlock / kCw) * k][xc] = bf16 ? bf16_round(xv[k]) : xv[k];
     __syncthreads();
     if (s0 + kSub < kRowsPer && r0 + s0 + kSub < n) load(s0 + kSub);
+    // A[l][k] = w of row k, B[k][c] = x of row k: lane t supplies row 2 s + t / 32
 #pragma unroll 4
-    for (int r = 0; r < kSub; ++r) {
-      const float4 w = *reinterpret_cast<const float4*>(&ws[r][4 * lg]);
-      const float4 xa = *reinterpret_cast<const float4*>(&xs[r][8 * cg]);
-      const float4 xb = *reinterpret_cast<const float4*>(&xs[r][8 * cg + 4]);
-      const float wv4[4] = {w.x, w.y, w.z, w.w};
-      const float xv8[8] = {xa.x, xa.y, xa.z, xa.w, xb.x, xb.y, xb.z, xb.w};
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 8; ++j) acc[i][j] = fmaf(wv4[i], xv8[j], acc[i][j]);
-      if (tid < kLmax) den += ws[r][tid];
+    for (int s2 = 0; s2 < kSub / 2; ++s2) {
+      const int r = 2 * s2 + g;
+      const float a = ws[r][32 * lb + col];
+      acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, xs[r][cb + col], acc[0], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, xs[r][cb + 32 + col], acc[1], 0, 0, 0);
     }
+    if (tid < kLmax)
+      for (int r = 0; r < kSub; ++r) den += ws[r][tid];
     if (r0 + s0 + kSub >= n) break;
   }
+  // C layout: lane t holds coordinate t % 32 of the tile, clusters 8 (r / 4) + 4 (t / 32) + r % 4
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int l = 4 * lg + i;
-    if (l >= L) continue;
+  for (int j = 0; j < 2; ++j) {
+    const int c = c0 + cb + 32 * j + col;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int c = c0 + 8 * cg + j;
-      if (c < d) part_num[(rb * L + l) * d + c] = acc[i][j];
+    for (int r = 0; r < 16; ++r) {
+      const int l = 32 * lb + 8 * (r >> 2) + 4 * g + (r & 3);
+      if (l < L && c < d) part_num[(rb * L + l) * d + c] = acc[j][r];
     }
   }
   if (blockIdx.y == 0 && tid < L) part_den[rb * L + tid] = den;
