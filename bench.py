@@ -264,7 +264,7 @@ def precision(slk, torch, big_x, big_g, big_inst, r32):
     return out
 
 
-def extensions(slk, torch, x, g, inst, fit_z, fit_modes):
+def extensions(slk, torch, x, g, inst, fit_z, fit_modes, workload):
     """The rows after the hot path, on the same resident points, each kernel timed with HIP
     events on its launch stream:
       K-means++ seeding (L rounds; kpp_dist_kernel reads X and D^2 once per round: HBM roofline),
@@ -296,6 +296,7 @@ def extensions(slk, torch, x, g, inst, fit_z, fit_modes):
                        "select_kernel_avg_us": round(sms / max(ns, 1) * 1e3, 2),
                        "roofline": {"kernel": "kpp_dist_kernel", "bound": "hbm", "achieved": round(ach, 1),
                                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                                    "traffic": traffic_entry("kpp_dist_kernel", workload),
                                     "alg_bytes_per_launch": alg}}
     log(f"[ext] kmeans++ {out['kmeanspp']}")
     # ---- exact modes by Eq. (1) from the nearest-seed assignment
@@ -338,6 +339,7 @@ def extensions(slk, torch, x, g, inst, fit_z, fit_modes):
                          "partial_kernel_avg_us": round(per * 1e3, 2),
                          "roofline": {"kernel": "ms_partial_kernel", "bound": "hbm", "achieved": round(ach, 1),
                                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                                      "traffic": traffic_entry("ms_partial_kernel", workload),
                                       "alg_bytes_per_launch": alg}}
     log(f"[ext] mean shift {out['mean_shift']}")
     # ---- out-of-sample assignment
@@ -452,7 +454,7 @@ def main():
     ext = None
     if args.extensions:
         fr = slk.fit(x, g, inst.init_modes, lam=lam)
-        ext = extensions(slk, torch, x, g, inst, fr["z"], fr["modes"])
+        ext = extensions(slk, torch, x, g, inst, fr["z"], fr["modes"], args.workload)
         del fr
 
     serve = None
