@@ -70,6 +70,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   constexpr int kZ = LB * 4 * 64 * 8;
   __shared__ __attribute__((aligned(16))) uint16_t zst[(HARD ? 1 : 2) * kZ];
   __shared__ __attribute__((aligned(16))) float nst[kPT];
+  __shared__ __attribute__((aligned(16))) int labs[kPT];
   __shared__ float tots[4 * 16 * LB * 64];
   static_assert(sizeof(float) * 4 * 64 * 2 <= sizeof(uint16_t) * 3 * 2 * kStage, "best lists fit in the ring");
   float(*wbv)[64] = reinterpret_cast<float(*)[64]>(xst);
@@ -129,38 +130,62 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     if (SPLIT) *reinterpret_cast<uint4*>(b + kStage + spt * kRow + spiece) = pl;
   };
 
-  // Z and norms of a tile: thread tid takes point tid / 4 and clusters (tid % 4) 8 LB .. + 8 LB - 1
-  constexpr int ZC = 8 * LB;
-  const int zp = tid >> 2, zq = (tid & 3) * ZC;
-  float zv[HARD ? 1 : ZC];
-  int zl = -1;
+  // Z and norms of a tile.  The Z^T operand of the second product is LB x 4 x 64 slots of 8 bf16
+  // (slot s = ((lb 4 + kc) 64 + lane): cluster 32 lb + lane % 32, points 16 kc + 8 (e / 4) +
+  // 4 (lane / 32) + e % 4); each thread builds whole slots and writes them as 16 bytes.
+  // Hard labels: thread tid < 64 loads the label of point tid of the next tile one step ahead,
+  // stores it in `labs` at the tile's second chunk (after a barrier), and the slots read it from
+  // there when the tile's Z is stashed (after the next barrier).
+  constexpr int SPT = LB * 4 * 64 / kBlock;   // slots per thread
+  float zv[SPT][8];
+  int lreg = -1;
   float nv = -INFINITY;
   auto zfetch = [&](int64_t t) __attribute__((always_inline)) {
-    const int64_t p = t * kPT + zp;
     if constexpr (HARD) {
-      zl = p < n ? lab[p] : -1;
+      if (tid < kPT) lreg = t * kPT + tid < n ? lab[t * kPT + tid] : -1;
     } else {
 #pragma unroll
-      for (int i = 0; i < ZC; ++i) zv[i] = (p < n && zq + i < L) ? z[p * L + zq + i] : 0.f;
+      for (int i = 0; i < SPT; ++i) {
+        const int sl = tid + kBlock * i;
+        const int sln = sl & 63, kc = (sl >> 6) & 3, lb2 = sl >> 8;
+        const int l = 32 * lb2 + (sln & 31), gg = sln >> 5;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int64_t p = t * kPT + 16 * kc + 8 * (e >> 2) + 4 * gg + (e & 3);
+          zv[i][e] = (p < n && l < L) ? z[p * L + l] : 0.f;
+        }
+      }
     }
     if (tid < kPT) nv = t * kPT + tid < n ? kscale * nrm[t * kPT + tid] : -INFINITY;
   };
+  auto lstash = [&]() __attribute__((always_inline)) {
+    if (HARD && tid < kPT) labs[tid] = lreg;
+  };
   auto zstash = [&]() __attribute__((always_inline)) {
-    const int pp = zp & 15, kc = zp >> 4;
-    const int gg = (pp >> 2) & 1, e = ((pp >> 3) << 2) | (pp & 3);
 #pragma unroll
-    for (int i = 0; i < ZC; ++i) {
-      const int l = zq + i;
-      const int lb = l >> 5, row = l & 31;
-      const int o = ((lb * 4 + kc) * 64 + 32 * gg + row) * 8 + e;
+    for (int i = 0; i < SPT; ++i) {
+      const int sl = tid + kBlock * i;
+      const int l = 32 * (sl >> 8) + (sl & 31);
+      bf16x8 hi, lo;
+      int lv[8];
       if constexpr (HARD) {
-        zst[o] = zl == l ? (uint16_t)0x3F80 : (uint16_t)0;  // bf16 1.0 / 0.0
-      } else {
-        const __bf16 hb = (__bf16)zv[i];
-        const __bf16 lb16 = (__bf16)(zv[i] - (float)hb);
-        zst[o] = __builtin_bit_cast(uint16_t, hb);
-        zst[kZ + o] = __builtin_bit_cast(uint16_t, lb16);
+        const int kc = (sl >> 6) & 3, gg = (sl >> 5) & 1;
+        const int4 a0 = *reinterpret_cast<const int4*>(labs + 16 * kc + 4 * gg);
+        const int4 a1 = *reinterpret_cast<const int4*>(labs + 16 * kc + 8 + 4 * gg);
+        lv[0] = a0.x; lv[1] = a0.y; lv[2] = a0.z; lv[3] = a0.w;
+        lv[4] = a1.x; lv[5] = a1.y; lv[6] = a1.z; lv[7] = a1.w;
       }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        if constexpr (HARD) {
+          hi[e] = lv[e] == l ? (__bf16)1.0f : (__bf16)0.0f;
+        } else {
+          hi[e] = (__bf16)zv[i][e];
+          lo[e] = (__bf16)(zv[i][e] - (float)hi[e]);
+        }
+      }
+      *reinterpret_cast<bf16x8*>(zst + sl * 8) = hi;
+      if constexpr (!HARD) *reinterpret_cast<bf16x8*>(zst + kZ + sl * 8) = lo;
     }
     if (tid < kPT) nst[tid] = nv;
   };
@@ -232,6 +257,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   if constexpr (RES == 0) yfetch(0);
   fetch(0);
   zfetch(0);
+  lstash();
   stash(0);
   if (steps > 1) fetch(1);
   for (int64_t i = 0; i < steps; ++i) {
@@ -241,6 +267,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     if (c == 0) {
       zstash();
       if (t + 1 < ntile) zfetch(t + 1);
+    } else if (c == 1) {
+      lstash();
     }
     if (i + 1 < steps) stash(i + 1);
     bf16x8 cbh[2], cbl[2];
