@@ -92,3 +92,50 @@ def test_python_layer_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(_lib, "_lib", None)
     with pytest.raises(ImportError):
         _lib.load(str(tmp_path / "missing.so"))
+
+
+def test_extension_entry_points_reject_invalid_arguments(lib):
+    """slk_kmeanspp, slk_dense_modes, slk_mean_shift, slk_fit_ms and slk_predict check their
+    arguments on the host before any device work."""
+    from paper_1810_13044_amd import _lib
+    fake = C.c_void_p(0x1000)
+    P = lambda a: a.ctypes.data_as(C.c_void_p)
+    u = np.array([0.2, 0.5, 1.0], dtype=np.float64)
+    cent = np.zeros(3, dtype=np.int32)
+    assert lib.slk_kmeanspp(fake, 100, 4, 3, P(u), 0, None, P(cent), None, None) == 1
+    assert b"[0, 1)" in lib.slk_last_error()
+    u[2] = 0.7
+    assert lib.slk_kmeanspp(fake, 100, 4, 101, P(u), 0, None, P(cent), None, None) == 1
+    assert lib.slk_kmeanspp(fake, 100, 4, 3, None, 0, None, P(cent), None, None) == 1
+    assert lib.slk_kmeanspp(fake, 100, 4, 3, P(u), 9, None, P(cent), None, None) == 1
+    modes = np.zeros(65, dtype=np.int32)
+    best = np.zeros(65, dtype=np.float32)
+    assert lib.slk_dense_modes(fake, 100, 4, 65, fake, None, 1.0, None, None, 0, None, P(modes), P(best), None) == 1
+    assert lib.slk_dense_modes(fake, 100, 4, 3, None, None, 1.0, None, None, 0, None, P(modes), P(best), None) == 1
+    assert b"exactly one" in lib.slk_last_error()
+    assert lib.slk_dense_modes(fake, 100, 4, 3, fake, fake, 1.0, None, None, 0, None, P(modes), P(best), None) == 1
+    assert lib.slk_dense_modes(fake, 100, 4, 3, fake, None, 0.0, None, None, 0, None, P(modes), P(best), None) == 1
+    prev = np.array([0, 1, 100], dtype=np.int32)
+    assert lib.slk_dense_modes(fake, 100, 4, 3, fake, None, 1.0, P(prev), None, 0, None, P(modes), P(best),
+                               None) == 1
+    assert b"out of range" in lib.slk_last_error()
+    it = C.c_int32(0)
+    assert lib.slk_mean_shift(fake, 100, 4, fake, 65, fake, 1.0, 1e-6, 10, 0, None, fake, C.byref(it)) == 1
+    assert lib.slk_mean_shift(fake, 100, 4, fake, 3, fake, -1.0, 1e-6, 10, 0, None, fake, C.byref(it)) == 1
+    assert lib.slk_mean_shift(fake, 100, 4, fake, 3, fake, 1.0, 1e-6, 0, 0, None, fake, C.byref(it)) == 1
+    p = _lib.Params()
+    lib.slk_params_default(C.byref(p))
+    r = _lib.Result()
+    assert lib.slk_fit_ms(fake, 100, 4, None, 3, fake, C.byref(p), 1e-6, 10, None, fake, None, fake, None, None,
+                          C.byref(r)) == 1
+    assert lib.slk_predict(fake, 100, 4, fake, 3, P(prev[:2]), fake, 10, 0, 1.0, 1.0, 0, 0, None, fake, None,
+                           None) == 1
+    assert b"k must" in lib.slk_last_error()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr and r.stdout == ""

@@ -131,6 +131,8 @@ DM_CASES = [
     ("d128-L33", dict(n=1300, d=128, L=33, seed=26), "soft", "fp32"),
     ("bf16-hard", dict(n=1200, d=20, L=6, seed=27), "hard", "bf16"),
     ("bf16-soft-wide", dict(n=900, d=200, L=9, seed=28), "soft", "bf16"),
+    ("L1", dict(n=500, d=5, L=1, seed=29), "soft", "fp32"),
+    ("d784-hard", dict(n=600, d=784, L=10, seed=30), "hard", "fp32"),
 ]
 
 
@@ -180,6 +182,12 @@ def test_dense_modes_empty_cluster(slk, torch):
     assert modes[2] == 577 and modes[2] == ref[2]
     with pytest.raises(SlkError):
         slk.dense_modes(x, 3, 10.0, labels=to_dev(torch, lab, torch.int32))
+    # Eq. (10): a cluster with no weight keeps its previous mode
+    prev = [5, 6, 321]
+    modes, _, _ = slk.dense_modes(x, 3, 10.0, labels=to_dev(torch, lab, torch.int32), prev=prev)
+    ref, _ = seeding.dense_modes(inst.X, np.eye(3)[lab], 10.0, prev=prev)
+    assert modes[2] == 321 == ref[2]
+    assert np.array_equal(modes[:2], ref[:2])
 
 
 def test_dense_modes_larger_ragged(slk, torch):
