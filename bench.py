@@ -109,21 +109,30 @@ def cpu_baseline(graph, A, Z0, lam, N, nnz, L, budget_s=20.0):
                       f"host has {os.cpu_count()} logical CPUs"}
 
 
-def serving(slk, torch, n_jobs, rate, max_jobs, passes, prec="fp32"):
-    """Poisson stream of independent jobs (N log-uniform in [500, 50000], D in {64, 128, 256},
-    L in [5, 50], k = 10, lambda = 1), points resident on the device before the clock starts.
-    plain: one job at a time, each slk_build_knn + slk_fit, in arrival order.
-    served: the continuous-batching server, jobs submitted as they arrive.
-    Latency = completion - arrival; solves/s = jobs / (last completion - first arrival)."""
+SERVE_WORKLOAD = ("Poisson arrivals (seed 5); N log-uniform [500, 50000], D in {64,128,256}, L in [5,50], k=10, "
+                  "lambda=1; Gaussian mixtures seeded per job (10000 + id)")
+
+
+def _materialise_jobs(torch, n_jobs):
+    """The job stream's data, resident on the device, and its arrival times at 1 job/s (the
+    stream at rate r arrives at these times / r: the gaps are exponential draws scaled by 1/r)."""
     import gen
-    specs = gen.job_stream(n_jobs=n_jobs, rate=rate, seed=5)
+    specs = gen.job_stream(n_jobs=n_jobs, rate=1.0, seed=5)
     t0 = time.perf_counter()
     insts = [gen.materialise(sp, K=10) for sp in specs]
     xs = [torch.from_numpy(i.X).to("cuda") for i in insts]
-    arr = np.array([sp[1] for sp in specs])
     torch.cuda.synchronize()
-    log(f"[serve] {n_jobs} jobs at {rate}/s materialised in {time.perf_counter() - t0:.1f}s "
+    log(f"[serve] {n_jobs} jobs materialised in {time.perf_counter() - t0:.1f}s "
         f"(N {min(i.N for i in insts)}..{max(i.N for i in insts)})")
+    return insts, xs, np.array([sp[1] for sp in specs])
+
+
+def _serve_once(slk, torch, insts, xs, arr, max_jobs, passes, prec):
+    """plain: one job at a time, each slk_build_knn + slk_fit, in arrival order.
+    served: the continuous-batching server, jobs submitted as they arrive.
+    Latency = completion - arrival; solves/s = jobs / (last completion - first arrival).
+    Also checks that every served result equals the plain one (labels and FP64 energy)."""
+    n_jobs = len(insts)
 
     def stats(done_t, wall):
         lat = (done_t - arr) * 1e3
@@ -139,20 +148,23 @@ def serving(slk, torch, n_jobs, rate, max_jobs, passes, prec="fp32"):
 
     # plain: one job at a time
     done = np.zeros(n_jobs)
+    plain_out = [None] * n_jobs
     start = time.perf_counter()
     for j, (inst, x) in enumerate(zip(insts, xs)):
         now = time.perf_counter() - start
         if now < arr[j]:
             time.sleep(arr[j] - now)
         g = slk.Graph.build_knn(x, k=10, prec=prec)
-        slk.fit(x, g, inst.init_modes, lam=inst.lam, prec=prec)
+        r = slk.fit(x, g, inst.init_modes, lam=inst.lam, prec=prec)
         done[j] = time.perf_counter() - start
+        plain_out[j] = r
         del g
     plain = stats(done, done.max() - arr[0])
 
     # served
     sv = slk.Server(max_jobs=max_jobs, passes_per_step=passes)
     done = np.zeros(n_jobs)
+    served_out = [None] * n_jobs
     tick = {}
     nxt, finished, steps = 0, 0, 0
     start = time.perf_counter()
@@ -171,16 +183,68 @@ def serving(slk, torch, n_jobs, rate, max_jobs, passes, prec="fp32"):
         for tk, o in out.items():
             assert o["status"] == 0, o["status"]
             done[tick[tk]] = t
+            served_out[tick[tk]] = o
             finished += 1
     sv.close()
     served = stats(done, done.max() - arr[0])
     served["steps"] = steps
-    return {"jobs": n_jobs, "rate_per_s": rate, "max_jobs": max_jobs, "passes_per_step": passes, "precision": prec,
-            "plain": plain, "served": served,
-            "speedup_solves": round(float(served["solves_per_s"] / plain["solves_per_s"]), 2),
-            "p99_ratio": round(float(plain["p99_ms"] / served["p99_ms"]), 2),
-            "workload": "Poisson arrivals (seed 5); N log-uniform [500, 50000], D in {64,128,256}, L in [5,50], "
-                        "k=10, lambda=1; Gaussian mixtures seeded per job (10000 + id)"}
+    same = sum(1 for a, b in zip(plain_out, served_out)
+               if a["result"]["energy_fp64"] == b["result"]["energy_fp64"] and torch.equal(a["labels"], b["labels"]))
+    res = {"precision": prec, "plain": plain, "served": served,
+           "speedup_solves": round(float(served["solves_per_s"] / plain["solves_per_s"]), 2),
+           "p99_ratio": round(float(plain["p99_ms"] / served["p99_ms"]), 2),
+           "served_identical_to_plain": f"{same}/{n_jobs}"}
+    return res, plain_out, served_out
+
+
+def serving(slk, torch, n_jobs, rate, max_jobs, passes, prec="fp32"):
+    """One rate and precision of the served form against one-at-a-time fits on the job stream."""
+    insts, xs, arr1 = _materialise_jobs(torch, n_jobs)
+    res, _, _ = _serve_once(slk, torch, insts, xs, arr1 / rate, max_jobs, passes, prec)
+    return dict({"jobs": n_jobs, "rate_per_s": rate, "max_jobs": max_jobs, "passes_per_step": passes,
+                 "workload": SERVE_WORKLOAD}, **res)
+
+
+def serving_sweep(slk, torch, n_jobs, rates, max_jobs, passes):
+    """The served form at several arrival rates, FP32 and BF16-X (points rounded to bf16 for the
+    kNN and the unary term), each against one-at-a-time fits of the same precision.  The BF16-X
+    results are compared with the FP32 ones on the FP32 problem: energy of the BF16-X labels and
+    modes on the FP32 graph with the FP64 unary term, and label agreement."""
+    insts, xs, arr1 = _materialise_jobs(torch, n_jobs)
+    runs = []
+    keep = {}
+    for rate in rates:
+        for prec in ("fp32", "bf16"):
+            res, _, sv_out = _serve_once(slk, torch, insts, xs, arr1 / rate, max_jobs, passes, prec)
+            res["rate_per_s"] = rate
+            log(f"[serve] rate {rate} {prec}: {res}")
+            runs.append(res)
+            if prec not in keep:
+                keep[prec] = sv_out
+    gaps, tgaps, lower, agree = [], [], [], []
+    for j, (inst, x) in enumerate(zip(insts, xs)):
+        o32, o16 = keep["fp32"][j], keep["bf16"][j]
+        g = slk.Graph.build_knn(x, k=10)
+        e = slk.energy(x, g, o16["labels"], o16["modes"], lam=inst.lam)["energy_fp64"]
+        r32 = o32["result"]
+        e32 = r32["energy_fp64"]
+        terms = (inst.lam * r32["cut"] - e32) + inst.lam * r32["cut"]    # |unary| + |pairwise|
+        gaps.append(abs(e - e32) / abs(e32))
+        tgaps.append(abs(e - e32) / terms)
+        lower.append(e < e32)
+        agree.append(float((o16["labels"] == o32["labels"]).float().mean()))
+        del g
+    gaps, tgaps, agree = np.array(gaps), np.array(tgaps), np.array(agree)
+    bf16_vs_fp32 = {"energy_rel_gap_median": float(np.median(gaps)), "energy_rel_gap_p99": float(np.percentile(gaps, 99)),
+                    "energy_rel_gap_max": float(gaps.max()), "jobs_within_1e-4": int((gaps <= 1e-4).sum()),
+                    "gap_over_term_magnitudes_median": float(np.median(tgaps)),
+                    "gap_over_term_magnitudes_p99": float(np.percentile(tgaps, 99)),
+                    "bf16_lower_energy_fraction": float(np.mean(lower)),
+                    "identical_labels_jobs": int((agree == 1.0).sum()),
+                    "label_agreement_median": float(np.median(agree)), "label_agreement_min": float(agree.min())}
+    log(f"[serve] bf16 vs fp32: {bf16_vs_fp32}")
+    return {"jobs": n_jobs, "max_jobs": max_jobs, "passes_per_step": passes, "workload": SERVE_WORKLOAD,
+            "runs": runs, "bf16_vs_fp32": bf16_vs_fp32}
 
 
 def _round_bf16(X):
@@ -373,6 +437,9 @@ def main():
     ap.add_argument("--serve-jobs", type=int, default=300, help="jobs in the served-form run (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--serve-sweep", default="",
+                    help="comma-separated arrival rates: the served form at each, FP32 and BF16-X (replaces the "
+                         "single-rate run)")
     ap.add_argument("--extensions", type=int, default=1,
                     help="time seeding, exact modes, mean-shift and out-of-sample assignment (0 = skip)")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -458,7 +525,10 @@ def main():
         del fr
 
     serve = None
-    if args.serve_jobs > 0:
+    if args.serve_jobs > 0 and args.serve_sweep:
+        rates = [float(v) for v in args.serve_sweep.split(",")]
+        serve = serving_sweep(slk, torch, args.serve_jobs, rates, args.serve_slots, 2)
+    elif args.serve_jobs > 0:
         serve = serving(slk, torch, args.serve_jobs, args.serve_rate, args.serve_slots, 2)
         log(f"[serve] {serve}")
 

@@ -349,8 +349,11 @@ slk_status slk_dense_modes(const float* x, int64_t n, int32_t d, int32_t L, cons
  * modes, energy) into one launch per kernel, whatever the jobs' sizes, so many small problems
  * share the GPU.  Queued jobs are admitted whenever a slot is free and the job's estimated
  * device footprint fits the memory budget (continuous batching: jobs join and leave between
- * steps while the others keep running).  Every job gets exactly the work-groups, tiles and
- * reduction order of its own slk_fit, so its outputs are bit-identical to running it alone.
+ * steps while the others keep running).  An admitted job's graph is built by one of
+ * opts.builders worker threads, each on its own stream, while the resident jobs keep stepping;
+ * the job joins the steps when its graph is ready.  Every job gets exactly the work-groups,
+ * tiles and reduction order of its own slk_fit, so its outputs are bit-identical to running it
+ * alone.
  *
  * slk_job: caller-owned descriptions and buffers, which must stay valid until the job is
  * reported done.
@@ -384,11 +387,14 @@ typedef struct {
   int32_t passes_per_step;  /* z-updates queued per step for jobs in their inner loop (>= 1)    */
   int64_t memory_budget;    /* bytes of device memory the resident jobs may use (0 = 80% of
                                the free memory when the server is created)                     */
+  int32_t builders;         /* worker threads building admitted jobs' graphs, each on its own
+                               stream, while the resident jobs step; 1 <= builders <= 8        */
+  int32_t reserved;
 } slk_server_opts;
 
 typedef struct slk_server slk_server;
 
-/* Fill *o with defaults: max_jobs 64, passes_per_step 2, memory_budget 0. */
+/* Fill *o with defaults: max_jobs 64, passes_per_step 2, memory_budget 0, builders 3. */
 slk_status slk_server_opts_default(slk_server_opts* o);
 
 /* Create a server that runs on `stream` (device = the current device).  Release with
@@ -400,10 +406,12 @@ slk_status slk_server_create(const slk_server_opts* opts, void* stream, slk_serv
    parameters and kNN options valid). */
 slk_status slk_server_submit(slk_server* sv, const slk_job* job, int64_t* ticket_host);
 
-/* Admit what fits, then run one step for every resident job and synchronise the server's
-   stream.  done_host (may be NULL) receives up to `cap` tickets of jobs finished in this or an
-   earlier step and not yet reported; *n_done_host their number.  *n_active_host and
-   *n_queued_host (may be NULL) receive the resident and waiting job counts after the step. */
+/* Admit what fits (queued jobs go to the graph builders), take in the jobs whose graphs are
+   ready, then run one step for every resident job and synchronise the server's stream.  With no
+   resident job and graphs still being built, waits for the first of them.  done_host (may be
+   NULL) receives up to `cap` tickets of jobs finished in this or an earlier step and not yet
+   reported; *n_done_host their number.  *n_active_host and *n_queued_host (may be NULL) receive
+   the resident and the waiting job counts (queued or in a graph build) after the step. */
 slk_status slk_server_step(slk_server* sv, int64_t* done_host, int32_t cap, int32_t* n_done_host,
                            int32_t* n_active_host, int32_t* n_queued_host);
 

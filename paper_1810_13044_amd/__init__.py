@@ -394,11 +394,13 @@ class Server:
     admit what fits and advance every resident job; finished jobs' outcomes are returned by
     step() and kept in .done."""
 
-    def __init__(self, max_jobs=64, passes_per_step=2, memory_budget=0):
+    def __init__(self, max_jobs=64, passes_per_step=2, memory_budget=0, builders=0):
         self._lib = _lib.load()
         o = _lib.ServerOpts()
         _lib.check(self._lib.slk_server_opts_default(C.byref(o)))
         o.max_jobs, o.passes_per_step, o.memory_budget = int(max_jobs), int(passes_per_step), int(memory_budget)
+        if builders:
+            o.builders = int(builders)
         h = C.c_void_p()
         _lib.check(self._lib.slk_server_create(C.byref(o), _stream(), C.byref(h)))
         self._h = h

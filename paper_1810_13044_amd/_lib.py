@@ -65,7 +65,8 @@ class Job(C.Structure):
 
 
 class ServerOpts(C.Structure):
-    _fields_ = [("max_jobs", C.c_int32), ("passes_per_step", C.c_int32), ("memory_budget", C.c_int64)]
+    _fields_ = [("max_jobs", C.c_int32), ("passes_per_step", C.c_int32), ("memory_budget", C.c_int64),
+                ("builders", C.c_int32), ("reserved", C.c_int32)]
 
 
 _lib = None

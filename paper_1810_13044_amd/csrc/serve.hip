@@ -11,13 +11,18 @@
 // (launch_*_packed: each job keeps the work-groups, tiles and reduction order of its own
 // launch), then copies every job's small device state (its Slot) back to the host in one copy
 // and synchronises.  Queued jobs are admitted between steps when a slot is free and their
-// estimated footprint fits the memory budget; their graphs are built on admission.
+// estimated footprint fits the memory budget.  An admitted job's graph is built by a worker
+// thread on its own stream while the resident jobs keep stepping (the builds overlap the
+// iterations on the device); the job joins the steps once its graph is ready.
 #include "common.h"
 
 #include <string.h>
 
 #include <algorithm>
+#include <condition_variable>
 #include <deque>
+#include <mutex>
+#include <thread>
 #include <vector>
 
 namespace slk {
@@ -98,6 +103,7 @@ struct Job {
   int launched = 0;      // z-updates queued in this outer iteration
   int passes = 0;        // z-updates that ran in the last finished inner loop
   int limit = 0;         // fixed_inner, else max_inner
+  slk_status build_status = SLK_OK;
   slk_result r{};
 };
 
@@ -135,6 +141,15 @@ struct slk_server {
   char* tab_dev = nullptr;
   char* tab_host = nullptr;     // pinned
   size_t tab_cap = 0;
+  // graph builds: worker threads, each with its own stream (default priority)
+  std::vector<std::thread> builders;
+  std::vector<hipStream_t> bss;
+  std::mutex mu;
+  std::condition_variable cv_todo, cv_built;
+  std::deque<Job*> to_build;    // admitted, graph not built yet
+  std::deque<Job*> built;       // graph built (or failed: build_status)
+  int building = 0;             // handed to the builder and not taken back yet
+  bool stop = false;
 };
 
 namespace slk {
@@ -172,13 +187,41 @@ void release(slk_server* sv, Job* j) {
   delete j;
 }
 
-// Graph, buffers and slot of a newly admitted job.  On failure the job is delivered with the
-// error and released; the server carries on.
+// A worker: builds the graphs of admitted jobs on its own stream, one at a time, and hands each
+// job back complete (its stream synchronised) with the build's status.
+void builder_loop(slk_server* sv, int w) {
+  (void)hipSetDevice(sv->device);
+  const hipStream_t bs = sv->bss[w];
+  for (;;) {
+    Job* j = nullptr;
+    {
+      std::unique_lock<std::mutex> lk(sv->mu);
+      sv->cv_todo.wait(lk, [&] { return sv->stop || !sv->to_build.empty(); });
+      if (sv->stop) return;
+      j = sv->to_build.front();
+      sv->to_build.pop_front();
+    }
+    const slk_job& sp = j->spec;
+    slk_status st = slk_build_knn(sp.x, sp.n, sp.d, &sp.knn, bs, &j->g);
+    if (st == SLK_OK && hipStreamSynchronize(bs) != hipSuccess) {
+      (void)hipGetLastError();
+      st = fail(SLK_ERR_DEVICE, "graph build");
+    }
+    j->build_status = st;
+    {
+      std::lock_guard<std::mutex> lk(sv->mu);
+      sv->built.push_back(j);
+    }
+    sv->cv_built.notify_all();
+  }
+}
+
+// Buffers and slot state of a job whose graph is built.  On failure the job is delivered with
+// the error and released; the server carries on.
 slk_status admit(slk_server* sv, Job* j) {
   hipStream_t s = sv->s;
   const slk_job& sp = j->spec;
-  slk_status st = slk_build_knn(sp.x, sp.n, sp.d, &sp.knn, s, &j->g);
-  if (st != SLK_OK) return st;
+  if (j->build_status != SLK_OK) return j->build_status;
   j->sigma2 = pick_sigma2(sp.params, j->g);
   if (!(j->sigma2 > 0.0)) return fail(SLK_ERR_INVALID_ARG, "sigma2 unknown: pass params.sigma2 > 0");
   const int64_t n = sp.n;
@@ -218,8 +261,6 @@ slk_status admit(slk_server* sv, Job* j) {
   j->epart_un64 = (double*)(b + oE2);
   j->epart_cut = (long long*)(b + oE3);
   SLK_TRY(launch_col_offsets(j->g->col_idx, j->g->nnz, n, j->L, j->col_off, s));
-  j->slot = sv->free_slots.back();
-  sv->free_slots.pop_back();
   j->phase = Phase::kUnary;
   j->fresh = true;
   j->limit = sp.params.fixed_inner > 0 ? sp.params.fixed_inner : sp.params.max_inner;
@@ -288,12 +329,31 @@ slk_status grow_tables(slk_server* sv, size_t need) {
 
 slk_status server_step(slk_server* sv) {
   hipStream_t s = sv->s;
-  // ---- admission
-  while (!sv->queue.empty() && !sv->free_slots.empty()) {
-    Job* j = sv->queue.front();
-    if (sv->used + j->footprint > sv->budget && !sv->active.empty()) break;
-    sv->queue.pop_front();
-    sv->used += j->footprint;
+  // ---- admission: a free slot and room in the budget send a queued job to the builder
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    while (!sv->queue.empty() && !sv->free_slots.empty()) {
+      Job* j = sv->queue.front();
+      if (sv->used + j->footprint > sv->budget && (!sv->active.empty() || sv->building > 0)) break;
+      sv->queue.pop_front();
+      sv->used += j->footprint;
+      j->slot = sv->free_slots.back();
+      sv->free_slots.pop_back();
+      sv->to_build.push_back(j);
+      ++sv->building;
+    }
+  }
+  sv->cv_todo.notify_all();
+  // ---- jobs whose graphs are ready join; with nothing resident, wait for the next one
+  std::deque<Job*> ready;
+  {
+    std::unique_lock<std::mutex> lk(sv->mu);
+    if (sv->active.empty() && sv->built.empty() && sv->building > 0)
+      sv->cv_built.wait(lk, [&] { return !sv->built.empty(); });
+    ready.swap(sv->built);
+    sv->building -= (int)ready.size();
+  }
+  for (Job* j : ready) {
     const slk_status st = admit(sv, j);
     if (st != SLK_OK) {
       deliver(sv, j, st);
@@ -607,6 +667,8 @@ slk_status slk_server_opts_default(slk_server_opts* o) {
   o->max_jobs = 64;
   o->passes_per_step = 2;
   o->memory_budget = 0;
+  o->builders = 3;
+  o->reserved = 0;
   return SLK_OK;
 }
 
@@ -619,6 +681,7 @@ slk_status slk_server_create(const slk_server_opts* opts, void* stream, slk_serv
   if (o.max_jobs < 1 || o.max_jobs > 1024) return fail(SLK_ERR_INVALID_ARG, "max_jobs must be in [1, 1024]");
   if (o.passes_per_step < 1) return fail(SLK_ERR_INVALID_ARG, "passes_per_step must be >= 1");
   if (o.memory_budget < 0) return fail(SLK_ERR_INVALID_ARG, "memory_budget must be >= 0");
+  if (o.builders < 1 || o.builders > 8) return fail(SLK_ERR_INVALID_ARG, "builders must be in [1, 8]");
   slk_server* sv = new slk_server();
   sv->o = o;
   sv->s = (hipStream_t)stream;
@@ -635,6 +698,13 @@ slk_status slk_server_create(const slk_server_opts* opts, void* stream, slk_serv
   if (hipHostMalloc(&sv->slots_host, sizeof(Slot) * o.max_jobs, hipHostMallocDefault) != hipSuccess)
     return bail(fail(SLK_ERR_OUT_OF_MEMORY, "server slot mirror"));
   for (int i = o.max_jobs - 1; i >= 0; --i) sv->free_slots.push_back(i);
+  for (int w = 0; w < o.builders; ++w) {
+    hipStream_t bs = nullptr;
+    if (hipStreamCreateWithFlags(&bs, hipStreamNonBlocking) != hipSuccess)
+      return bail(fail(SLK_ERR_DEVICE, "builder stream"));
+    sv->bss.push_back(bs);
+  }
+  for (int w = 0; w < o.builders; ++w) sv->builders.emplace_back(builder_loop, sv, w);
   *out = sv;
   return SLK_OK;
 }
@@ -667,12 +737,28 @@ slk_status slk_server_step(slk_server* sv, int64_t* done_host, int32_t cap, int3
   sv->finished.erase(sv->finished.begin(), sv->finished.begin() + nd);
   if (n_done_host) *n_done_host = nd;
   if (n_active_host) *n_active_host = (int32_t)sv->active.size();
-  if (n_queued_host) *n_queued_host = (int32_t)sv->queue.size();
+  if (n_queued_host) {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    *n_queued_host = (int32_t)(sv->queue.size() + sv->building);
+  }
   return SLK_OK;
 }
 
 void slk_server_destroy(slk_server* sv) {
   if (!sv) return;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->stop = true;
+  }
+  sv->cv_todo.notify_all();
+  for (auto& t : sv->builders)
+    if (t.joinable()) t.join();
+  for (Job* j : sv->to_build) delete j;
+  for (Job* j : sv->built) {
+    if (j->g) slk_graph_destroy(j->g);
+    delete j;
+  }
+  for (hipStream_t bs : sv->bss) (void)hipStreamDestroy(bs);
   for (Job* j : sv->active) {
     if (j->mem) (void)hipFreeAsync(j->mem, sv->s);
     if (j->g) slk_graph_destroy(j->g);
