@@ -279,21 +279,40 @@ slk_status check_row_ptr(const int32_t* rp, int64_t n, int64_t nnz, hipStream_t 
 // ------------------------------------------------------------------------------------------
 // graph helpers
 // ------------------------------------------------------------------------------------------
-void free_graph(slk_graph* g) {
+thread_local bool t_graph_pool = false;
+
+}  // namespace
+
+void set_graph_pool(bool on) { t_graph_pool = on; }
+bool graph_pool() { return t_graph_pool; }
+
+hipError_t graph_alloc(void** p, size_t bytes, hipStream_t s) {
+  return t_graph_pool ? hipMallocAsync(p, bytes, s) : hipMalloc(p, bytes);
+}
+
+void graph_free(void* p, bool pooled, hipStream_t s) {
+  if (!p) return;
+  if (pooled) (void)hipFreeAsync(p, s);
+  else (void)hipFree(p);
+}
+
+namespace {
+
+// Releases the arrays; pooled arrays are freed in the order of stream s.
+void free_graph(slk_graph* g, hipStream_t s) {
   if (!g) return;
-  (void)hipFree(g->row_ptr);
-  (void)hipFree(g->col_idx);
-  (void)hipFree(g->knn_idx);
-  (void)hipFree(g->knn_d2);
-  (void)hipFree(g->perm);
-  (void)hipFree(g->iperm);
-  (void)hipFree(g->heavy);
+  const bool pl = g->pooled != 0;
+  for (void* p : {(void*)g->row_ptr, (void*)g->col_idx, (void*)g->knn_idx, (void*)g->knn_d2, (void*)g->perm,
+                  (void*)g->iperm, (void*)g->heavy})
+    graph_free(p, pl, s);
   delete g;
 }
 
+
 struct GraphGuard {
   slk_graph* g;
-  ~GraphGuard() { free_graph(g); }
+  hipStream_t s;
+  ~GraphGuard() { free_graph(g, s); }
   slk_graph* release() {
     slk_graph* r = g;
     g = nullptr;
@@ -303,7 +322,7 @@ struct GraphGuard {
 
 // The rows of degree > kHeavyDeg (internal numbering), largest degree first, ties by row.
 slk_status build_heavy(slk_graph* g, hipStream_t s) {
-  (void)hipFree(g->heavy);
+  graph_free(g->heavy, g->pooled, s);
   g->heavy = nullptr;
   g->n_heavy = 0;
   const int64_t n = g->n;
@@ -315,7 +334,7 @@ slk_status build_heavy(slk_graph* g, hipStream_t s) {
     if (rp[i + 1] - rp[i] > kHeavyDeg) h.push_back((int32_t)i);
   std::stable_sort(h.begin(), h.end(), [&](int32_t u, int32_t v) { return rp[u + 1] - rp[u] > rp[v + 1] - rp[v]; });
   if (h.empty()) return SLK_OK;
-  SLK_HIP(hipMalloc(&g->heavy, sizeof(int32_t) * h.size()));
+  SLK_HIP(graph_alloc((void**)&g->heavy, sizeof(int32_t) * h.size(), s));
   SLK_HIP(hipMemcpyAsync(g->heavy, h.data(), sizeof(int32_t) * h.size(), hipMemcpyHostToDevice, s));
   SLK_HIP(hipStreamSynchronize(s));
   g->n_heavy = (int64_t)h.size();
@@ -352,27 +371,27 @@ slk_status bfs_reorder(slk_graph* g, hipStream_t s) {
   }
   std::vector<int32_t> inv(n);
   for (int64_t i = 0; i < n; ++i) inv[order[i]] = (int32_t)i;
-  SLK_HIP(hipMalloc(&g->perm, sizeof(int32_t) * n));
-  SLK_HIP(hipMalloc(&g->iperm, sizeof(int32_t) * n));
+  SLK_HIP(graph_alloc((void**)&g->perm, sizeof(int32_t) * n, s));
+  SLK_HIP(graph_alloc((void**)&g->iperm, sizeof(int32_t) * n, s));
   SLK_HIP(hipMemcpyAsync(g->perm, order.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
   SLK_HIP(hipMemcpyAsync(g->iperm, inv.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
   int32_t *nrp = nullptr, *nci = nullptr;
-  SLK_HIP(hipMalloc(&nrp, sizeof(int32_t) * (n + 1)));
-  if (hipMalloc(&nci, sizeof(int32_t) * (g->nnz + kColPad)) != hipSuccess) {
+  SLK_HIP(graph_alloc((void**)&nrp, sizeof(int32_t) * (n + 1), s));
+  if (graph_alloc((void**)&nci, sizeof(int32_t) * (g->nnz + kColPad), s) != hipSuccess) {
     (void)hipGetLastError();
-    (void)hipFree(nrp);
+    graph_free(nrp, g->pooled, s);
     return fail(SLK_ERR_OUT_OF_MEMORY, "relabelled CSR");
   }
   SLK_HIP(hipMemsetAsync(nci + g->nnz, 0, sizeof(int32_t) * kColPad, s));
   slk_status st = relabel_csr(n, g->row_ptr, g->col_idx, g->perm, g->iperm, nrp, nci, s);
   if (st == SLK_OK && hipStreamSynchronize(s) != hipSuccess) st = fail(SLK_ERR_DEVICE, "relabel");
   if (st != SLK_OK) {
-    (void)hipFree(nrp);
-    (void)hipFree(nci);
+    graph_free(nrp, g->pooled, s);
+    graph_free(nci, g->pooled, s);
     return st;
   }
-  (void)hipFree(g->row_ptr);
-  (void)hipFree(g->col_idx);
+  graph_free(g->row_ptr, g->pooled, s);
+  graph_free(g->col_idx, g->pooled, s);
   g->row_ptr = nrp;
   g->col_idx = nci;
   g->reordered = 1;
@@ -678,6 +697,8 @@ void set_heavy(EnergyArgs& e, const slk_graph* g) {
   e.heavy_deg = g->n_heavy ? kHeavyDeg : INT32_MAX;
 }
 
+void destroy_graph_on(slk_graph* g, hipStream_t s) { free_graph(g, s); }
+
 }  // namespace slk
 
 using namespace slk;
@@ -749,13 +770,14 @@ slk_status slk_build_knn(const float* x, int64_t n, int32_t d, const slk_knn_opt
   if ((int64_t)n * 2 * o.k >= (int64_t)INT32_MAX) return fail(SLK_ERR_INVALID_ARG, "n * 2k exceeds the CSR index range");
   hipStream_t s = (hipStream_t)stream;
   SLK_TRY(check_finite(x, n * (int64_t)d, s));
-  GraphGuard gg{new slk_graph()};
+  GraphGuard gg{new slk_graph(), s};
   slk_graph* g = gg.g;
+  g->pooled = graph_pool();
   SLK_HIP(hipGetDevice(&g->device));
   g->n = n;
   g->k = o.k;
-  SLK_HIP(hipMalloc(&g->knn_idx, sizeof(int32_t) * n * o.k));
-  SLK_HIP(hipMalloc(&g->knn_d2, sizeof(double) * n * o.k));
+  SLK_HIP(graph_alloc((void**)&g->knn_idx, sizeof(int32_t) * n * o.k, s));
+  SLK_HIP(graph_alloc((void**)&g->knn_d2, sizeof(double) * n * o.k, s));
   const int bf16 = o.prec == SLK_PREC_BF16;
   int method = o.method;
   if (method == SLK_KNN_AUTO) method = ((double)n * (double)n * (double)d <= 4.0e9) ? SLK_KNN_EXACT : SLK_KNN_MFMA;
@@ -783,15 +805,16 @@ slk_status slk_graph_from_knn(int64_t n, int32_t k, const int32_t* knn_idx, cons
   if ((int64_t)n * 2 * k >= (int64_t)INT32_MAX) return fail(SLK_ERR_INVALID_ARG, "n * 2k exceeds the CSR index range");
   hipStream_t s = (hipStream_t)stream;
   SLK_TRY(check_indices(knn_idx, n * (int64_t)k, n, s, "kNN indices must lie in [0, n)"));
-  GraphGuard gg{new slk_graph()};
+  GraphGuard gg{new slk_graph(), s};
   slk_graph* g = gg.g;
+  g->pooled = graph_pool();
   SLK_HIP(hipGetDevice(&g->device));
   g->n = n;
   g->k = k;
-  SLK_HIP(hipMalloc(&g->knn_idx, sizeof(int32_t) * n * k));
+  SLK_HIP(graph_alloc((void**)&g->knn_idx, sizeof(int32_t) * n * k, s));
   SLK_HIP(hipMemcpyAsync(g->knn_idx, knn_idx, sizeof(int32_t) * n * k, hipMemcpyDeviceToDevice, s));
   if (knn_d2) {
-    SLK_HIP(hipMalloc(&g->knn_d2, sizeof(double) * n * k));
+    SLK_HIP(graph_alloc((void**)&g->knn_d2, sizeof(double) * n * k, s));
     SLK_HIP(hipMemcpyAsync(g->knn_d2, knn_d2, sizeof(double) * n * k, hipMemcpyDeviceToDevice, s));
   }
   SLK_TRY(finish_from_knn(g, reorder, s));
@@ -810,15 +833,16 @@ slk_status slk_graph_from_csr(int64_t n, int64_t nnz, const int32_t* row_ptr, co
   hipStream_t s = (hipStream_t)stream;
   SLK_TRY(check_row_ptr(row_ptr, n, nnz, s));
   if (nnz > 0) SLK_TRY(check_indices(col_idx, nnz, n, s, "CSR columns must lie in [0, n)"));
-  GraphGuard gg{new slk_graph()};
+  GraphGuard gg{new slk_graph(), s};
   slk_graph* g = gg.g;
+  g->pooled = graph_pool();
   SLK_HIP(hipGetDevice(&g->device));
   g->n = n;
   g->k = 0;
   g->nnz = nnz;
   g->sigma2 = sigma2_hint > 0 ? sigma2_hint : 0.0;
-  SLK_HIP(hipMalloc(&g->row_ptr, sizeof(int32_t) * (n + 1)));
-  SLK_HIP(hipMalloc(&g->col_idx, sizeof(int32_t) * (nnz + kColPad)));
+  SLK_HIP(graph_alloc((void**)&g->row_ptr, sizeof(int32_t) * (n + 1), s));
+  SLK_HIP(graph_alloc((void**)&g->col_idx, sizeof(int32_t) * (nnz + kColPad), s));
   SLK_HIP(hipMemsetAsync(g->col_idx + nnz, 0, sizeof(int32_t) * kColPad, s));
   SLK_HIP(hipMemcpyAsync(g->row_ptr, row_ptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToDevice, s));
   if (nnz) SLK_HIP(hipMemcpyAsync(g->col_idx, col_idx, sizeof(int32_t) * nnz, hipMemcpyDeviceToDevice, s));
@@ -887,8 +911,11 @@ slk_status slk_graph_export(const slk_graph* g, int32_t* row_ptr, int32_t* col_i
 }
 
 void slk_graph_destroy(slk_graph* g) {
-  if (g) (void)hipDeviceSynchronize();
-  free_graph(g);
+  if (!g) return;
+  (void)hipDeviceSynchronize();
+  const bool pl = g->pooled != 0;
+  free_graph(g, nullptr);
+  if (pl) (void)hipStreamSynchronize(nullptr);
 }
 
 slk_status slk_unary(const float* x, int64_t n, int32_t d, int32_t L, const int32_t* modes_host, double sigma2,

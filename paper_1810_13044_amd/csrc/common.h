@@ -130,6 +130,7 @@ struct slk_graph {
   int32_t* iperm = nullptr;     // n: original index -> internal row (null = identity)
   int32_t* heavy = nullptr;     // internal rows of degree > kHeavyDeg, by degree descending
   int64_t n_heavy = 0;
+  int32_t pooled = 0;           // arrays from the stream-ordered pool (graphs built for the served form)
 };
 
 namespace slk {
@@ -320,6 +321,15 @@ slk_status knn_exact(const float* x, int64_t n, int32_t d, int32_t k, int32_t bf
 slk_status knn_mfma(const float* x, int64_t n, int32_t d, int32_t k, int32_t cand, int32_t bf16,
                     int32_t* out_idx, double* out_d2, int64_t* n_certified, int64_t* n_fallback, hipStream_t s,
                     const float* y = nullptr, int64_t m = 0);
+// Graph arrays.  A thread that enables the pooled mode (the served form's graph builders)
+// allocates them from the stream-ordered pool; such a graph is released with destroy_graph_on,
+// stream-ordered, without the device-wide synchronisation that freeing plain allocations implies.
+void set_graph_pool(bool on);
+bool graph_pool();
+hipError_t graph_alloc(void** p, size_t bytes, hipStream_t s);
+void graph_free(void* p, bool pooled, hipStream_t s);
+void destroy_graph_on(slk_graph* g, hipStream_t s);
+
 // Centred bf16 split of the points for MFMA Gram products (knn_mfma.hip): y = x - mean (FP64;
 // bf16 points: y = bf16(x), no centring), xh = bf16(y), xl = bf16(y - xh), dp columns (zero
 // padded), nrm = ||y||^2; mean receives the d column means (unused with bf16 points).

@@ -566,19 +566,19 @@ slk_status build_csr(int64_t n, int32_t k, const int32_t* knn_idx, int32_t** row
   hipLaunchKernelGGL(unique_count_kernel, dim3(g4), dim3(kBlock), 0, s, off, n, cols, uniq);
   SLK_LAUNCHED("unique_count_kernel");
   int32_t* rp = nullptr;
-  SLK_HIP(hipMalloc(&rp, sizeof(int32_t) * (n + 1)));
+  SLK_HIP(graph_alloc((void**)&rp, sizeof(int32_t) * (n + 1), s));
   slk_status st = exclusive_scan_i32(uniq, n, rp, s);
   if (st != SLK_OK) {
-    (void)hipFree(rp);
+    graph_free(rp, graph_pool(), s);
     return st;
   }
   int32_t nnz = 0;
   SLK_HIP(hipMemcpyAsync(&nnz, rp + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   SLK_HIP(hipStreamSynchronize(s));
   int32_t* ci = nullptr;
-  if (hipMalloc(&ci, sizeof(int32_t) * ((int64_t)nnz + kColPad)) != hipSuccess) {
+  if (graph_alloc((void**)&ci, sizeof(int32_t) * ((int64_t)nnz + kColPad), s) != hipSuccess) {
     (void)hipGetLastError();
-    (void)hipFree(rp);
+    graph_free(rp, graph_pool(), s);
     return fail(SLK_ERR_OUT_OF_MEMORY, "CSR columns");
   }
   SLK_HIP(hipMemsetAsync(ci + nnz, 0, sizeof(int32_t) * kColPad, s));

@@ -181,7 +181,7 @@ void deliver(slk_server* sv, Job* j, slk_status st) {
 
 void release(slk_server* sv, Job* j) {
   if (j->mem) (void)hipFreeAsync(j->mem, sv->s);
-  if (j->g) slk_graph_destroy(j->g);
+  if (j->g) destroy_graph_on(j->g, sv->s);
   if (j->slot >= 0) sv->free_slots.push_back(j->slot);
   sv->used -= std::min(sv->used, j->footprint);
   delete j;
@@ -191,6 +191,7 @@ void release(slk_server* sv, Job* j) {
 // job back complete (its stream synchronised) with the build's status.
 void builder_loop(slk_server* sv, int w) {
   (void)hipSetDevice(sv->device);
+  set_graph_pool(true);   // graphs freed stream-ordered when their jobs finish
   const hipStream_t bs = sv->bss[w];
   for (;;) {
     Job* j = nullptr;
@@ -755,13 +756,13 @@ void slk_server_destroy(slk_server* sv) {
     if (t.joinable()) t.join();
   for (Job* j : sv->to_build) delete j;
   for (Job* j : sv->built) {
-    if (j->g) slk_graph_destroy(j->g);
+    if (j->g) destroy_graph_on(j->g, sv->s);
     delete j;
   }
   for (hipStream_t bs : sv->bss) (void)hipStreamDestroy(bs);
   for (Job* j : sv->active) {
     if (j->mem) (void)hipFreeAsync(j->mem, sv->s);
-    if (j->g) slk_graph_destroy(j->g);
+    if (j->g) destroy_graph_on(j->g, sv->s);
     delete j;
   }
   for (Job* j : sv->queue) delete j;
