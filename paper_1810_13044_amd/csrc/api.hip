@@ -320,15 +320,13 @@ struct GraphGuard {
   }
 };
 
-// The rows of degree > kHeavyDeg (internal numbering), largest degree first, ties by row.
-slk_status build_heavy(slk_graph* g, hipStream_t s) {
+// The rows of degree > kHeavyDeg (internal numbering), largest degree first, ties by row, from a
+// host copy of row_ptr.
+slk_status heavy_from(slk_graph* g, const std::vector<int32_t>& rp, hipStream_t s) {
   graph_free(g->heavy, g->pooled, s);
   g->heavy = nullptr;
   g->n_heavy = 0;
   const int64_t n = g->n;
-  std::vector<int32_t> rp(n + 1);
-  SLK_HIP(hipMemcpyAsync(rp.data(), g->row_ptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, s));
-  SLK_HIP(hipStreamSynchronize(s));
   std::vector<int32_t> h;
   for (int64_t i = 0; i < n; ++i)
     if (rp[i + 1] - rp[i] > kHeavyDeg) h.push_back((int32_t)i);
@@ -339,6 +337,13 @@ slk_status build_heavy(slk_graph* g, hipStream_t s) {
   SLK_HIP(hipStreamSynchronize(s));
   g->n_heavy = (int64_t)h.size();
   return SLK_OK;
+}
+
+slk_status build_heavy(slk_graph* g, hipStream_t s) {
+  std::vector<int32_t> rp(g->n + 1);
+  SLK_HIP(hipMemcpyAsync(rp.data(), g->row_ptr, sizeof(int32_t) * (g->n + 1), hipMemcpyDeviceToHost, s));
+  SLK_HIP(hipStreamSynchronize(s));
+  return heavy_from(g, rp, s);
 }
 
 // Breadth-first order of the graph, component by component (roots in increasing index
@@ -398,25 +403,35 @@ slk_status bfs_reorder(slk_graph* g, hipStream_t s) {
   return SLK_OK;
 }
 
-// CSR, degree statistics, sigma^2 and the optional permutation for a graph whose kNN lists are set
+// CSR, degree statistics, sigma^2 and the optional permutation for a graph whose kNN lists are
+// set.  The entry count, sigma^2's sum, the degree range and row_ptr come back in one readback.
 slk_status finish_from_knn(slk_graph* g, int32_t reorder, hipStream_t s) {
-  SLK_TRY(build_csr(g->n, g->k, g->knn_idx, &g->row_ptr, &g->col_idx, &g->nnz, s));
-  if (g->knn_d2) {
-    Scratch sc(s);
-    double* sum;
-    SLK_TRY(sc.get(&sum, 1));
-    SLK_TRY(sum_f64(g->knn_d2, g->n * g->k, sum, s));
-    double h = 0.0;
-    SLK_HIP(hipMemcpyAsync(&h, sum, sizeof(double), hipMemcpyDeviceToHost, s));
-    SLK_HIP(hipStreamSynchronize(s));
-    g->sigma2 = h / ((double)g->n * (double)g->k);
+  struct Stats {
+    double d2sum;
+    int32_t nnz, mn, mx, pad;
+  };
+  Scratch sc(s);
+  Stats* st;
+  SLK_TRY(sc.get(&st, 1));
+  SLK_HIP(hipMemsetAsync(st, 0, sizeof(Stats), s));
+  SLK_TRY(build_csr(g->n, g->k, g->knn_idx, &g->row_ptr, &g->col_idx, &st->nnz, s));
+  if (g->knn_d2) SLK_TRY(sum_f64(g->knn_d2, g->n * g->k, &st->d2sum, s));
+  SLK_TRY(launch_degree_minmax(g->row_ptr, g->n, &st->mn, s));
+  std::vector<int32_t> rp(g->n + 1);
+  Stats h{};
+  SLK_HIP(hipMemcpyAsync(rp.data(), g->row_ptr, sizeof(int32_t) * (g->n + 1), hipMemcpyDeviceToHost, s));
+  SLK_HIP(hipMemcpyAsync(&h, st, sizeof(Stats), hipMemcpyDeviceToHost, s));
+  SLK_HIP(hipStreamSynchronize(s));
+  g->nnz = h.nnz;
+  if (g->knn_d2) g->sigma2 = h.d2sum / ((double)g->n * (double)g->k);
+  g->min_degree = h.mn;
+  g->max_degree = h.mx;
+  if (reorder) {
+    SLK_TRY(bfs_reorder(g, s));
+    SLK_TRY(build_heavy(g, s));
+  } else {
+    SLK_TRY(heavy_from(g, rp, s));
   }
-  if (reorder) SLK_TRY(bfs_reorder(g, s));
-  SLK_TRY(build_heavy(g, s));
-  int32_t mn, mx;
-  SLK_TRY(degree_stats(g->row_ptr, g->n, &mn, &mx, s));
-  g->min_degree = mn;
-  g->max_degree = mx;
   return SLK_OK;
 }
 

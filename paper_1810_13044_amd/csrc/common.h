@@ -336,12 +336,14 @@ void destroy_graph_on(slk_graph* g, hipStream_t s);
 slk_status split_points(const float* x, int64_t n, int32_t d, int32_t dp, int32_t bf16, double* mean, uint16_t* xh,
                         uint16_t* xl, float* nrm, hipStream_t s);
 slk_status build_csr(int64_t n, int32_t k, const int32_t* knn_idx, int32_t** row_ptr, int32_t** col_idx,
-                     int64_t* nnz, hipStream_t s);
+                     int32_t* nnz_dev, hipStream_t s);
 slk_status sum_f64(const double* v, int64_t count, double* out_dev, hipStream_t s);
 slk_status exclusive_scan_i32(const int32_t* in, int64_t count, int32_t* out, hipStream_t s);
-slk_status sort_rows(const int32_t* row_ptr, int64_t n, int32_t* col_idx, int32_t max_len, hipStream_t s);
+slk_status sort_rows(const int32_t* row_ptr, int64_t n, int32_t* col_idx, hipStream_t s);
 slk_status relabel_csr(int64_t n, const int32_t* row_ptr, const int32_t* col_idx, const int32_t* perm,
                        const int32_t* iperm, int32_t* new_row_ptr, int32_t* new_col_idx, hipStream_t s);
 slk_status degree_stats(const int32_t* row_ptr, int64_t n, int32_t* mn, int32_t* mx, hipStream_t s);
+// min and max row length into mm_dev[0], mm_dev[1] (stream-ordered, no readback)
+slk_status launch_degree_minmax(const int32_t* row_ptr, int64_t n, int32_t* mm_dev, hipStream_t s);
 
 }  // namespace slk

@@ -445,6 +445,14 @@ __global__ void init_minmax_kernel(int32_t* out) {
 
 __global__ void set_last_kernel(int32_t* arr, int64_t pos, const int32_t* total) { arr[pos] = *total; }
 
+// zero padding after the last column entry, and the entry count
+__global__ void csr_tail_kernel(const int32_t* __restrict__ rp, int64_t n, int32_t* __restrict__ ci,
+                                int32_t* __restrict__ nnz_out) {
+  const int32_t nnz = rp[n];
+  if (threadIdx.x < kColPad) ci[(int64_t)nnz + threadIdx.x] = 0;
+  if (threadIdx.x == 0 && nnz_out) *nnz_out = nnz;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------------------------------
@@ -489,18 +497,25 @@ slk_status sum_f64(const double* v, int64_t count, double* out_dev, hipStream_t 
   return SLK_OK;
 }
 
-slk_status sort_rows(const int32_t* row_ptr, int64_t n, int32_t* cols, int32_t max_len, hipStream_t s) {
+// Sorts every row of a CSR in place.  The longest row and the number of rows above 64 entries
+// come back to the host in one copy (one synchronisation).
+slk_status sort_rows(const int32_t* row_ptr, int64_t n, int32_t* cols, hipStream_t s) {
   Scratch sc(s);
-  int32_t *long_rows, *n_long;
+  int32_t *long_rows, *info;   // info: [0] rows above 64 entries, [1] INT32_MAX, [2] longest row
   SLK_TRY(sc.get(&long_rows, n));
-  SLK_TRY(sc.get(&n_long, 1));
-  SLK_HIP(hipMemsetAsync(n_long, 0, sizeof(int32_t), s));
+  SLK_TRY(sc.get(&info, 3));
+  SLK_HIP(hipMemsetAsync(info, 0, sizeof(int32_t), s));
+  hipLaunchKernelGGL(init_minmax_kernel, dim3(1), dim3(1), 0, s, info + 1);
+  const int mgrid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 1024));
+  hipLaunchKernelGGL(degree_minmax_kernel, dim3(mgrid), dim3(256), 0, s, row_ptr, n, info + 1);
+  SLK_LAUNCHED("degree_minmax_kernel");
   hipLaunchKernelGGL(sort_small_kernel, dim3((unsigned)((n + 3) / 4)), dim3(kBlock), 0, s, row_ptr, n, cols, long_rows,
-                     n_long);
+                     info);
   SLK_LAUNCHED("sort_small_kernel");
-  int32_t h_long = 0;
-  SLK_HIP(hipMemcpyAsync(&h_long, n_long, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  int32_t h[3] = {0, 0, 0};
+  SLK_HIP(hipMemcpyAsync(h, info, sizeof(h), hipMemcpyDeviceToHost, s));
   SLK_HIP(hipStreamSynchronize(s));
+  const int32_t h_long = h[0], max_len = h[2];
   if (h_long == 0) return SLK_OK;
   if (max_len <= kBigSort) {
     hipLaunchKernelGGL(sort_long_kernel, dim3(h_long), dim3(kBlock), 0, s, row_ptr, long_rows, cols,
@@ -509,9 +524,6 @@ slk_status sort_rows(const int32_t* row_ptr, int64_t n, int32_t* cols, int32_t m
     return SLK_OK;
   }
   // rows longer than the LDS tile: one launch per row with a global scratch area
-  std::vector<int32_t> ids(h_long);
-  SLK_HIP(hipMemcpyAsync(ids.data(), long_rows, sizeof(int32_t) * h_long, hipMemcpyDeviceToHost, s));
-  SLK_HIP(hipStreamSynchronize(s));
   int P = 1;
   while (P < max_len) P <<= 1;
   int32_t* scr;
@@ -520,6 +532,14 @@ slk_status sort_rows(const int32_t* row_ptr, int64_t n, int32_t* cols, int32_t m
     hipLaunchKernelGGL(sort_long_kernel, dim3(1), dim3(kBlock), 0, s, row_ptr, long_rows + i, cols, scr);
     SLK_LAUNCHED("sort_long_kernel");
   }
+  return SLK_OK;
+}
+
+slk_status launch_degree_minmax(const int32_t* row_ptr, int64_t n, int32_t* mm_dev, hipStream_t s) {
+  hipLaunchKernelGGL(init_minmax_kernel, dim3(1), dim3(1), 0, s, mm_dev);
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 1024));
+  hipLaunchKernelGGL(degree_minmax_kernel, dim3(grid), dim3(256), 0, s, row_ptr, n, mm_dev);
+  SLK_LAUNCHED("degree_minmax_kernel");
   return SLK_OK;
 }
 
@@ -539,29 +559,28 @@ slk_status degree_stats(const int32_t* row_ptr, int64_t n, int32_t* mn, int32_t*
   return SLK_OK;
 }
 
+// OR-symmetrised, sorted, duplicate-free CSR of the kNN lists.  The column array is allocated at
+// its upper bound 2 n k (+ pad), so nothing but the row sort reads back to the host; the number
+// of entries is left in *nnz_dev.
 slk_status build_csr(int64_t n, int32_t k, const int32_t* knn_idx, int32_t** row_ptr_out, int32_t** col_idx_out,
-                     int64_t* nnz_out, hipStream_t s) {
+                     int32_t* nnz_dev, hipStream_t s) {
   Scratch sc(s);
   int32_t *cap, *off, *fill, *cols, *uniq;
+  const int64_t bound = 2 * n * (int64_t)k;   // every kNN entry adds at most two
   SLK_TRY(sc.get(&cap, n));
   SLK_TRY(sc.get(&off, n + 1));
   SLK_TRY(sc.get(&fill, n));
   SLK_TRY(sc.get(&uniq, n));
+  SLK_TRY(sc.get(&cols, bound));
   SLK_HIP(hipMemsetAsync(cap, 0, sizeof(int32_t) * n, s));
   SLK_HIP(hipMemsetAsync(fill, 0, sizeof(int32_t) * n, s));
   const unsigned g1 = (unsigned)((n + 255) / 256);
   hipLaunchKernelGGL(count_edges_kernel, dim3(g1), dim3(256), 0, s, knn_idx, n, k, cap);
   SLK_LAUNCHED("count_edges_kernel");
   SLK_TRY(exclusive_scan_i32(cap, n, off, s));
-  int32_t total = 0;
-  SLK_HIP(hipMemcpyAsync(&total, off + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  SLK_HIP(hipStreamSynchronize(s));
-  SLK_TRY(sc.get(&cols, total));
   hipLaunchKernelGGL(fill_edges_kernel, dim3(g1), dim3(256), 0, s, knn_idx, n, k, off, fill, cols);
   SLK_LAUNCHED("fill_edges_kernel");
-  int32_t mn = 0, mx = 0;
-  SLK_TRY(degree_stats(off, n, &mn, &mx, s));
-  SLK_TRY(sort_rows(off, n, cols, mx, s));
+  SLK_TRY(sort_rows(off, n, cols, s));
   const unsigned g4 = (unsigned)((n + 3) / 4);
   hipLaunchKernelGGL(unique_count_kernel, dim3(g4), dim3(kBlock), 0, s, off, n, cols, uniq);
   SLK_LAUNCHED("unique_count_kernel");
@@ -572,22 +591,18 @@ slk_status build_csr(int64_t n, int32_t k, const int32_t* knn_idx, int32_t** row
     graph_free(rp, graph_pool(), s);
     return st;
   }
-  int32_t nnz = 0;
-  SLK_HIP(hipMemcpyAsync(&nnz, rp + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  SLK_HIP(hipStreamSynchronize(s));
   int32_t* ci = nullptr;
-  if (graph_alloc((void**)&ci, sizeof(int32_t) * ((int64_t)nnz + kColPad), s) != hipSuccess) {
+  if (graph_alloc((void**)&ci, sizeof(int32_t) * (bound + kColPad), s) != hipSuccess) {
     (void)hipGetLastError();
     graph_free(rp, graph_pool(), s);
     return fail(SLK_ERR_OUT_OF_MEMORY, "CSR columns");
   }
-  SLK_HIP(hipMemsetAsync(ci + nnz, 0, sizeof(int32_t) * kColPad, s));
   hipLaunchKernelGGL(unique_copy_kernel, dim3(g4), dim3(kBlock), 0, s, off, n, cols, rp, ci);
   SLK_LAUNCHED("unique_copy_kernel");
-  SLK_HIP(hipStreamSynchronize(s));
+  hipLaunchKernelGGL(csr_tail_kernel, dim3(1), dim3(64), 0, s, rp, n, ci, nnz_dev);
+  SLK_LAUNCHED("csr_tail_kernel");
   *row_ptr_out = rp;
   *col_idx_out = ci;
-  *nnz_out = nnz;
   return SLK_OK;
 }
 
@@ -602,9 +617,7 @@ slk_status relabel_csr(int64_t n, const int32_t* row_ptr, const int32_t* col_idx
   hipLaunchKernelGGL(relabel_copy_kernel, dim3((unsigned)((n + 3) / 4)), dim3(kBlock), 0, s, row_ptr, col_idx, n, perm,
                      iperm, new_row_ptr, new_col_idx);
   SLK_LAUNCHED("relabel_copy_kernel");
-  int32_t mn, mx;
-  SLK_TRY(degree_stats(new_row_ptr, n, &mn, &mx, s));
-  SLK_TRY(sort_rows(new_row_ptr, n, new_col_idx, mx, s));
+  SLK_TRY(sort_rows(new_row_ptr, n, new_col_idx, s));
   return SLK_OK;
 }
 
