@@ -103,9 +103,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   // staging of the point chunks: thread tid moves point tid / 4, 8 coordinates at (tid % 4) * 8
   const int spt = tid >> 2, spiece = (tid & 3) * 8;
   uint4 ph = make_uint4(0, 0, 0, 0), pl = ph;
-  auto fetch = [&](int64_t i) __attribute__((always_inline)) {
-    const int64_t t = i / nch;
-    const int c = (int)(i - t * nch);
+  // step positions (tile, chunk) and ring slots advance by counters: no divisions in the loop
+  auto fetch = [&](int64_t t, int c) __attribute__((always_inline)) {
     const int64_t pr = t * kPT + spt;
     ph = make_uint4(0, 0, 0, 0);
     pl = ph;
@@ -116,16 +115,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   };
   // RES == 0: the candidate operands of the next chunk are loaded one step ahead
   bf16x8 nbh[2], nbl[2];
-  auto yfetch = [&](int64_t i) __attribute__((always_inline)) {
-    const int c = (int)(i % nch);
+  auto yfetch = [&](int c) __attribute__((always_inline)) {
 #pragma unroll
     for (int s2 = 0; s2 < 2; ++s2) {
       nbh[s2] = gload8(yph + kDK * c + 16 * s2);
       nbl[s2] = SPLIT ? gload8(ypl + kDK * c + 16 * s2) : nbh[s2];
     }
   };
-  auto stash = [&](int64_t i) __attribute__((always_inline)) {
-    uint16_t* b = xst + (int)(i % 3) * 2 * kStage;
+  auto stash = [&](int slot) __attribute__((always_inline)) {
+    uint16_t* b = xst + slot * 2 * kStage;
     *reinterpret_cast<uint4*>(b + spt * kRow + spiece) = ph;
     if (SPLIT) *reinterpret_cast<uint4*>(b + kStage + spt * kRow + spiece) = pl;
   };
@@ -253,16 +251,26 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     }
   };
 
+  auto advance = [&](int64_t& tt, int& cc) __attribute__((always_inline)) {
+    if (++cc == nch) {
+      cc = 0;
+      ++tt;
+    }
+  };
   // prologue: chunk 0 staged, chunk 1 and tile 0's Z in flight
+  int64_t tf = 0;   // position of the next fetch
+  int cf = 0;
   if constexpr (RES == 0) yfetch(0);
-  fetch(0);
+  fetch(tf, cf);
   zfetch(0);
   lstash();
   stash(0);
-  if (steps > 1) fetch(1);
+  advance(tf, cf);
+  if (steps > 1) fetch(tf, cf);
+  int64_t t = 0;    // position of this step
+  int c = 0;
+  int slot = 0;     // ring slot of this step
   for (int64_t i = 0; i < steps; ++i) {
-    const int64_t t = i / nch;
-    const int c = (int)(i - t * nch);
     __syncthreads();
     if (c == 0) {
       zstash();
@@ -270,21 +278,23 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     } else if (c == 1) {
       lstash();
     }
-    if (i + 1 < steps) stash(i + 1);
+    const int nslot = slot == 2 ? 0 : slot + 1;
+    if (i + 1 < steps) stash(nslot);
     bf16x8 cbh[2], cbl[2];
     if constexpr (RES == 0) {
       cbh[0] = nbh[0];
       cbh[1] = nbh[1];
       cbl[0] = nbl[0];
       cbl[1] = nbl[1];
-      if (i + 1 < steps) yfetch(i + 1);
+      if (i + 1 < steps) yfetch(c + 1 == nch ? 0 : c + 1);
     }
-    if (i + 2 < steps) fetch(i + 2);
+    advance(tf, cf);
+    if (i + 2 < steps) fetch(tf, cf);
     if (c == 0) {
       acc[0] = f32x16{};
       acc[1] = f32x16{};
     }
-    const uint16_t* b = xst + (int)(i % 3) * 2 * kStage;
+    const uint16_t* b = xst + slot * 2 * kStage;
 #pragma unroll
     for (int s2 = 0; s2 < 2; ++s2) {
       bf16x8 yb, yl;
@@ -313,6 +323,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
       }
     }
     if (c == nch - 1) epilogue(t);
+    slot = nslot;
+    advance(t, c);
   }
 
   // per cluster: the best candidate of this wave, then of the work-group (the lists reuse the

@@ -259,10 +259,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   const int64_t steps = nkt * nch;
   uint4 ph[2], pl[2];
   bf16x8 sah[2][2], sal[2][2];  // query operands in flight (RES == 0)
-  auto fetch = [&](auto slot_c, int64_t i) __attribute__((always_inline)) {
+  // positions (key tile kt, chunk c) and ring slots are passed in: no divisions by the runtime
+  // chunk count in the loop
+  auto fetch = [&](auto slot_c, int64_t kt, int c) __attribute__((always_inline)) {
     constexpr int SL = decltype(slot_c)::value;
-    const int64_t kt = i / nch;
-    const int c = (int)(i - kt * nch);
     const int64_t kr = kt * kKT + skey;
     ph[SL] = make_uint4(0, 0, 0, 0);
     pl[SL] = ph[SL];
@@ -278,9 +278,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
       }
     }
   };
-  auto stash = [&](auto slot_c, int64_t i) __attribute__((always_inline)) {
+  auto stash = [&](auto slot_c, int ring) __attribute__((always_inline)) {
     constexpr int SL = decltype(slot_c)::value;
-    uint16_t* b = kst + (int)(i % 3) * 2 * kStage;
+    uint16_t* b = kst + ring * 2 * kStage;
     *reinterpret_cast<uint4*>(b + skey * kRow + spiece) = ph[SL];
     if (SPLIT) *reinterpret_cast<uint4*>(b + kStage + skey * kRow + spiece) = pl[SL];
     if constexpr (RES == 0) {
@@ -357,11 +357,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   };
   // step i: loads for step i + 2 go out, chunk i is multiplied from the ring, step i + 1's
   // registers land in the ring, one barrier
-  auto step = [&](auto slot_c, int64_t i, auto ai_c) __attribute__((always_inline)) {
+  auto step = [&](auto slot_c, int64_t i, int64_t kt, int c, int ring, int64_t kt2, int c2, auto ai_c)
+                  __attribute__((always_inline)) {
     constexpr int ai = decltype(ai_c)::value;
     constexpr int SL = decltype(slot_c)::value;
-    const int64_t kt = i / nch;
-    const int c = (int)(i - kt * nch);
     if (c == 0) {
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
@@ -369,8 +368,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
         nk[j] = key < n ? c1 * nrm[key] : 0.f;
       }
     }
-    if (i + 2 < steps) fetch(slot_c, i + 2);
-    const uint16_t* b = kst + (int)(i % 3) * 2 * kStage;
+    if (i + 2 < steps) fetch(slot_c, kt2, c2);
+    const uint16_t* b = kst + ring * 2 * kStage;
     // d <= 128 (RES > 0): one accumulator over all coordinates; else a fresh one per chunk,
     // added to the total (the error constant of the bound follows the same structure)
     f32x16* acc = RES > 0 ? tot : part;
@@ -399,28 +398,51 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
         for (int r = 0; r < 16; ++r) tot[j][r] = c == 0 ? part[j][r] : tot[j][r] + part[j][r];
     }
     if (c == nch - 1) epilogue(kt);
-    if (i + 1 < steps) stash(std::integral_constant<int, 1 - SL>{}, i + 1);
+    if (i + 1 < steps) stash(std::integral_constant<int, 1 - SL>{}, ring == 2 ? 0 : ring + 1);
     __syncthreads();
   };
   using S0 = std::integral_constant<int, 0>;
   using S1 = std::integral_constant<int, 1>;
-  fetch(S0{}, 0);
+  fetch(S0{}, 0, 0);
   stash(S0{}, 0);
-  if (steps > 1) fetch(S1{}, 1);
+  if (steps > 1) fetch(S1{}, nch > 1 ? 0 : 1, nch > 1 ? 1 : 0);
   __syncthreads();
   if constexpr (RES > 0) {
-    // two tiles per iteration, so every step's register slot and query chunk are static
+    // two tiles per iteration, so every step's register slot, query chunk and the chunk two
+    // steps ahead are static
     for (int64_t kt = 0; kt < nkt; kt += 2) {
       static_for<0, 2 * RES>([&](auto tc) __attribute__((always_inline)) {
         constexpr int u = decltype(tc)::value;   // step within the pair of tiles
         constexpr int t = u / RES, c = u % RES;
-        if (kt + t < nkt) step(std::integral_constant<int, u & 1>{}, (kt + t) * RES + c, std::integral_constant<int, c>{});
+        constexpr int t2 = (u + 2) / RES, c2 = (u + 2) % RES;
+        const int64_t i = (kt + t) * RES + c;
+        if (kt + t < nkt)
+          step(std::integral_constant<int, u & 1>{}, i, kt + t, c, (int)(i % 3), kt + t2, c2,
+               std::integral_constant<int, c>{});
       });
     }
   } else {
+    int64_t kt = 0, kt2 = 0;
+    int c = 0, c2 = 0, ring = 0;
+    auto advance = [&](int64_t& tt, int& cc) __attribute__((always_inline)) {
+      if (++cc == nch) {
+        cc = 0;
+        ++tt;
+      }
+    };
+    advance(kt2, c2);
+    advance(kt2, c2);   // two steps ahead
     for (int64_t i = 0; i < steps; i += 2) {
-      step(S0{}, i, S0{});
-      if (i + 1 < steps) step(S1{}, i + 1, S0{});
+      step(S0{}, i, kt, c, ring, kt2, c2, S0{});
+      advance(kt, c);
+      advance(kt2, c2);
+      ring = ring == 2 ? 0 : ring + 1;
+      if (i + 1 < steps) {
+        step(S1{}, i + 1, kt, c, ring, kt2, c2, S0{});
+        advance(kt, c);
+        advance(kt2, c2);
+        ring = ring == 2 ? 0 : ring + 1;
+      }
     }
   }
   for (int e = lane; e < 32 * C; e += 64) {
