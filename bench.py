@@ -109,6 +109,47 @@ def cpu_baseline(graph, A, Z0, lam, N, nnz, L, budget_s=20.0):
                       f"host has {os.cpu_count()} logical CPUs"}
 
 
+def cpu_other(slk, torch, X, K, knn_s, n_rows=8):
+    """Two more oracle timings on the host, each beside the GPU's: the exact kNN of sampled query rows
+    of the main workload (FP64 brute force, one thread; extrapolated to all rows and labelled so),
+    and the whole pipeline at the 2,000-point mixture (kNN, CSR, sigma^2 and the fit)."""
+    import gen
+    from oracle import slk as orc
+    N = X.shape[0]
+    X64 = np.asarray(X, dtype=np.float64)
+    rows = np.random.default_rng(11).choice(N, n_rows, replace=False)
+    t0 = time.perf_counter()
+    orc.knn(X64, K, rows=rows, block=n_rows)
+    per_row = (time.perf_counter() - t0) / n_rows
+    del X64
+    inst = gen.make("mixture-2k")
+    t0 = time.perf_counter()
+    idx, d2 = orc.knn(inst.X, inst.K, block=256)
+    rp, ci = orc.symmetrize(idx, inst.N)
+    orc.fit(inst.X, rp, ci, inst.init_modes, orc.sigma2_from_knn(d2), inst.lam)
+    small_cpu = time.perf_counter() - t0
+    x = torch.from_numpy(inst.X).to("cuda")
+    gpu = []
+    for _ in range(6):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = slk.Graph.build_knn(x, k=inst.K)
+        slk.fit(x, g, inst.init_modes, lam=inst.lam)
+        torch.cuda.synchronize()
+        gpu.append(time.perf_counter() - t0)
+        g.close()
+    small_gpu = float(np.median(gpu[1:]))
+    return {"knn": {"kind": "oracle", "cores": 1,
+                    "sample": f"exact kNN of {n_rows} seeded query rows against all N={N} points (FP64, one thread), "
+                              f"extrapolated to N rows",
+                    "s_per_row": round(per_row, 3), "extrapolated_s": round(per_row * N, 1),
+                    "gpu_build_s": round(knn_s, 3), "ratio": round(per_row * N / knn_s, 1)},
+            "mixture-2k": {"kind": "oracle", "cores": 1,
+                           "sample": "whole pipeline at N=2000 D=16 L=5: kNN, CSR, sigma^2 and the SLK-BO fit",
+                           "cpu_s": round(small_cpu, 4), "gpu_s_median": round(small_gpu, 5),
+                           "ratio": round(small_cpu / small_gpu, 1)}}
+
+
 SERVE_WORKLOAD = ("Poisson arrivals (seed 5); N log-uniform [500, 50000], D in {64,128,256}, L in [5,50], k=10, "
                   "lambda=1; Gaussian mixtures seeded per job (10000 + id)")
 
@@ -209,7 +250,9 @@ def serving_sweep(slk, torch, n_jobs, rates, max_jobs, passes):
     """The served form at several arrival rates, FP32 and BF16-X (points rounded to bf16 for the
     kNN and the unary term), each against one-at-a-time fits of the same precision.  The BF16-X
     results are compared with the FP32 ones on the FP32 problem: energy of the BF16-X labels and
-    modes on the FP32 graph with the FP64 unary term, and label agreement."""
+    modes on the FP32 graph with the FP64 unary term, and label agreement; and, in lock-step, the
+    first outer iteration of each job from the same modes and with the FP32 run's number of
+    z-updates, so that the gap measures the precision alone rather than a different local optimum."""
     insts, xs, arr1 = _materialise_jobs(torch, n_jobs)
     runs = []
     keep = {}
@@ -234,6 +277,22 @@ def serving_sweep(slk, torch, n_jobs, rates, max_jobs, passes):
         lower.append(e < e32)
         agree.append(float((o16["labels"] == o32["labels"]).float().mean()))
         del g
+    # lock-step: the first outer iteration from the same modes with the same number of z-updates,
+    # so the gap is the precision's own effect, not a different local optimum
+    lgaps, ltgaps = [], []
+    for j, (inst, x) in enumerate(zip(insts, xs)):
+        g32 = slk.Graph.build_knn(x, k=10)
+        g16 = slk.Graph.build_knn(x, k=10, prec="bf16")
+        a32 = slk.assign(x, g32, inst.init_modes, lam=inst.lam, trace=False)
+        npass = a32["result"]["inner_iters_last"]
+        a16 = slk.assign(x, g16, inst.init_modes, lam=inst.lam, trace=False, fixed_inner=npass, prec="bf16")
+        o32 = slk.energy(x, g32, a32["labels"], inst.init_modes, lam=inst.lam)
+        e32, cut32 = o32["energy_fp64"], o32["cut"]
+        e16 = slk.energy(x, g32, a16["labels"], inst.init_modes, lam=inst.lam)["energy_fp64"]
+        lgaps.append(abs(e16 - e32) / abs(e32))
+        ltgaps.append(abs(e16 - e32) / ((inst.lam * cut32 - e32) + inst.lam * cut32))
+        del g32, g16
+    lgaps, ltgaps = np.array(lgaps), np.array(ltgaps)
     gaps, tgaps, agree = np.array(gaps), np.array(tgaps), np.array(agree)
     bf16_vs_fp32 = {"energy_rel_gap_median": float(np.median(gaps)), "energy_rel_gap_p99": float(np.percentile(gaps, 99)),
                     "energy_rel_gap_max": float(gaps.max()), "jobs_within_1e-4": int((gaps <= 1e-4).sum()),
@@ -241,7 +300,12 @@ def serving_sweep(slk, torch, n_jobs, rates, max_jobs, passes):
                     "gap_over_term_magnitudes_p99": float(np.percentile(tgaps, 99)),
                     "bf16_lower_energy_fraction": float(np.mean(lower)),
                     "identical_labels_jobs": int((agree == 1.0).sum()),
-                    "label_agreement_median": float(np.median(agree)), "label_agreement_min": float(agree.min())}
+                    "label_agreement_median": float(np.median(agree)), "label_agreement_min": float(agree.min()),
+                    "lockstep_energy_rel_gap_median": float(np.median(lgaps)),
+                    "lockstep_energy_rel_gap_p99": float(np.percentile(lgaps, 99)),
+                    "lockstep_jobs_within_1e-4": int((lgaps <= 1e-4).sum()),
+                    "lockstep_gap_over_term_magnitudes_median": float(np.median(ltgaps)),
+                    "lockstep_gap_over_term_magnitudes_p99": float(np.percentile(ltgaps, 99))}
     log(f"[serve] bf16 vs fp32: {bf16_vs_fp32}")
     return {"jobs": n_jobs, "max_jobs": max_jobs, "passes_per_step": passes, "workload": SERVE_WORKLOAD,
             "runs": runs, "bf16_vs_fp32": bf16_vs_fp32}
@@ -491,8 +555,11 @@ def main():
     results = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    fit_ms = []
     for i in range(args.steps):
+        t1 = time.perf_counter()
         results.append(slk.fit(x, g, inst.init_modes, lam=lam)["result"])
+        fit_ms.append((time.perf_counter() - t1) * 1e3)     # each fit ends with its result on the host
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     n_iter, iter_ms = slk.timing_read("iter_kernel")
@@ -532,12 +599,14 @@ def main():
         serve = serving(slk, torch, args.serve_jobs, args.serve_rate, args.serve_slots, 2)
         log(f"[serve] {serve}")
 
-    cpu = None
+    cpu = cpu_more = None
     if not args.no_cpu_baseline:
         a, z0 = slk.unary(x, inst.init_modes, info["sigma2"])
         log("[bench] CPU oracle baseline ...")
         cpu = cpu_baseline(g, a, z0, lam, N, nnz, L)
         log(f"[bench] cpu baseline {cpu}")
+        cpu_more = cpu_other(slk, torch, inst.X, K, knn_s)
+        log(f"[bench] other oracle timings {cpu_more}")
 
     out = {
         "metric": METRIC,
@@ -571,6 +640,10 @@ def main():
             "launches": n_iter,
         },
         "cpu_baseline": cpu,
+        "cpu_oracle_other": cpu_more,
+        "fit_ms": {"median": round(float(np.median(fit_ms)), 3),
+                   "iqr": [round(float(np.percentile(fit_ms, 25)), 3), round(float(np.percentile(fit_ms, 75)), 3)],
+                   "min": round(float(min(fit_ms)), 3), "max": round(float(max(fit_ms)), 3)},
         "knn": {
             "method": "bf16x3 MFMA Gram candidates + FP64 re-rank + certificate",
             "build_s": round(knn_s, 3),

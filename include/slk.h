@@ -19,7 +19,9 @@
  *    complete when the stream reaches the call's end.
  *  - The caller owns every array it passes in; the library never frees caller memory.
  *    Graph handles are owned by the library until slk_graph_destroy.  Temporary device
- *    memory is taken from the stream-ordered allocator and returned before the call ends.
+ *    memory is taken from the library's stream-ordered pool on the current device and
+ *    returned to it before the call ends; the pool keeps up to 4 GiB of freed memory per
+ *    device for later calls (slk_pool_trim releases it).
  *  - Errors are returned as slk_status; no exception or abort crosses the ABI.  Arguments
  *    are validated before any launch; on a non-OK status the outputs are unspecified and
  *    slk_last_error() describes the failure (thread-local text, valid until the next call
@@ -435,6 +437,11 @@ slk_status slk_fit_batched(const slk_job* jobs, int32_t n_jobs, const slk_server
  */
 slk_status slk_timing_enable(int32_t on);
 slk_status slk_timing_read(const char* kernel, int64_t* launches_host, double* total_ms_host);
+
+/* Returns the freed memory held by the library's pool on the current device to the system.
+   Memory of calls still in flight on any stream stays allocated; the pool refills as later
+   calls run.  SLK_ERR_DEVICE if the pool cannot be created or trimmed. */
+slk_status slk_pool_trim(void);
 
 /* Text for the last non-OK status returned on this thread. */
 const char* slk_last_error(void);

@@ -463,6 +463,11 @@ def fit_batched(problems, max_jobs=64, passes_per_step=2, **common):
     return [r.outcome() for r in recs]
 
 
+def pool_trim() -> None:
+    """Return the freed memory held by the library's pool on the current device."""
+    _lib.check(_lib.load().slk_pool_trim())
+
+
 def timing_enable(on: bool = True) -> None:
     """Switch per-kernel HIP-event timing on or off (clears the totals)."""
     _lib.check(_lib.load().slk_timing_enable(int(bool(on))))

@@ -104,6 +104,8 @@ def load(path: str = LIB_PATH):
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = C.c_int
+    lib.slk_pool_trim.argtypes = []
+    lib.slk_pool_trim.restype = C.c_int
     lib.slk_timing_enable.argtypes = [I32]
     lib.slk_timing_enable.restype = C.c_int
     lib.slk_timing_read.argtypes = [C.c_char_p, C.POINTER(C.c_int64), C.POINTER(C.c_double)]

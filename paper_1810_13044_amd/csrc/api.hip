@@ -31,6 +31,50 @@ bool scratch_sync_alloc() {
   return v;
 }
 
+// Per-device stream-ordered pool for the calls' temporary buffers (and the served form's graphs).
+// Freed blocks stay in the pool up to kPoolKeepBytes, so that the next call on the device reuses
+// them instead of mapping fresh memory (the default pool returns everything at each synchronise).
+namespace {
+constexpr uint64_t kPoolKeepBytes = 4ull << 30;
+constexpr int kMaxDevices = 64;
+std::mutex g_pool_mu;
+hipMemPool_t g_pools[kMaxDevices] = {};
+}  // namespace
+
+hipError_t work_pool(hipMemPool_t* out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  if (!g_pools[dev]) {
+    hipMemPoolProps props{};
+    props.allocType = hipMemAllocationTypePinned;
+    props.handleTypes = hipMemHandleTypeNone;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = dev;
+    hipMemPool_t pool = nullptr;
+    e = hipMemPoolCreate(&pool, &props);
+    if (e != hipSuccess) return e;
+    uint64_t keep = kPoolKeepBytes;
+    e = hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    if (e != hipSuccess) {
+      (void)hipMemPoolDestroy(pool);
+      return e;
+    }
+    g_pools[dev] = pool;
+  }
+  *out = g_pools[dev];
+  return hipSuccess;
+}
+
+hipError_t pool_alloc(void** p, size_t bytes, hipStream_t s) {
+  hipMemPool_t pool = nullptr;
+  const hipError_t e = work_pool(&pool);
+  if (e != hipSuccess) return e;
+  return hipMallocFromPoolAsync(p, bytes, pool, s);
+}
+
 slk_status pinned(void** out, size_t bytes) {
   thread_local void* buf = nullptr;
   thread_local size_t cap = 0;
@@ -287,7 +331,7 @@ void set_graph_pool(bool on) { t_graph_pool = on; }
 bool graph_pool() { return t_graph_pool; }
 
 hipError_t graph_alloc(void** p, size_t bytes, hipStream_t s) {
-  return t_graph_pool ? hipMallocAsync(p, bytes, s) : hipMalloc(p, bytes);
+  return t_graph_pool ? pool_alloc(p, bytes, s) : hipMalloc(p, bytes);
 }
 
 void graph_free(void* p, bool pooled, hipStream_t s) {
@@ -726,6 +770,15 @@ extern "C" {
 const char* slk_last_error(void) { return g_err.c_str(); }
 
 const char* slk_version(void) { return "libslk 0.1 (gfx950)"; }
+
+slk_status slk_pool_trim(void) {
+  hipMemPool_t pool = nullptr;
+  if (work_pool(&pool) != hipSuccess || hipMemPoolTrimTo(pool, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(SLK_ERR_DEVICE, "slk_pool_trim: the device's memory pool");
+  }
+  return SLK_OK;
+}
 
 slk_status slk_timing_enable(int32_t on) {
   timing_flush();

@@ -56,6 +56,10 @@ slk_status fail(slk_status s, const std::string& msg);
 // stream-ordered device buffers owned by one call
 // ------------------------------------------------------------------------------------
 bool scratch_sync_alloc();
+// Stream-ordered allocation from the library's pool on the current device (freed blocks are
+// kept for reuse by later calls up to a fixed size; hipFreeAsync returns a block to it).
+hipError_t pool_alloc(void** p, size_t bytes, hipStream_t s);
+hipError_t work_pool(hipMemPool_t* out);
 struct Scratch {
   hipStream_t stream;
   void* ptrs[32];
@@ -74,10 +78,10 @@ struct Scratch {
     if (count == 0) count = 1;
     if (n >= 32) return fail(SLK_ERR_INVALID_ARG, "internal: too many scratch buffers");
     void* p = nullptr;
-    hipError_t e = sync_alloc ? hipMalloc(&p, count * sizeof(T)) : hipMallocAsync(&p, count * sizeof(T), stream);
+    hipError_t e = sync_alloc ? hipMalloc(&p, count * sizeof(T)) : pool_alloc(&p, count * sizeof(T), stream);
     if (e != hipSuccess) {
       (void)hipGetLastError();
-      return fail(SLK_ERR_OUT_OF_MEMORY, std::string("hipMallocAsync: ") + hipGetErrorString(e));
+      return fail(SLK_ERR_OUT_OF_MEMORY, std::string("device allocation: ") + hipGetErrorString(e));
     }
     ptrs[n++] = p;
     *out = static_cast<T*>(p);
