@@ -68,6 +68,94 @@ hipError_t work_pool(hipMemPool_t* out) {
   return hipSuccess;
 }
 
+struct Arena {
+  int device = 0;
+  std::vector<std::pair<char*, size_t>> chunks;  // (base, bytes)
+  size_t ci = 0, off = 0;                        // carving position
+  size_t demand = 0;                             // bytes carved by the current call
+};
+
+namespace {
+constexpr size_t kArenaAlign = 256;
+constexpr size_t kArenaMinChunk = 64ull << 20;
+std::mutex g_arena_mu;
+std::vector<Arena*> g_arenas_idle[kMaxDevices];
+}  // namespace
+
+Arena* arena_acquire() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    (void)hipGetLastError();
+    dev = 0;
+  }
+  Arena* a = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_arena_mu);
+    if (!g_arenas_idle[dev].empty()) {
+      a = g_arenas_idle[dev].back();
+      g_arenas_idle[dev].pop_back();
+    }
+  }
+  if (!a) {
+    a = new Arena;
+    a->device = dev;
+  }
+  a->ci = 0;
+  a->off = 0;
+  a->demand = 0;
+  return a;
+}
+
+hipError_t arena_carve(Arena* a, size_t bytes, void** out) {
+  bytes = (bytes + kArenaAlign - 1) / kArenaAlign * kArenaAlign;
+  a->demand += bytes;
+  for (; a->ci < a->chunks.size(); ++a->ci, a->off = 0) {
+    const auto& c = a->chunks[a->ci];
+    if (a->off + bytes <= c.second) {
+      *out = c.first + a->off;
+      a->off += bytes;
+      return hipSuccess;
+    }
+  }
+  void* p = nullptr;
+  const size_t cap = std::max(bytes, kArenaMinChunk);
+  const hipError_t e = hipMalloc(&p, cap);
+  if (e != hipSuccess) return e;
+  a->chunks.push_back({static_cast<char*>(p), cap});
+  a->ci = a->chunks.size() - 1;
+  a->off = bytes;
+  *out = p;
+  return hipSuccess;
+}
+
+// The caller has synchronised the stream the memory was used on.  A call that needed more than
+// one chunk leaves the arena with one chunk of its whole demand, so the next call carves from a
+// single block.
+void arena_release(Arena* a) {
+  if (a->chunks.size() > 1) {
+    for (auto& c : a->chunks) (void)hipFree(c.first);
+    a->chunks.clear();
+    void* p = nullptr;
+    if (hipMalloc(&p, a->demand) == hipSuccess) a->chunks.push_back({static_cast<char*>(p), a->demand});
+    else (void)hipGetLastError();
+  }
+  std::lock_guard<std::mutex> lk(g_arena_mu);
+  g_arenas_idle[a->device].push_back(a);
+}
+
+// Frees the idle arenas of one device (those of calls in progress stay).
+void arena_trim(int dev) {
+  std::vector<Arena*> idle;
+  {
+    std::lock_guard<std::mutex> lk(g_arena_mu);
+    idle.swap(g_arenas_idle[dev]);
+  }
+  for (Arena* a : idle) {
+    for (auto& c : a->chunks) (void)hipFree(c.first);
+    delete a;
+  }
+}
+
 hipError_t pool_alloc(void** p, size_t bytes, hipStream_t s) {
   hipMemPool_t pool = nullptr;
   const hipError_t e = work_pool(&pool);
@@ -164,9 +252,20 @@ void timing_retag_tail(const char* name, int count, const char* to) {
 // Host-visible mirror of the z-update loop state (two slots, alternating by pass) and one event
 // per slot, per device and thread.  The pass reduction stores the state there, so the driver
 // watches the loop without a copy on the stream.
+// The results of one outer iteration, written by its kernels straight into host-mapped memory:
+// the host reads them after one synchronise, with no copies on the stream.
+struct OuterHost {
+  double eout[2];        // unary sums: FP32 path, FP64 recheck
+  long long cut;
+  double bound;          // relaxed bound at the final pass's input
+  int32_t modes_next[256];
+};
+
 struct Watch {
   IterState* host = nullptr;
   IterState* dev = nullptr;
+  OuterHost* oh_host = nullptr;
+  OuterHost* oh_dev = nullptr;
   hipEvent_t ev[2] = {nullptr, nullptr};
 };
 
@@ -176,8 +275,10 @@ slk_status watch_for_device(Watch** out) {
   SLK_HIP(hipGetDevice(&dev));
   Watch& w = per_dev[dev];
   if (!w.host) {
+    // two IterState slots, then the OuterHost block (IterState's size keeps it 8-byte aligned)
     void* h = nullptr;
-    if (hipHostMalloc(&h, 2 * sizeof(IterState), hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) {
+    if (hipHostMalloc(&h, 2 * sizeof(IterState) + sizeof(OuterHost), hipHostMallocCoherent | hipHostMallocMapped) !=
+        hipSuccess) {
       (void)hipGetLastError();
       return fail(SLK_ERR_OUT_OF_MEMORY, "pinned loop-state mirror");
     }
@@ -194,6 +295,8 @@ slk_status watch_for_device(Watch** out) {
       }
     w.host = (IterState*)h;
     w.dev = (IterState*)d;
+    w.oh_host = reinterpret_cast<OuterHost*>(w.host + 2);
+    w.oh_dev = reinterpret_cast<OuterHost*>(w.dev + 2);
   }
   *out = &w;
   return SLK_OK;
@@ -496,6 +599,7 @@ struct Work {
   double* bound = nullptr;
   int32_t* modes = nullptr;
   int32_t* modes_next = nullptr;
+  int32_t* moved = nullptr;     // L flags: modes_next[l] != modes[l]
   const float* mvec = nullptr;  // SLK-MS: L x d mode vectors used in place of the points at `modes`
   double* epart_un = nullptr;
   double* epart_un64 = nullptr;
@@ -535,6 +639,7 @@ slk_status alloc_work(Scratch& sc, const slk_graph* g, int32_t L, int trace_cap,
   SLK_TRY(sc.get(&w.bound, 1));
   SLK_TRY(sc.get(&w.modes, L));
   SLK_TRY(sc.get(&w.modes_next, L));
+  SLK_TRY(sc.get(&w.moved, L));
   SLK_TRY(sc.get(&w.epart_un, w.egrid));
   SLK_TRY(sc.get(&w.epart_un64, w.egrid));
   SLK_TRY(sc.get(&w.epart_cut, w.egrid));
@@ -549,6 +654,7 @@ struct OuterOut {
   int converged = 0;
   double energy = 0, energy64 = 0, bound = 0;
   long long cut = 0;
+  int32_t modes_next[256] = {};  // the byproduct modes (also in Work::modes_next on the device)
 };
 
 IterArgs make_iter(const slk_graph* g, const Work& w, int64_t n, int32_t L, const slk_params& p) {
@@ -572,10 +678,14 @@ IterArgs make_iter(const slk_graph* g, const Work& w, int64_t n, int32_t L, cons
   return a;
 }
 
-// One outer iteration with the modes in w.modes.  Device outputs: z_user / labels_user (may
-// be null), w.modes_next, w.trace.  Host outputs in *o.
+// One outer iteration with the modes in w.modes.  Device outputs: labels_user (may be null),
+// w.modes_next, w.trace, and Z of the last z-update in w.Z[o->passes & 1] (internal order; the
+// final pass recomputes that z-update for the labels and modes, with the same result, so the
+// caller's Z is scattered from there once, after the last outer iteration).  Host outputs in *o;
+// with energy_always = false the energy, cut and their o-> fields are left stale when a mode
+// moved (the caller then runs another outer iteration and never reports them).
 slk_status run_outer(const float* x, int64_t n, int32_t d, const slk_graph* g, int32_t L, const slk_params& p,
-                     double sigma2, int trace_cap, int want_fp64, hipStream_t s, Work& w, float* z_user,
+                     double sigma2, int trace_cap, int want_fp64, bool energy_always, hipStream_t s, Work& w,
                      int32_t* labels_user, OuterOut* o) {
   {
     KernelTimer kt("unary_kernel", s);
@@ -589,6 +699,8 @@ slk_status run_outer(const float* x, int64_t n, int32_t d, const slk_graph* g, i
   IterArgs a = make_iter(g, w, n, L, p);
   IterState hs{};
   int launched = 0;
+  Watch* wt = nullptr;
+  SLK_TRY(watch_for_device(&wt));
   if (!check) {
     for (; launched < p.fixed_inner; ++launched) {
       a.Zin = w.Z[launched & 1];
@@ -602,8 +714,6 @@ slk_status run_outer(const float* x, int64_t n, int32_t d, const slk_graph* g, i
     // One pass ahead: pass k+1 is queued before the host looks at the state after pass k, so
     // the device never waits for the host; once the bound has settled, the one pass already
     // queued returns at once.
-    Watch* wt = nullptr;
-    SLK_TRY(watch_for_device(&wt));
     auto enqueue = [&](int k) -> slk_status {
       a.Zin = w.Z[k & 1];
       a.Zout = w.Z[(k + 1) & 1];
@@ -614,24 +724,21 @@ slk_status run_outer(const float* x, int64_t n, int32_t d, const slk_graph* g, i
     };
     SLK_TRY(enqueue(0));
     launched = 1;
+    int last = 0;
     for (int k = 0; k < launched; ++k) {
       if (launched < p.max_inner) {
         SLK_TRY(enqueue(launched));
         ++launched;
       }
       SLK_HIP(hipEventSynchronize(wt->ev[k & 1]));
+      last = k;
       const volatile IterState* m = wt->host + (k & 1);
       if (m->done) break;
     }
-    void* pin;
-    SLK_TRY(pinned(&pin, sizeof(IterState)));
-    SLK_HIP(hipMemcpyAsync(pin, w.state, sizeof(IterState), hipMemcpyDeviceToHost, s));
-    SLK_HIP(hipStreamSynchronize(s));
-    memcpy(&hs, pin, sizeof(IterState));
-    if (timing_on()) {
-      timing_retag_tail("iter_kernel", launched - hs.pass, "iter_kernel_after_stop");
-      timing_flush();
-    }
+    // The state after pass `last` is the final one: either it is done, and the passes queued
+    // after it are no-ops that leave the state alone, or it is the last pass launched.
+    memcpy(&hs, (const void*)(wt->host + (last & 1)), sizeof(IterState));
+    if (timing_on()) timing_retag_tail("iter_kernel", launched - hs.pass, "iter_kernel_after_stop");
   }
   if (hs.numeric) return fail(SLK_ERR_NUMERIC, "relaxed bound is not finite");
   const int passes = hs.pass;
@@ -646,9 +753,9 @@ slk_status run_outer(const float* x, int64_t n, int32_t d, const slk_graph* g, i
   f.it.state = w.state2;
   f.it.partial = w.partial2;
   f.it.trace = nullptr;
-  f.it.bound_out = w.bound;
+  f.it.bound_out = &wt->oh_dev->bound;
   f.perm = g->perm;
-  f.z_user = z_user;
+  f.z_user = nullptr;
   f.labels_int = w.labels_int;
   f.labels_user = labels_user;
   f.cand_v = w.cand_v;
@@ -656,7 +763,8 @@ slk_status run_outer(const float* x, int64_t n, int32_t d, const slk_graph* g, i
   SLK_TRY(launch_final(f, w.grid, s));
   {
     KernelTimer kt("mode_reduce_kernel", s);
-    SLK_TRY(launch_mode_reduce(w.cand_v, w.cand_i, w.grid, L, w.modes_next, s));
+    SLK_TRY(launch_mode_reduce(w.cand_v, w.cand_i, w.grid, L, w.modes_next, s, wt->oh_dev->modes_next,
+                               energy_always ? nullptr : w.modes, energy_always ? nullptr : w.moved));
   }
   EnergyArgs e{};
   set_heavy(e, g);
@@ -676,21 +784,19 @@ slk_status run_outer(const float* x, int64_t n, int32_t d, const slk_graph* g, i
   e.part_un = w.epart_un;
   e.part_un64 = w.epart_un64;
   e.part_cut = w.epart_cut;
-  e.out = w.eout;
-  e.out_cut = w.eout_cut;
+  e.out = wt->oh_dev->eout;
+  e.out_cut = &wt->oh_dev->cut;
+  e.moved = energy_always ? nullptr : w.moved;
   SLK_TRY(launch_energy(e, w.egrid, s));
-  double eo[2];
-  long long cut = 0;
-  double bnd = 0;
-  SLK_HIP(hipMemcpyAsync(eo, w.eout, sizeof(eo), hipMemcpyDeviceToHost, s));
-  SLK_HIP(hipMemcpyAsync(&cut, w.eout_cut, sizeof(cut), hipMemcpyDeviceToHost, s));
-  SLK_HIP(hipMemcpyAsync(&bnd, w.bound, sizeof(bnd), hipMemcpyDeviceToHost, s));
   SLK_HIP(hipStreamSynchronize(s));
   if (timing_on()) timing_flush();
+  const volatile OuterHost* oh = wt->oh_host;
+  const long long cut = oh->cut;
   o->cut = cut;
-  o->energy = -eo[0] + p.lambda * (double)cut;
-  o->energy64 = want_fp64 ? -eo[1] + p.lambda * (double)cut : o->energy;
-  o->bound = bnd;
+  o->energy = -oh->eout[0] + p.lambda * (double)cut;
+  o->energy64 = want_fp64 ? -oh->eout[1] + p.lambda * (double)cut : o->energy;
+  o->bound = oh->bound;
+  for (int l = 0; l < L; ++l) o->modes_next[l] = oh->modes_next[l];
   return SLK_OK;
 }
 
@@ -772,6 +878,8 @@ const char* slk_last_error(void) { return g_err.c_str(); }
 const char* slk_version(void) { return "libslk 0.1 (gfx950)"; }
 
 slk_status slk_pool_trim(void) {
+  int dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < kMaxDevices) arena_trim(dev);
   hipMemPool_t pool = nullptr;
   if (work_pool(&pool) != hipSuccess || hipMemPoolTrimTo(pool, 0) != hipSuccess) {
     (void)hipGetLastError();
@@ -1075,7 +1183,7 @@ static slk_status assign_or_fit(bool fit, const float* x, int64_t n, int32_t d, 
   if (trace_cap < 0) return fail(SLK_ERR_INVALID_ARG, "trace_cap must be >= 0");
   hipStream_t s = (hipStream_t)stream;
   const int cap = std::max(trace_cap, std::max(p.max_inner, p.fixed_inner));
-  Scratch sc(s);
+  Scratch sc(s, true);  // the call synchronises before it returns
   Work w;
   SLK_TRY(alloc_work(sc, g, L, cap, w));
   SLK_TRY(prepare_col_off(g, L, sc, &w.col_off));
@@ -1085,9 +1193,8 @@ static slk_status assign_or_fit(bool fit, const float* x, int64_t n, int32_t d, 
   OuterOut o;
   const int outer_cap = fit ? p.max_outer : 1;
   for (int t = 0; t < outer_cap; ++t) {
-    SLK_TRY(run_outer(x, n, d, g, L, p, sigma2, cap, 0, s, w, z_out, labels_out, &o));
-    SLK_HIP(hipMemcpyAsync(nxt.data(), w.modes_next, sizeof(int32_t) * L, hipMemcpyDeviceToHost, s));
-    SLK_HIP(hipStreamSynchronize(s));
+    SLK_TRY(run_outer(x, n, d, g, L, p, sigma2, cap, 0, !fit || t + 1 == outer_cap, s, w, labels_out, &o));
+    nxt.assign(o.modes_next, o.modes_next + L);
     r.outer_iters = t + 1;
     r.inner_iters_total += o.passes;
     r.inner_iters_last = o.passes;
@@ -1106,8 +1213,9 @@ static slk_status assign_or_fit(bool fit, const float* x, int64_t n, int32_t d, 
     // out of outer iterations: w.modes keeps the modes that produced the last labels
     if (t + 1 == outer_cap) break;
     cur = nxt;
-    SLK_HIP(hipMemcpyAsync(w.modes, w.modes_next, sizeof(int32_t) * L, hipMemcpyDeviceToDevice, s));
+    std::swap(w.modes, w.modes_next);  // the next outer iteration runs on the byproduct modes
   }
+  SLK_TRY(launch_scatter_rows(w.Z[o.passes & 1], g->perm, n, L, ldz_for(L), z_out, s));
   // FP64 recheck of the final energy: the unary term recomputed from X in FP64 at the last
   // labels and the modes that produced them (both still resident in the work buffers)
   {
@@ -1181,7 +1289,7 @@ slk_status slk_fit_ms(const float* x, int64_t n, int32_t d, const slk_graph* g, 
   if (!(sigma2 > 0.0)) return fail(SLK_ERR_INVALID_ARG, "sigma2 unknown: pass params.sigma2 > 0");
   hipStream_t s = (hipStream_t)stream;
   const int cap = std::max(p.max_inner, p.fixed_inner);
-  Scratch sc(s);
+  Scratch sc(s, true);  // the call synchronises before it returns
   Work w;
   SLK_TRY(alloc_work(sc, g, L, cap, w));
   SLK_TRY(prepare_col_off(g, L, sc, &w.col_off));
@@ -1198,7 +1306,7 @@ slk_status slk_fit_ms(const float* x, int64_t n, int32_t d, const slk_graph* g, 
   SLK_HIP(hipMemsetAsync(w.modes, 0, sizeof(int32_t) * L, s));  // unused: the modes are the vectors
   for (int t = 0; t < p.max_outer; ++t) {
     w.mvec = cur;
-    SLK_TRY(run_outer(x, n, d, g, L, p, sigma2, cap, 0, s, w, z_out, labels_out, &o));
+    SLK_TRY(run_outer(x, n, d, g, L, p, sigma2, cap, 0, true, s, w, labels_out, &o));
     r.outer_iters = t + 1;
     r.inner_iters_total += o.passes;
     r.inner_iters_last = o.passes;
@@ -1235,6 +1343,7 @@ slk_status slk_fit_ms(const float* x, int64_t n, int32_t d, const slk_graph* g, 
     if (t + 1 == p.max_outer) break;
     std::swap(cur, nxt);
   }
+  SLK_TRY(launch_scatter_rows(w.Z[o.passes & 1], g->perm, n, L, ldz_for(L), z_out, s));
   // FP64 recheck of the final energy at the last labels and the modes that produced them
   {
     EnergyArgs e{};
@@ -1283,7 +1392,7 @@ slk_status slk_energy(const float* x, int64_t n, int32_t d, const slk_graph* g, 
   if (!(s2 > 0.0)) return fail(SLK_ERR_INVALID_ARG, "sigma2 unknown: pass sigma2 > 0");
   hipStream_t s = (hipStream_t)stream;
   SLK_TRY(check_labels(labels, n, L, s));
-  Scratch sc(s);
+  Scratch sc(s, true);  // the call synchronises before it returns
   Work w;
   SLK_TRY(alloc_work(sc, g, L, 1, w));
   if (z) SLK_TRY(prepare_col_off(g, L, sc, &w.col_off));

@@ -60,13 +60,33 @@ bool scratch_sync_alloc();
 // kept for reuse by later calls up to a fixed size; hipFreeAsync returns a block to it).
 hipError_t pool_alloc(void** p, size_t bytes, hipStream_t s);
 hipError_t work_pool(hipMemPool_t* out);
+// Work memory that outlives the calls: a block per concurrent user, taken at the start of a
+// call and handed back at its end, grown (and consolidated into one allocation) when a call
+// needs more.  Allocating and freeing a fit's buffers on the stream costs milliseconds of host
+// time per call; carving them from a kept block costs nothing.
+struct Arena;
+Arena* arena_acquire();
+hipError_t arena_carve(Arena* a, size_t bytes, void** out);
+void arena_release(Arena* a);
+
+// Temporary device buffers of one call.  Default: stream-ordered allocations from the pool,
+// freed stream-ordered when the Scratch goes out of scope.  Cached (for calls that
+// synchronise their stream before returning): carved from an arena; the destructor
+// synchronises the stream (so that nothing in flight still uses the memory, error paths
+// included) before the arena goes back.
 struct Scratch {
   hipStream_t stream;
   void* ptrs[32];
   int n = 0;
-  explicit Scratch(hipStream_t s) : stream(s) {}
+  Arena* arena = nullptr;
+  explicit Scratch(hipStream_t s, bool cached = false) : stream(s), arena(cached ? arena_acquire() : nullptr) {}
   bool sync_alloc = scratch_sync_alloc();
   ~Scratch() {
+    if (arena) {
+      (void)hipStreamSynchronize(stream);
+      arena_release(arena);
+      return;
+    }
     for (int i = 0; i < n; ++i) {
       if (sync_alloc) (void)hipFree(ptrs[i]);
       else (void)hipFreeAsync(ptrs[i], stream);
@@ -78,7 +98,8 @@ struct Scratch {
     if (count == 0) count = 1;
     if (n >= 32) return fail(SLK_ERR_INVALID_ARG, "internal: too many scratch buffers");
     void* p = nullptr;
-    hipError_t e = sync_alloc ? hipMalloc(&p, count * sizeof(T)) : pool_alloc(&p, count * sizeof(T), stream);
+    hipError_t e = arena ? arena_carve(arena, count * sizeof(T), &p)
+                   : sync_alloc ? hipMalloc(&p, count * sizeof(T)) : pool_alloc(&p, count * sizeof(T), stream);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       return fail(SLK_ERR_OUT_OF_MEMORY, std::string("device allocation: ") + hipGetErrorString(e));
@@ -266,8 +287,11 @@ slk_status launch_mode_reduce_packed(const ModeJob* jobs, const int32_t* start, 
 int iter_grid(int64_t n, int32_t L, int64_t n_heavy);
 slk_status launch_iter(const IterArgs& a, int grid, hipStream_t s);
 slk_status launch_final(const FinalArgs& a, int grid, hipStream_t s);
+// modes_out: L int32 on the device; mirror (may be null): a second copy, e.g. host-mapped memory;
+// cur and moved (both null or both set): moved[l] = (modes_out[l] != cur[l]).
 slk_status launch_mode_reduce(const float* cand_v, const int32_t* cand_i, int grid, int32_t L, int32_t* modes_out,
-                              hipStream_t s);
+                              hipStream_t s, int32_t* mirror = nullptr, const int32_t* cur = nullptr,
+                              int32_t* moved = nullptr);
 struct EnergyArgs {
   const int32_t* row_ptr;
   const int32_t* col_idx;
@@ -289,6 +313,10 @@ struct EnergyArgs {
   int32_t n_heavy;
   int32_t hblocks;
   int32_t heavy_deg;
+  // L flags from the mode reduction (launch_energy only): if any mode moved, another outer
+  // iteration follows and this energy is never reported, so both kernels return at once.
+  // Null: always compute.
+  const int32_t* moved;
 };
 // Grids include the heavy-row work-groups in front (n_heavy = 0: none).
 int energy_grid(int64_t n, int64_t n_heavy);

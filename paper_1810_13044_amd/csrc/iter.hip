@@ -335,7 +335,8 @@ __global__ __launch_bounds__(kBlock) void final_kernel(FinalArgs f) {
       } else if (l == jt) {
         v = (o.m - m2) - logf(S2);      // log z/(1-z) for the top entry, no underflow
       } else {
-        v = (o.s[e] - o.m) - log1pf(T - o.e[e]);
+        const float ub = o.s[e] - o.m;  // v <= ub (see final_row)
+        v = ub < bv[e] ? -INFINITY : ub - log1pf(T - o.e[e]);
       }
       if (v > bv[e] || (v == bv[e] && (int)orow < bi[e])) {
         bv[e] = v;
@@ -442,6 +443,7 @@ __device__ __forceinline__ void gargmax4(float& v, int& i) {
 __device__ __forceinline__ float f4(const float4& v, int e) { return e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w; }
 
 typedef float vf4 __attribute__((ext_vector_type(4)));  // native vector for the non-temporal builtins
+typedef float vf2 __attribute__((ext_vector_type(2)));
 
 struct Row4 {
   float s[4], e[4], z[4];
@@ -755,7 +757,10 @@ __device__ __forceinline__ void final_row(const FinalArgs& f, int64_t row, bool 
     } else if (l == jt) {
       v = (o.m - m2) - logf(S2);      // log z/(1-z) for the top entry, no underflow
     } else {
-      v = (o.s[e] - o.m) - log1pf(T - o.e[e]);
+      // T >= e exactly (a rounded sum of nonnegative terms is at least each term), so the log1p
+      // is >= 0 and v <= s - m: an entry below this lane's best candidate cannot win or tie
+      const float ub = o.s[e] - o.m;
+      v = ub < bv[e] ? -INFINITY : ub - log1pf(T - o.e[e]);
     }
     if (v > bv[e] || (v == bv[e] && (int)orow < bi[e])) {
       bv[e] = v;
@@ -859,7 +864,8 @@ __global__ __launch_bounds__(kBlock) void final4_packed(const FinalArgs* __restr
 }
 
 __device__ __forceinline__ void mode_reduce_block(const float* __restrict__ cv, const int32_t* __restrict__ ci, int grid,
-                                                  int32_t* __restrict__ modes, int l) {
+                                                  int32_t* __restrict__ modes, int l, int32_t* mirror = nullptr,
+                                                  const int32_t* cur = nullptr, int32_t* moved = nullptr) {
   const int tid = threadIdx.x;
   float v = -INFINITY;
   int i = INT32_MAX;
@@ -885,12 +891,18 @@ __device__ __forceinline__ void mode_reduce_block(const float* __restrict__ cv, 
     }
     __syncthreads();
   }
-  if (tid == 0) modes[l] = si[0] == INT32_MAX ? 0 : si[0];
+  if (tid == 0) {
+    const int32_t m = si[0] == INT32_MAX ? 0 : si[0];
+    modes[l] = m;
+    if (mirror) mirror[l] = m;
+    if (moved) moved[l] = m != cur[l];
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void mode_reduce_kernel(const float* __restrict__ cv, const int32_t* __restrict__ ci,
-                                                             int grid, int L, int32_t* __restrict__ modes) {
-  mode_reduce_block(cv, ci, grid, modes, blockIdx.x);
+                                                             int grid, int L, int32_t* __restrict__ modes,
+                                                             int32_t* mirror, const int32_t* cur, int32_t* moved) {
+  mode_reduce_block(cv, ci, grid, modes, blockIdx.x, mirror, cur, moved);
 }
 
 // one block per (job, cluster): start[j] = first block of job j, L_j blocks each
@@ -1018,7 +1030,16 @@ __device__ __forceinline__ void energy_block(const EnergyArgs& e, int bid) {
   }
 }
 
+// True when a mode moved (the energy of this outer iteration is not needed).
+__device__ __forceinline__ bool energy_skipped(const int32_t* moved, int L) {
+  if (!moved) return false;
+  for (int l = 0; l < L; ++l)
+    if (moved[l]) return true;
+  return false;
+}
+
 __global__ __launch_bounds__(kBlock) void energy_kernel(EnergyArgs e) {
+  if (energy_skipped(e.moved, e.L)) return;
   energy_block(e, blockIdx.x);
 }
 
@@ -1064,7 +1085,9 @@ __device__ __forceinline__ void energy_reduce_block(const double* __restrict__ p
 __global__ __launch_bounds__(kBlock) void energy_reduce_kernel(const double* __restrict__ p_un,
                                                                const double* __restrict__ p_un64,
                                                                const long long* __restrict__ p_cut, int nparts,
-                                                               double* out, long long* out_cut) {
+                                                               double* out, long long* out_cut,
+                                                               const int32_t* moved, int L) {
+  if (energy_skipped(moved, L)) return;
   energy_reduce_block(p_un, p_un64, p_cut, nparts, out, out_cut);
 }
 
@@ -1151,6 +1174,29 @@ __global__ void scatter_rows_kernel(const float* __restrict__ src, const int32_t
   const int64_t r = i / L, l = i % L;
   const int64_t dr = perm ? perm[r] : r;
   dst[dr * L + l] = src[r * ldz + l];
+}
+
+// Internal rows of 4-float slices (ldz = 4 * L4) to the caller's layout: one thread per slice,
+// 16-byte loads; two 8-byte stores where the destination row starts 8-byte aligned (L or the
+// row index even) and the slice is whole, else one store per entry.
+__global__ void scatter_rows4_kernel(const float* __restrict__ src, const int32_t* __restrict__ perm, uint32_t n,
+                                     int L, uint32_t L4, float* __restrict__ dst) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * L4) return;
+  const uint32_t r = i / L4, j = i - r * L4;
+  const vf4 v = __builtin_nontemporal_load(reinterpret_cast<const vf4*>(src) + i);
+  const int64_t dr = perm ? perm[r] : r;
+  float* d = dst + dr * L + 4 * j;
+  const int l0 = 4 * (int)j;
+  if (l0 + 3 < L && ((dr * L) & 1) == 0) {
+    __builtin_nontemporal_store(vf2{v.x, v.y}, reinterpret_cast<vf2*>(d));
+    __builtin_nontemporal_store(vf2{v.z, v.w}, reinterpret_cast<vf2*>(d + 2));
+  } else {
+    if (l0 < L) d[0] = v.x;
+    if (l0 + 1 < L) d[1] = v.y;
+    if (l0 + 2 < L) d[2] = v.z;
+    if (l0 + 3 < L) d[3] = v.w;
+  }
 }
 
 // Neighbour columns as byte offsets of Z rows (row bytes rb); the padding entries after the
@@ -1293,8 +1339,9 @@ slk_status launch_final(const FinalArgs& f0, int grid, hipStream_t s) {
 }
 
 slk_status launch_mode_reduce(const float* cand_v, const int32_t* cand_i, int grid, int32_t L, int32_t* modes_out,
-                              hipStream_t s) {
-  hipLaunchKernelGGL(mode_reduce_kernel, dim3(L), dim3(kBlock), 0, s, cand_v, cand_i, grid, L, modes_out);
+                              hipStream_t s, int32_t* mirror, const int32_t* cur, int32_t* moved) {
+  hipLaunchKernelGGL(mode_reduce_kernel, dim3(L), dim3(kBlock), 0, s, cand_v, cand_i, grid, L, modes_out, mirror, cur,
+                     moved);
   SLK_LAUNCHED("mode_reduce_kernel");
   return SLK_OK;
 }
@@ -1311,7 +1358,7 @@ slk_status launch_energy(const EnergyArgs& a, int grid, hipStream_t s) {
     SLK_LAUNCHED("energy_kernel");
   }
   hipLaunchKernelGGL(energy_reduce_kernel, dim3(1), dim3(kBlock), 0, s, a.part_un, a.part_un64, a.part_cut, grid, a.out,
-                     a.out_cut);
+                     a.out_cut, a.moved, a.L);
   SLK_LAUNCHED("energy_reduce_kernel");
   return SLK_OK;
 }
@@ -1327,6 +1374,14 @@ slk_status launch_gather_rows(const float* src, const int32_t* perm, int64_t n, 
 
 slk_status launch_scatter_rows(const float* src, const int32_t* perm, int64_t n, int32_t L, int32_t ldz, float* dst,
                                hipStream_t s) {
+  if (ldz == ldz_for(L) && ldz % 4 == 0 && n * (ldz / 4) < (int64_t)INT32_MAX) {
+    const uint32_t L4 = (uint32_t)(ldz / 4);
+    const int64_t slices = n * L4;
+    hipLaunchKernelGGL(scatter_rows4_kernel, dim3((unsigned)((slices + 255) / 256)), dim3(256), 0, s, src, perm,
+                       (uint32_t)n, L, L4, dst);
+    SLK_LAUNCHED("scatter_rows4_kernel");
+    return SLK_OK;
+  }
   const int64_t tot = n * L;
   hipLaunchKernelGGL(scatter_rows_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, src, perm, n, L, ldz,
                      dst);
