@@ -46,8 +46,14 @@ def bytes_iter(N, nnz, L):
 
 
 def bytes_final(N, nnz, L):
-    """Final pass: as a z-update, plus int32 labels in two orders."""
-    return bytes_iter(N, nnz, L) + 8 * N
+    """Final pass: the z-update's reads (it recomputes the last z-update for the labels and the
+    byproduct modes, without storing Z), plus int32 labels in two orders."""
+    return 4 * (N + 1) + 4 * nnz + 8 * N * L + 8 * N
+
+
+def bytes_scatter(N, L):
+    """Z of the last z-update to the caller's order, once per fit: Z read, perm read, Z written."""
+    return 8 * N * L + 4 * N
 
 
 def bytes_unary(N, D, L):
@@ -61,11 +67,13 @@ def bytes_energy(N, nnz, D, fp64):
 
 
 def fit_bytes(N, D, L, nnz, inner_total, outer):
-    """Every launch of a fit: per outer iteration the unary term, the z-updates, the final pass
-    and the energy; once per fit the FP64 energy recheck."""
+    """Every launch of a fit: per outer iteration the unary term, the z-updates and the final
+    pass; once per fit the energy of the last outer iteration (the earlier ones are skipped on
+    the device: a mode moved, so another outer iteration follows), its FP64 recheck and the
+    scatter of Z to the caller's order."""
     return (inner_total * bytes_iter(N, nnz, L)
-            + outer * (bytes_final(N, nnz, L) + bytes_unary(N, D, L) + bytes_energy(N, nnz, D, False))
-            + bytes_energy(N, nnz, D, True))
+            + outer * (bytes_final(N, nnz, L) + bytes_unary(N, D, L))
+            + bytes_energy(N, nnz, D, False) + bytes_energy(N, nnz, D, True) + bytes_scatter(N, L))
 
 
 def traffic_entry(kernel, workload):

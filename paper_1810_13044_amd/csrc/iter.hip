@@ -988,6 +988,9 @@ __device__ __forceinline__ void energy_block(const EnergyArgs& e, int bid) {
   // a block without a tile (grid padding) walks nothing
   const int64_t b0 = tile >= 0 ? tile * 4 * kWaveSteps + wave : 0;
   const int64_t bstop = tile >= 0 ? min(nbatch, (tile + 1) * 4 * kWaveSteps) : 0;
+  // d = 64 or 128 with 16-byte rows: the FP64 recheck's coordinates are loaded as float4 before
+  // the cut's dependent gathers, so both are in flight together
+  const bool x4 = e.x && (e.d == 64 || e.d == 128) && (((uintptr_t)e.x | (uintptr_t)e.mvec) & 15) == 0;
   for (int64_t b = b0; b < bstop; b += 4) {
     const int64_t row = b * RW + g;
     const int64_t rowc = row >= 0 && row < e.n ? row : e.n - 1;
@@ -996,11 +999,38 @@ __device__ __forceinline__ void energy_block(const EnergyArgs& e, int bid) {
     // heavy rows belong to the work-groups in front of the grid
     const bool valid = row >= 0 && row < e.n && end0 - beg <= e.heavy_deg;
     const int32_t end = valid ? end0 : beg;
+    float4 xv[2], mv[2];
+    if (x4) {
+      const int64_t orow = e.perm ? e.perm[rowc] : rowc;
+      const float4* xp = reinterpret_cast<const float4*>(e.x + orow * e.d);
+      const float4* mp = reinterpret_cast<const float4*>(e.mvec ? e.mvec + (int64_t)lab * e.d
+                                                                 : e.x + (int64_t)e.modes[lab] * e.d);
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int q = j + 16 * i;  // float4 index: coordinates 4 q .. 4 q + 3
+        xv[i] = q < e.d / 4 ? xp[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+        mv[i] = q < e.d / 4 ? mp[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+    }
     int c = 0;
     for (int32_t t = beg + j; t < end; t += G) c += (e.labels_int[e.col_idx[t]] != lab);
     c = gsum16i(c);
     double d64 = 0.0;
-    if (e.x) d64 = gsum16d(unary64_part(e, rowc, lab, j));
+    if (x4) {
+      double p = 0.0;
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const double t0 = (double)xv[i].x - (double)mv[i].x, t1 = (double)xv[i].y - (double)mv[i].y;
+        const double t2 = (double)xv[i].z - (double)mv[i].z, t3 = (double)xv[i].w - (double)mv[i].w;
+        p += t0 * t0;
+        p += t1 * t1;
+        p += t2 * t2;
+        p += t3 * t3;
+      }
+      d64 = gsum16d(p);
+    } else if (e.x) {
+      d64 = gsum16d(unary64_part(e, rowc, lab, j));
+    }
     if (valid && j == 0) {
       un += (double)e.A[rowc * e.ldz + lab];
       cut += c;
