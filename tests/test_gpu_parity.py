@@ -43,6 +43,7 @@ CASES = [
     ("ragged-1001-L7", dict(n=1001, d=9, L=7, K=5, seed=8)),
     ("wide-L70", dict(n=700, d=6, L=70, K=6, seed=9)),
     ("L1", dict(n=200, d=4, L=1, K=5, seed=10)),
+    ("d64", dict(n=3001, d=64, L=6, K=8, seed=11)),   # 16-byte paths (unary staging, FP64 recheck)
 ]
 
 
@@ -273,6 +274,33 @@ def test_fit_free_running(case, slk, torch):
                 trajectory_ztol(out, case["rp"], case["ci"], inst.lam))
     if same_modes:
         assert rel_gap(r["energy_fp64"], ref["E"]) <= 1e-4
+
+
+@pytest.mark.parametrize("max_outer", [1, 2, 20])
+def test_fit_reports_the_energy_of_its_last_labels(case, slk, torch, max_outer):
+    """The fit's energy, cut and FP64 recheck are those of its last labels at the modes that
+    produced them, also when it stops at max_outer with the modes still moving (the energies of
+    earlier outer iterations are skipped on the device)."""
+    inst = case["inst"]
+    g = slk.Graph.from_knn(to_dev(torch, case["idx"], torch.int32), to_dev(torch, case["d2"], torch.float64))
+    res = slk.fit(case["x"], g, inst.init_modes, lam=inst.lam, max_outer=max_outer)
+    r = res["result"]
+    assert r["outer_iters"] <= max_outer
+    # replay the outer iterations one at a time: the modes in force at the last one
+    m = np.asarray(inst.init_modes, dtype=np.int32)
+    for _ in range(r["outer_iters"] - 1):
+        m = slk.assign(case["x"], g, m, lam=inst.lam, trace=False)["modes_next"]
+    last = slk.assign(case["x"], g, m, lam=inst.lam, trace=False)
+    assert torch.equal(last["labels"], res["labels"]) and torch.equal(last["z"], res["z"])
+    assert np.array_equal(last["modes_next"], res["modes"])
+    assert r["converged"] == int(np.array_equal(last["modes_next"], m))
+    e = slk.energy(case["x"], g, res["labels"], m, lam=inst.lam)
+    assert e["cut"] == r["cut"]
+    assert rel_gap(r["energy"], e["energy"]) <= 1e-12
+    assert rel_gap(r["energy_fp64"], e["energy_fp64"]) <= 1e-12
+    A = orc.unary(inst.X, m, case["s2"])
+    E, cut = orc.energy(A, res["labels"].cpu().numpy().astype(np.int64), case["rp"], case["ci"], inst.lam)
+    assert cut == r["cut"] and rel_gap(r["energy_fp64"], E) <= 1e-12
 
 
 # ------------------------------------------------------------------- a8: energy API
