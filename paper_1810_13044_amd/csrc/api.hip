@@ -678,15 +678,15 @@ IterArgs make_iter(const slk_graph* g, const Work& w, int64_t n, int32_t L, cons
   return a;
 }
 
-// One outer iteration with the modes in w.modes.  Device outputs: labels_user (may be null),
-// w.modes_next, w.trace, and Z of the last z-update in w.Z[o->passes & 1] (internal order; the
-// final pass recomputes that z-update for the labels and modes, with the same result, so the
-// caller's Z is scattered from there once, after the last outer iteration).  Host outputs in *o;
+// One outer iteration with the modes in w.modes.  Device outputs: w.labels_int, w.modes_next,
+// w.trace, and Z of the last z-update in w.Z[o->passes & 1] (internal order; the final pass
+// recomputes that z-update for the labels and modes, with the same result, so the caller's Z and
+// labels are scattered from there once, after the last outer iteration).  Host outputs in *o;
 // with energy_always = false the energy, cut and their o-> fields are left stale when a mode
 // moved (the caller then runs another outer iteration and never reports them).
 slk_status run_outer(const float* x, int64_t n, int32_t d, const slk_graph* g, int32_t L, const slk_params& p,
                      double sigma2, int trace_cap, int want_fp64, bool energy_always, hipStream_t s, Work& w,
-                     int32_t* labels_user, OuterOut* o) {
+                     OuterOut* o) {
   {
     KernelTimer kt("unary_kernel", s);
     SLK_TRY(launch_unary(x, n, d, g->perm, w.modes, L, ldz_for(L), sigma2, p.prec == SLK_PREC_BF16, w.A, w.Z[0], s,
@@ -757,7 +757,7 @@ slk_status run_outer(const float* x, int64_t n, int32_t d, const slk_graph* g, i
   f.perm = g->perm;
   f.z_user = nullptr;
   f.labels_int = w.labels_int;
-  f.labels_user = labels_user;
+  f.labels_user = nullptr;
   f.cand_v = w.cand_v;
   f.cand_i = w.cand_i;
   SLK_TRY(launch_final(f, w.grid, s));
@@ -1193,7 +1193,7 @@ static slk_status assign_or_fit(bool fit, const float* x, int64_t n, int32_t d, 
   OuterOut o;
   const int outer_cap = fit ? p.max_outer : 1;
   for (int t = 0; t < outer_cap; ++t) {
-    SLK_TRY(run_outer(x, n, d, g, L, p, sigma2, cap, 0, !fit || t + 1 == outer_cap, s, w, labels_out, &o));
+    SLK_TRY(run_outer(x, n, d, g, L, p, sigma2, cap, 0, !fit || t + 1 == outer_cap, s, w, &o));
     nxt.assign(o.modes_next, o.modes_next + L);
     r.outer_iters = t + 1;
     r.inner_iters_total += o.passes;
@@ -1216,6 +1216,7 @@ static slk_status assign_or_fit(bool fit, const float* x, int64_t n, int32_t d, 
     std::swap(w.modes, w.modes_next);  // the next outer iteration runs on the byproduct modes
   }
   SLK_TRY(launch_scatter_rows(w.Z[o.passes & 1], g->perm, n, L, ldz_for(L), z_out, s));
+  if (labels_out) SLK_TRY(launch_labels_to_user(w.labels_int, g->perm, n, labels_out, s));
   // FP64 recheck of the final energy: the unary term recomputed from X in FP64 at the last
   // labels and the modes that produced them (both still resident in the work buffers)
   {
@@ -1306,7 +1307,7 @@ slk_status slk_fit_ms(const float* x, int64_t n, int32_t d, const slk_graph* g, 
   SLK_HIP(hipMemsetAsync(w.modes, 0, sizeof(int32_t) * L, s));  // unused: the modes are the vectors
   for (int t = 0; t < p.max_outer; ++t) {
     w.mvec = cur;
-    SLK_TRY(run_outer(x, n, d, g, L, p, sigma2, cap, 0, true, s, w, labels_out, &o));
+    SLK_TRY(run_outer(x, n, d, g, L, p, sigma2, cap, 0, true, s, w, &o));
     r.outer_iters = t + 1;
     r.inner_iters_total += o.passes;
     r.inner_iters_last = o.passes;
@@ -1344,6 +1345,7 @@ slk_status slk_fit_ms(const float* x, int64_t n, int32_t d, const slk_graph* g, 
     std::swap(cur, nxt);
   }
   SLK_TRY(launch_scatter_rows(w.Z[o.passes & 1], g->perm, n, L, ldz_for(L), z_out, s));
+  if (labels_out) SLK_TRY(launch_labels_to_user(w.labels_int, g->perm, n, labels_out, s));
   // FP64 recheck of the final energy at the last labels and the modes that produced them
   {
     EnergyArgs e{};

@@ -344,6 +344,8 @@ slk_status launch_scatter_rows(const float* src, const int32_t* perm, int64_t n,
 slk_status launch_col_offsets(const int32_t* col_idx, int64_t nnz, int64_t n, int32_t L, uint32_t* out, hipStream_t s);
 slk_status launch_to_internal_labels(const int32_t* labels_user, const int32_t* iperm, int64_t n, int32_t* out,
                                      hipStream_t s);
+slk_status launch_labels_to_user(const int32_t* labels_int, const int32_t* perm, int64_t n, int32_t* out,
+                                 hipStream_t s);
 
 // graph construction
 // k nearest points of x for each query: rows of x (rows[] or all n_rows, the point itself

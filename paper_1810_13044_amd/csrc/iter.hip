@@ -1238,11 +1238,13 @@ __global__ void col_offsets_kernel(const int32_t* __restrict__ col_idx, int64_t 
   else if (i < nnz + kColPad) out[i] = dead;
 }
 
-__global__ void labels_to_internal_kernel(const int32_t* __restrict__ lu, const int32_t* __restrict__ iperm,
-                                          int64_t n, int32_t* __restrict__ out) {
+// out[p[i]] = in[i]: labels from one order to the other (p = iperm: caller's -> internal;
+// p = perm: internal -> caller's)
+__global__ void permute_labels_kernel(const int32_t* __restrict__ in, const int32_t* __restrict__ p, int64_t n,
+                                      int32_t* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  out[iperm ? iperm[i] : i] = lu[i];
+  out[p ? p[i] : i] = in[i];
 }
 
 inline int lanes_for(int L) {
@@ -1430,10 +1432,15 @@ slk_status launch_col_offsets(const int32_t* col_idx, int64_t nnz, int64_t n, in
 
 slk_status launch_to_internal_labels(const int32_t* labels_user, const int32_t* iperm, int64_t n, int32_t* out,
                                      hipStream_t s) {
-  hipLaunchKernelGGL(labels_to_internal_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, labels_user, iperm,
-                     n, out);
-  SLK_LAUNCHED("labels_to_internal_kernel");
+  hipLaunchKernelGGL(permute_labels_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, labels_user, iperm, n,
+                     out);
+  SLK_LAUNCHED("permute_labels_kernel");
   return SLK_OK;
+}
+
+slk_status launch_labels_to_user(const int32_t* labels_int, const int32_t* perm, int64_t n, int32_t* out,
+                                 hipStream_t s) {
+  return launch_to_internal_labels(labels_int, perm, n, out, s);
 }
 
 }  // namespace slk
