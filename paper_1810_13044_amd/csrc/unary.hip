@@ -38,7 +38,7 @@ __device__ __forceinline__ void unary_block(const UnaryArgs& u, int64_t bid) {
   const int RS = R + 4, MS = MG * kUT + 4;  // padded strides (multiples of 4 floats)
   float* xs = sm;                 // DC x RS, coordinate-major
   float* ms = xs + DC * RS;       // DC x MS
-  float* as = ms + DC * MS;       // R x L
+  float* as = sm;                 // R x L, written after the last chunk: shares the staging space
   const int tid = threadIdx.x;
   const int64_t row0 = bid * R;
   const int nr = (int)min<int64_t>(R, n - row0);
@@ -220,7 +220,8 @@ int unary_grid(const UnaryArgs& u) { return (int)((u.n + u.R - 1) / u.R); }
 size_t unary_lds(const UnaryArgs& u) {
   const int DC = u.L <= 128 ? 32 : 16;
   const int MG = (u.L + kUT - 1) / kUT;
-  return sizeof(float) * ((size_t)DC * (u.R + 4) + (size_t)DC * (MG * kUT + 4) + (size_t)u.R * u.L);
+  const size_t staging = (size_t)DC * (u.R + 4) + (size_t)DC * (MG * kUT + 4);
+  return sizeof(float) * std::max(staging, (size_t)u.R * u.L);
 }
 
 // 16-byte loads need d % 4 == 0 (rows then start on 16-byte boundaries of a 16-byte aligned x).
