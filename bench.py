@@ -68,12 +68,12 @@ def bytes_energy(N, nnz, D, fp64):
 
 def fit_bytes(N, D, L, nnz, inner_total, outer):
     """Every launch of a fit: per outer iteration the unary term, the z-updates and the final
-    pass; once per fit the energy of the last outer iteration (the earlier ones are skipped on
-    the device: a mode moved, so another outer iteration follows), its FP64 recheck and the
-    scatter of Z to the caller's order."""
+    pass; once per fit the energy of the last outer iteration with its FP64 recheck in the same
+    pass (the earlier ones are skipped on the device: a mode moved, so another outer iteration
+    follows) and the scatter of Z to the caller's order."""
     return (inner_total * bytes_iter(N, nnz, L)
             + outer * (bytes_final(N, nnz, L) + bytes_unary(N, D, L))
-            + bytes_energy(N, nnz, D, False) + bytes_energy(N, nnz, D, True) + bytes_scatter(N, L))
+            + bytes_energy(N, nnz, D, True) + bytes_scatter(N, L))
 
 
 def traffic_entry(kernel, workload):

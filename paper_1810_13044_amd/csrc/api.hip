@@ -1193,7 +1193,7 @@ static slk_status assign_or_fit(bool fit, const float* x, int64_t n, int32_t d, 
   OuterOut o;
   const int outer_cap = fit ? p.max_outer : 1;
   for (int t = 0; t < outer_cap; ++t) {
-    SLK_TRY(run_outer(x, n, d, g, L, p, sigma2, cap, 0, !fit || t + 1 == outer_cap, s, w, &o));
+    SLK_TRY(run_outer(x, n, d, g, L, p, sigma2, cap, 1, !fit || t + 1 == outer_cap, s, w, &o));
     nxt.assign(o.modes_next, o.modes_next + L);
     r.outer_iters = t + 1;
     r.inner_iters_total += o.passes;
@@ -1217,35 +1217,9 @@ static slk_status assign_or_fit(bool fit, const float* x, int64_t n, int32_t d, 
   }
   SLK_TRY(launch_scatter_rows(w.Z[o.passes & 1], g->perm, n, L, ldz_for(L), z_out, s));
   if (labels_out) SLK_TRY(launch_labels_to_user(w.labels_int, g->perm, n, labels_out, s));
-  // FP64 recheck of the final energy: the unary term recomputed from X in FP64 at the last
-  // labels and the modes that produced them (both still resident in the work buffers)
-  {
-    EnergyArgs e{};
-    set_heavy(e, g);
-    e.row_ptr = g->row_ptr;
-    e.col_idx = g->col_idx;
-    e.labels_int = w.labels_int;
-    e.A = w.A;
-    e.x = x;
-    e.perm = g->perm;
-    e.modes = w.modes;
-    e.n = n;
-    e.d = d;
-    e.L = L;
-    e.ldz = ldz_for(L);
-    e.inv2s2 = 1.0 / (2.0 * sigma2);
-    e.part_un = w.epart_un;
-    e.part_un64 = w.epart_un64;
-    e.part_cut = w.epart_cut;
-    e.out = w.eout;
-    e.out_cut = w.eout_cut;
-    SLK_TRY(launch_energy(e, w.egrid, s));
-    double eo[2];
-    SLK_HIP(hipMemcpyAsync(eo, w.eout, sizeof(eo), hipMemcpyDeviceToHost, s));
-    SLK_HIP(hipStreamSynchronize(s));
-    if (timing_on()) timing_flush();
-    r.energy_fp64 = -eo[1] + p.lambda * (double)r.cut;
-  }
+  // r.energy_fp64 is the FP64 recheck of the last outer iteration's energy: its energy pass also
+  // recomputed the unary term from X in FP64 at the last labels and the modes that produced them
+  // (the only energy pass of a fit that is not skipped, see run_outer)
   if (trace_host && trace_cap > 0) {
     const int m = std::min(trace_cap, std::min(o.passes, cap));
     SLK_HIP(hipMemcpyAsync(trace_host, w.trace, sizeof(double) * m, hipMemcpyDeviceToHost, s));
