@@ -19,9 +19,11 @@
  *    complete when the stream reaches the call's end.
  *  - The caller owns every array it passes in; the library never frees caller memory.
  *    Graph handles are owned by the library until slk_graph_destroy.  Temporary device
- *    memory is taken from the library's stream-ordered pool on the current device and
- *    returned to it before the call ends; the pool keeps up to 4 GiB of freed memory per
- *    device for later calls (slk_pool_trim releases it).
+ *    memory stays with the library for later calls on the same device: slk_fit, slk_assign,
+ *    slk_fit_ms and slk_energy (which synchronise their stream before returning) carve theirs
+ *    from one kept block per concurrent call, as large as the largest such call needed; the
+ *    other calls take it from a stream-ordered pool that keeps up to 4 GiB of freed memory.
+ *    slk_pool_trim releases both.
  *  - Errors are returned as slk_status; no exception or abort crosses the ABI.  Arguments
  *    are validated before any launch; on a non-OK status the outputs are unspecified and
  *    slk_last_error() describes the failure (thread-local text, valid until the next call
@@ -438,9 +440,11 @@ slk_status slk_fit_batched(const slk_job* jobs, int32_t n_jobs, const slk_server
 slk_status slk_timing_enable(int32_t on);
 slk_status slk_timing_read(const char* kernel, int64_t* launches_host, double* total_ms_host);
 
-/* Returns the freed memory held by the library's pool on the current device to the system.
-   Memory of calls still in flight on any stream stays allocated; the pool refills as later
-   calls run.  SLK_ERR_DEVICE if the pool cannot be created or trimmed. */
+/* Returns the work memory the library keeps on the current device (the blocks of the
+   synchronising calls and the pool's freed memory) to the system.  Memory of calls still in
+   progress on any thread or stream stays allocated; later calls allocate again as they need.
+   For callers that must bound the device memory the library holds between calls.
+   SLK_ERR_DEVICE if the pool cannot be created or trimmed. */
 slk_status slk_pool_trim(void);
 
 /* Text for the last non-OK status returned on this thread. */
