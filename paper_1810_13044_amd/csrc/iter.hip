@@ -869,9 +869,28 @@ __device__ __forceinline__ void mode_reduce_block(const float* __restrict__ cv, 
   const int tid = threadIdx.x;
   float v = -INFINITY;
   int i = INT32_MAX;
-  for (int b = tid; b < grid; b += kBlock) {
-    const float ov = cv[(int64_t)l * grid + b];
-    const int oi = ci[(int64_t)l * grid + b];
+  const float* __restrict__ cvl = cv + (int64_t)l * grid;
+  const int32_t* __restrict__ cil = ci + (int64_t)l * grid;
+  // candidates tid, tid + kBlock, ... in that order; their loads are issued 8 at a time
+  int b = tid;
+  for (; b + 7 * kBlock < grid; b += 8 * kBlock) {
+    float ov[8];
+    int oi[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      ov[u] = cvl[b + u * kBlock];
+      oi[u] = cil[b + u * kBlock];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (ov[u] > v || (ov[u] == v && oi[u] < i)) {
+        v = ov[u];
+        i = oi[u];
+      }
+  }
+  for (; b < grid; b += kBlock) {
+    const float ov = cvl[b];
+    const int oi = cil[b];
     if (ov > v || (ov == v && oi < i)) {
       v = ov;
       i = oi;
@@ -1088,7 +1107,25 @@ __device__ __forceinline__ void energy_reduce_block(const double* __restrict__ p
   const int tid = threadIdx.x;
   double a0 = 0, a1 = 0;
   long long c0 = 0;
-  for (int i = tid; i < nparts; i += kBlock) {
+  // partials tid, tid + kBlock, ... in that order; their loads are issued 4 at a time
+  int i = tid;
+  for (; i + 3 * kBlock < nparts; i += 4 * kBlock) {
+    double u0[4], u1[4];
+    long long uc[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      u0[u] = p_un[i + u * kBlock];
+      u1[u] = p_un64[i + u * kBlock];
+      uc[u] = p_cut[i + u * kBlock];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a0 += u0[u];
+      a1 += u1[u];
+      c0 += uc[u];
+    }
+  }
+  for (; i < nparts; i += kBlock) {
     a0 += p_un[i];
     a1 += p_un64[i];
     c0 += p_cut[i];
