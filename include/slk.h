@@ -48,7 +48,7 @@ typedef enum {
   SLK_ERR_OUT_OF_MEMORY = 2, /* a device or pinned host allocation failed             */
   SLK_ERR_DEVICE = 3,        /* a HIP runtime call or kernel launch failed            */
   SLK_ERR_NUMERIC = 4,       /* the relaxed bound became NaN or infinite              */
-  SLK_ERR_UNSUPPORTED = 5    /* a valid request this build does not implement          */
+  SLK_ERR_UNSUPPORTED = 5    /* a valid request the library does not implement         */
 } slk_status;
 
 /* Precision of the points used by the distance computations. */

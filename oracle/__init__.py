@@ -7,7 +7,7 @@ and never imports it; the product path must not route through it.
 Modules:
   slk    -- the method step by step: kNN affinity, bandwidth, unary affinities,
             the bound-optimizer z-update, relaxed bound, labels, byproduct modes,
-            discrete energy and the outer/inner driver (SLK-BO).
+            discrete energy and the outer/inner loops (SLK-BO).
   brute  -- brute-force minimisation of the discrete objective over all labelings
             with modes taken by their definition (small N only).
   extend -- out-of-sample assignment and the SLK-MS mean-shift mode update.

@@ -1,4 +1,4 @@
-// The C ABI of libslk: argument validation, graph handles and the SLK-BO driver
+// The C ABI of libslk: argument validation, graph handles and the SLK-BO host loop
 // (Algorithm 1: outer mode updates around inner z-updates).
 #include "common.h"
 
@@ -250,8 +250,8 @@ void timing_retag_tail(const char* name, int count, const char* to) {
 }
 
 // Host-visible mirror of the z-update loop state (two slots, alternating by pass) and one event
-// per slot, per device and thread.  The pass reduction stores the state there, so the driver
-// watches the loop without a copy on the stream.
+// per slot, per device and thread.  The pass reduction stores the state there, so the host loop
+// watches the z-updates without a copy on the stream.
 // The results of one outer iteration, written by its kernels straight into host-mapped memory:
 // the host reads them after one synchronise, with no copies on the stream.
 struct OuterHost {
