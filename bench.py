@@ -602,9 +602,9 @@ def main():
     serve = None
     if args.serve_jobs > 0 and args.serve_sweep:
         rates = [float(v) for v in args.serve_sweep.split(",")]
-        serve = serving_sweep(slk, torch, args.serve_jobs, rates, args.serve_slots, 2)
+        serve = serving_sweep(slk, torch, args.serve_jobs, rates, args.serve_slots, 4)
     elif args.serve_jobs > 0:
-        serve = serving(slk, torch, args.serve_jobs, args.serve_rate, args.serve_slots, 2)
+        serve = serving(slk, torch, args.serve_jobs, args.serve_rate, args.serve_slots, 4)
         log(f"[serve] {serve}")
 
     cpu = cpu_more = None

@@ -398,7 +398,7 @@ typedef struct {
 
 typedef struct slk_server slk_server;
 
-/* Fill *o with defaults: max_jobs 64, passes_per_step 2, memory_budget 0, builders 3. */
+/* Fill *o with defaults: max_jobs 64, passes_per_step 4, memory_budget 0, builders 3. */
 slk_status slk_server_opts_default(slk_server_opts* o);
 
 /* Create a server that runs on `stream` (device = the current device).  Release with

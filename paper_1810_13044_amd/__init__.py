@@ -394,7 +394,7 @@ class Server:
     admit what fits and advance every resident job; finished jobs' outcomes are returned by
     step() and kept in .done."""
 
-    def __init__(self, max_jobs=64, passes_per_step=2, memory_budget=0, builders=0):
+    def __init__(self, max_jobs=64, passes_per_step=4, memory_budget=0, builders=0):
         self._lib = _lib.load()
         o = _lib.ServerOpts()
         _lib.check(self._lib.slk_server_opts_default(C.byref(o)))
@@ -443,7 +443,7 @@ class Server:
             pass
 
 
-def fit_batched(problems, max_jobs=64, passes_per_step=2, **common):
+def fit_batched(problems, max_jobs=64, passes_per_step=4, **common):
     """Fit a list of problems with slk_fit_batched.  Each problem is a dict with x and
     init_modes (and optionally lam, k, method, reorder, knn_prec and slk_params keywords);
     `common` supplies defaults.  Returns one outcome dict per problem, in order."""

@@ -666,7 +666,7 @@ extern "C" {
 slk_status slk_server_opts_default(slk_server_opts* o) {
   if (!o) return fail(SLK_ERR_INVALID_ARG, "opts is NULL");
   o->max_jobs = 64;
-  o->passes_per_step = 2;
+  o->passes_per_step = 4;
   o->memory_budget = 0;
   o->builders = 3;
   o->reserved = 0;
