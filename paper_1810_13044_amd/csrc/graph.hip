@@ -72,6 +72,7 @@ __global__ __launch_bounds__(kBlock) void knn_exact_kernel(const float* __restri
                                                            int64_t n_rows, int32_t* __restrict__ out_idx,
                                                            double* __restrict__ out_d2, const float* __restrict__ y) {
   const float* __restrict__ qsrc = y ? y : x;
+  const bool vec4 = (d & 3) == 0 && ((uintptr_t)x & 15) == 0;
   __shared__ double qs[kQB][kQDc];
   __shared__ double ld[kQB][64];
   __shared__ int lq[kQB][64];
@@ -113,7 +114,24 @@ __global__ __launch_bounds__(kBlock) void knn_exact_kernel(const float* __restri
       __syncthreads();
       if (q < n) {
         const float* xq = x + q * d + c0;
-        for (int j = 0; j < dc; ++j) {
+        // the key's coordinates in order; 16 bytes per load where rows allow it (each thread
+        // walks its own row, so single floats re-fetch every cache line from L2 up to 16 times)
+        int j = 0;
+        if (vec4) {
+          for (; j + 4 <= dc; j += 4) {
+            const float4 f4 = *reinterpret_cast<const float4*>(xq + j);
+            const float fv[4] = {f4.x, f4.y, f4.z, f4.w};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              float f = fv[u];
+              if (bf16) f = bf16_round(f);
+              const double xv = (double)f;
+#pragma unroll
+              for (int i = 0; i < kQB; ++i) acc[i] = sqdist_step(acc[i], qs[i][j + u], xv);
+            }
+          }
+        }
+        for (; j < dc; ++j) {
           float f = xq[j];
           if (bf16) f = bf16_round(f);
           const double xv = (double)f;
