@@ -48,6 +48,9 @@ def test_defaults(lib):
     assert lib.slk_knn_opts_default(C.byref(o)) == 0
     assert (o.k, o.reorder, o.candidates, o.method, o.prec) == (10, 0, 0, 0, 0)
     assert lib.slk_version().startswith(b"libslk")
+    so = _lib.ServerOpts()
+    assert lib.slk_server_opts_default(C.byref(so)) == 0
+    assert (so.max_jobs, so.passes_per_step, so.memory_budget, so.builders) == (64, 4, 0, 3)
 
 
 def test_invalid_arguments_rejected_before_launch(lib):
