@@ -38,7 +38,10 @@ __device__ __forceinline__ bool key_less(double d0, int q0, double d1, int q1) {
 // ------------------------------------------------------------------------------------------
 // exact kNN: QB query rows per block, keys streamed 256 at a time (one key per thread)
 // ------------------------------------------------------------------------------------------
-constexpr int kQB = 8;      // queries per block
+// Queries per block: 8 where there are many rows (each key read serves more queries), 4 where
+// there are few (twice the blocks, less LDS per block, more blocks per CU).
+constexpr int kQBWide = 8, kQBNarrow = 4;
+constexpr int64_t kQBNarrowMaxRows = 12000;
 constexpr int kQDc = 256;   // query coordinates staged per chunk
 constexpr int kSortP = 512; // bitonic width of a merge (k + 256 <= 320 entries)
 
@@ -66,7 +69,8 @@ __device__ void block_bitonic(double* kd, int* kq, int P) {
 }
 
 // Queries are rows of x (rows[] or all, the point itself excluded) or, with y, the rows of y
-// (nothing excluded).
+// (nothing excluded).  The result does not depend on kQB.
+template <int kQB>
 __global__ __launch_bounds__(kBlock) void knn_exact_kernel(const float* __restrict__ x, int64_t n, int d, int k,
                                                            int bf16, const int32_t* __restrict__ rows,
                                                            int64_t n_rows, int32_t* __restrict__ out_idx,
@@ -480,9 +484,15 @@ slk_status knn_exact(const float* x, int64_t n, int32_t d, int32_t k, int32_t bf
                      int64_t n_rows, int32_t* out_idx, double* out_d2, hipStream_t s, const float* y) {
   if (n_rows <= 0) return SLK_OK;
   if (k > 64) return fail(SLK_ERR_INVALID_ARG, "k > 64");
-  const int64_t grid = (n_rows + kQB - 1) / kQB;
-  hipLaunchKernelGGL(knn_exact_kernel, dim3((unsigned)grid), dim3(kBlock), 0, s, x, n, d, k, bf16, rows, n_rows,
-                     out_idx, out_d2, y);
+  if (n_rows <= kQBNarrowMaxRows) {
+    const int64_t grid = (n_rows + kQBNarrow - 1) / kQBNarrow;
+    hipLaunchKernelGGL(knn_exact_kernel<kQBNarrow>, dim3((unsigned)grid), dim3(kBlock), 0, s, x, n, d, k, bf16, rows,
+                       n_rows, out_idx, out_d2, y);
+  } else {
+    const int64_t grid = (n_rows + kQBWide - 1) / kQBWide;
+    hipLaunchKernelGGL(knn_exact_kernel<kQBWide>, dim3((unsigned)grid), dim3(kBlock), 0, s, x, n, d, k, bf16, rows,
+                       n_rows, out_idx, out_d2, y);
+  }
   SLK_LAUNCHED("knn_exact_kernel");
   return SLK_OK;
 }

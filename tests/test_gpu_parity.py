@@ -80,6 +80,24 @@ def test_knn_exact_bit_identical(case, slk, torch):
     assert info["max_degree"] == int(np.max(np.diff(case["rp"])))
 
 
+@pytest.mark.parametrize("n,d", [(12000, 20), (12289, 20), (12291, 64)])
+def test_knn_exact_block_widths(n, d, slk, torch):
+    """The exact search runs 4 queries per work-group up to 12,000 rows and 8 above; both widths
+    (and a ragged last work-group) give the oracle's lists bit for bit, checked on sampled rows:
+    the first and last 40, and 200 drawn at random."""
+    inst = gen.gaussian_mixture(n=n, d=d, L=5, K=9, seed=n % 97)
+    g = slk.Graph.build_knn(to_dev(torch, inst.X, torch.float32), k=inst.K, method="exact")
+    ex = g.export()
+    idx, d2 = ex["knn_idx"].cpu().numpy(), ex["knn_d2"].cpu().numpy()
+    g.close()
+    rng = np.random.default_rng(n)
+    rows = np.unique(np.concatenate([np.arange(40), np.arange(n - 40, n), rng.integers(0, n, 200)]))
+    _say(f"[exact widths] n={n} d={d}: {len(rows)} sampled rows")
+    oi, od = orc.knn(inst.X, inst.K, rows=rows, block=64)
+    assert np.array_equal(idx[rows], oi)
+    assert np.array_equal(d2[rows], od)
+
+
 def test_graph_from_knn_and_reorder(case, slk, torch):
     inst = case["inst"]
     for reorder in (False, True):
