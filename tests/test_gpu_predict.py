@@ -32,7 +32,8 @@ def check(z, lab, nn, ref, lam, k):
 
 
 @pytest.mark.parametrize("L,m,k,method", [(5, 37, 10, "exact"), (5, 1001, 10, "mfma"), (12, 300, 1, "exact"),
-                                          (40, 513, 7, "mfma"), (70, 200, 10, "exact")])
+                                          (40, 513, 7, "mfma"), (70, 200, 10, "exact"),
+                                          (6, 12003, 10, "exact")])   # 8 queries per exact work-group
 def test_predict_against_oracle(slk, torch, L, m, k, method):
     inst = gen.gaussian_mixture(n=1500, d=12, L=L, K=10, seed=50 + L)
     x = to_dev(torch, inst.X, torch.float32)
