@@ -38,10 +38,12 @@ __device__ __forceinline__ bool key_less(double d0, int q0, double d1, int q1) {
 // ------------------------------------------------------------------------------------------
 // exact kNN: QB query rows per block, keys streamed 256 at a time (one key per thread)
 // ------------------------------------------------------------------------------------------
-// Queries per block: 8 where there are many rows (each key read serves more queries), 4 where
-// there are few (twice the blocks, less LDS per block, more blocks per CU).
+// Queries per block: 4 while the keys fit in one XCD's L2 (4 MiB), so that key reads are L2 hits
+// and twice the blocks (less LDS each, more per CU) hide their latency, or while the wide grid
+// would have fewer than two blocks per CU; otherwise 8, halving the key reads that go past L2.
 constexpr int kQBWide = 8, kQBNarrow = 4;
-constexpr int64_t kQBNarrowMaxRows = 12000;
+constexpr double kQBNarrowKeyBytes = 4.0 * 1024 * 1024;
+constexpr int64_t kQBNarrowMaxRows = 8 * 512;
 constexpr int kQDc = 256;   // query coordinates staged per chunk
 constexpr int kSortP = 512; // bitonic width of a merge (k + 256 <= 320 entries)
 
@@ -484,7 +486,7 @@ slk_status knn_exact(const float* x, int64_t n, int32_t d, int32_t k, int32_t bf
                      int64_t n_rows, int32_t* out_idx, double* out_d2, hipStream_t s, const float* y) {
   if (n_rows <= 0) return SLK_OK;
   if (k > 64) return fail(SLK_ERR_INVALID_ARG, "k > 64");
-  if (n_rows <= kQBNarrowMaxRows) {
+  if ((double)n * d * sizeof(float) <= kQBNarrowKeyBytes || n_rows < kQBNarrowMaxRows) {
     const int64_t grid = (n_rows + kQBNarrow - 1) / kQBNarrow;
     hipLaunchKernelGGL(knn_exact_kernel<kQBNarrow>, dim3((unsigned)grid), dim3(kBlock), 0, s, x, n, d, k, bf16, rows,
                        n_rows, out_idx, out_d2, y);

@@ -33,7 +33,7 @@ def check(z, lab, nn, ref, lam, k):
 
 @pytest.mark.parametrize("L,m,k,method", [(5, 37, 10, "exact"), (5, 1001, 10, "mfma"), (12, 300, 1, "exact"),
                                           (40, 513, 7, "mfma"), (70, 200, 10, "exact"),
-                                          (6, 12003, 10, "exact")])   # 8 queries per exact work-group
+                                          (6, 12003, 10, "exact")])
 def test_predict_against_oracle(slk, torch, L, m, k, method):
     inst = gen.gaussian_mixture(n=1500, d=12, L=L, K=10, seed=50 + L)
     x = to_dev(torch, inst.X, torch.float32)
@@ -46,6 +46,26 @@ def test_predict_against_oracle(slk, torch, L, m, k, method):
                              method=method)
     ref = extend.predict(inst.X, Z.cpu().numpy().astype(np.float64), inst.init_modes, Y, k, s2, 0.8)
     check(z, lab, nn, ref, 0.8, k)
+
+
+@pytest.mark.parametrize("m", [4095, 4101])
+def test_predict_exact_widths(slk, torch, m):
+    """Queries into 20,000 x 64 points (5 MiB): the exact search runs 4 queries per work-group
+    below 4,096 queries and 8 from there.  Z is any row-stochastic matrix (seeded); each query's
+    result depends on that query alone, so the oracle checks a sample: the first and last 40
+    queries and 200 drawn at random."""
+    inst = gen.gaussian_mixture(n=20000, d=64, L=6, K=10, seed=81)
+    rng = np.random.default_rng(m)
+    Zh = rng.random((inst.N, 6)) + 0.05
+    Zh = (Zh / Zh.sum(axis=1, keepdims=True)).astype(np.float32)
+    x = to_dev(torch, inst.X, torch.float32)
+    Y = queries(inst, m, seed=m)
+    z, lab, nn = slk.predict(x, to_dev(torch, Zh, torch.float32), inst.init_modes, to_dev(torch, Y, torch.float32),
+                             k=10, lam=0.8, sigma2=2000.0, method="exact")
+    rows = np.unique(np.concatenate([np.arange(40), np.arange(m - 40, m), rng.integers(0, m, 200)]))
+    ref = extend.predict(inst.X, Zh.astype(np.float64), inst.init_modes, Y[rows], 10, 2000.0, 0.8)
+    r = torch.as_tensor(rows, device="cuda")
+    check(z[r], lab[r], nn[r], ref, 0.8, 10)
 
 
 def test_predict_bf16_points(slk, torch):
