@@ -246,6 +246,13 @@ def energy(A, labels, row_ptr, col_idx, lam: float):
 # Algorithm 1 (SLK-BO)
 # ----------------------------------------------------------------------------------
 
+def inner_settled(r_prev: float, r_cur: float, tol: float) -> bool:
+    """R10, the inner "until convergence" of Algorithm 1: the loop has settled once the relaxed
+    bound of the newest input iterate differs from the bound of the one before it by at most
+    tol times the magnitude of the earlier bound."""
+    return abs(r_cur - r_prev) <= tol * abs(r_prev)
+
+
 def assign(X, row_ptr, col_idx, modes, sigma2: float, lam: float, *, delta: float = 0.0,
            scale: float = 1.0, tol: float = 1e-8, max_inner: int = 1000,
            n_inner: int | None = None, A=None, W=None):
@@ -270,10 +277,8 @@ def assign(X, row_ptr, col_idx, modes, sigma2: float, lam: float, *, delta: floa
         Aux_trace.append(aux_at_minimiser(S, Z, B, lam, scale))
         Z_in = Z
         Z = softmax_rows(S)
-        if n_inner is None and i >= 1:
-            r0, r1 = R_trace[-2], R_trace[-1]
-            if abs(r1 - r0) <= tol * abs(r0):
-                break
+        if n_inner is None and i >= 1 and inner_settled(R_trace[-2], R_trace[-1], tol):
+            break
     labels = hard_labels(S)
     new_modes, ties, V = byproduct_modes(S)
     E, cut = energy(A, labels, row_ptr, col_idx, lam)

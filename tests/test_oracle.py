@@ -377,6 +377,103 @@ def test_fit_mixture2k_converges():
     assert len(np.unique(out["modes"])) == inst.L
 
 
+# ---------------------------------------------------------------- R10: the inner stop rule
+
+def _sigmoid(t):
+    return 1.0 / (1.0 + math.exp(-t))
+
+
+def _two_point_bounds(alpha, lam, c, passes):
+    """Relaxed bound R(Z^0), R(Z^1), ... of a two-point instance, derived by hand.
+
+    Two points joined by one edge, L = 2, and the same unary row a_p = (alpha + c, c) for both.
+    By symmetry both rows stay equal, z_p = (u, 1 - u); b_p = z_q gives the logits
+    s_p = (alpha + c + lam u, c + lam (1 - u)), so Eq. (8) is the scalar map
+    u <- sigmoid(alpha + lam (2u - 1)) from u = sigmoid(alpha) (Z^0 = softmax(a)).  Summed over the
+    two points, z_p.log z_p - z_p.a_p - (lam/2) z_p.b_p is
+        R(u) = 2 [u log u + (1 - u) log(1 - u) - alpha u - c - (lam/2) (u^2 + (1 - u)^2)].
+    The shift c moves every R by -2c and leaves the iterates unchanged."""
+    u = _sigmoid(alpha)
+    out = []
+    for _ in range(passes):
+        h = u * math.log(u) + (1.0 - u) * math.log(1.0 - u)
+        out.append(2.0 * (h - alpha * u - c - 0.5 * lam * (u * u + (1.0 - u) ** 2)))
+        u = _sigmoid(alpha + lam * (2.0 * u - 1.0))
+    return out
+
+
+def _stop_pass(R, tol, rule):
+    """Passes run under a stop rule, from the bound trace R: 'rel' is reading R10 (relative change
+    between the bounds of consecutive input iterates); 'abs' an absolute change; 'out' the change
+    between the bounds of consecutive output iterates (one pass earlier).  Also returns the margin:
+    how far the deciding change lies below tol, and the previous one above it."""
+    for i in range(1, len(R) - 1):
+        if rule == "rel":
+            num, den = abs(R[i] - R[i - 1]), tol * abs(R[i - 1])
+        elif rule == "abs":
+            num, den = abs(R[i] - R[i - 1]), tol
+        else:
+            num, den = abs(R[i + 1] - R[i]), tol * abs(R[i])
+        if num <= den:
+            margin = den / max(num, 1e-300)
+            if rule == "rel" and i >= 2:
+                margin = min(margin, abs(R[i - 1] - R[i - 2]) / (tol * abs(R[i - 2])))
+            return i + 1, margin
+    raise AssertionError("no stop within the trace")
+
+
+R10_CASES = [(0.3, 1.0, 0.0, 3e-8), (0.3, 1.0, 1000.0, 3e-8)]
+
+
+def _two_point_assign(alpha, lam, c, tol):
+    A = np.array([[alpha + c, c], [alpha + c, c]])
+    rp, ci = np.array([0, 1, 2]), np.array([1, 0])
+    return slk.assign(np.zeros((2, 1)), rp, ci, np.array([0, 1]), 1.0, lam, tol=tol, A=A)
+
+
+def test_r10_two_point_trace_and_stop():
+    """The oracle's bound trace equals the hand-derived one, and it stops at the pass the relative
+    rule gives: 10 passes unshifted, 6 with the bound shifted by -2000 (the same iterates)."""
+    for alpha, lam, c, tol in R10_CASES:
+        out = _two_point_assign(alpha, lam, c, tol)
+        R = _two_point_bounds(alpha, lam, c, 40)
+        n, margin = _stop_pass(R, tol, "rel")
+        assert margin >= 1.3, "the case sits too close to the threshold"
+        assert out["n_pass"] == n
+        np.testing.assert_allclose(out["R_trace"], R[:n], rtol=1e-13, atol=1e-13)
+        u = np.full(2, _sigmoid(alpha))
+        for _ in range(n):
+            u = np.array([_sigmoid(alpha + lam * (2 * u[0] - 1))] * 2)
+        np.testing.assert_allclose(out["Z"][:, 0], u, rtol=1e-14)
+    assert [_two_point_assign(*cs)["n_pass"] for cs in R10_CASES] == [10, 6]
+
+
+def test_r10_cases_tell_the_rules_apart():
+    """Under an absolute rule both cases would stop together (11 passes); under a rule on the
+    output iterates' bounds each would stop one pass earlier (9 and 5)."""
+    got = {rule: [_stop_pass(_two_point_bounds(a, l, c, 40), t, rule)[0] for a, l, c, t in R10_CASES]
+           for rule in ("rel", "abs", "out")}
+    assert got == {"rel": [10, 6], "abs": [11, 11], "out": [9, 5]}
+
+
+def test_planted_absolute_stop_rule_is_caught(monkeypatch):
+    monkeypatch.setattr(slk, "inner_settled", lambda r0, r1, tol: abs(r1 - r0) <= tol)
+    assert [_two_point_assign(*cs)["n_pass"] for cs in R10_CASES] != [10, 6]
+
+
+def test_planted_output_bound_rule_is_caught(monkeypatch):
+    # the trace records the bound of each pass's output instead of its input
+    orig = slk.relaxed_bound
+
+    def out_bound(Z, A, B, lam, scale=1.0):
+        Zn = slk.softmax_rows(A + scale * lam * B)
+        W = slk.csr_matrix(np.array([0, 1, 2]), np.array([1, 0]), 2)
+        return orig(Zn, A, slk.pairwise(W, Zn), lam, scale)
+
+    monkeypatch.setattr(slk, "relaxed_bound", out_bound)
+    assert [_two_point_assign(*cs)["n_pass"] for cs in R10_CASES] != [10, 6]
+
+
 # ---------------------------------------------------------------- planted mistakes are caught
 
 def test_planted_factor_two_breaks_monotonicity(small, monkeypatch):
