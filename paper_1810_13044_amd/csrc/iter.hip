@@ -515,10 +515,11 @@ __device__ __forceinline__ float4 gather_sum(const IterArgs& a, __amdgpu_buffer_
                                              int32_t beg, int cnt, uint32_t dead) {
   constexpr int U = kCH / G;   // offset registers per lane and round
   float bx = 0.f, by = 0.f, bz = 0.f, bw = 0.f;
-  for (int t0 = 0; __ballot(t0 < cnt) != 0ull; t0 += kCH) {
-    uint32_t off[U];
+  // the offsets of round t0 + kCH are loaded while round t0's rows are in flight
+  uint32_t off[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) off[u] = neighbour_offset(a, beg, cnt, t0 + j + G * u, dead);
+  for (int u = 0; u < U; ++u) off[u] = neighbour_offset(a, beg, cnt, j + G * u, dead);
+  for (int t0 = 0; __ballot(t0 < cnt) != 0ull; t0 += kCH) {
     float4 v[kCH];
     auto gather_lo = [&](auto ic) {
       constexpr int i = decltype(ic)::value;
@@ -531,6 +532,10 @@ __device__ __forceinline__ float4 gather_sum(const IterArgs& a, __amdgpu_buffer_
     static_for<0, kHalf>(gather_lo);
     const bool hi = __ballot(t0 + kHalf < cnt) != 0ull;
     if (hi) static_for<0, kHalf>(gather_hi);
+    if (__ballot(t0 + kCH < cnt) != 0ull) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) off[u] = neighbour_offset(a, beg, cnt, t0 + kCH + j + G * u, dead);
+    }
 #pragma unroll
     for (int i = 0; i < kHalf; ++i) {
       bx += v[i].x;
@@ -680,10 +685,23 @@ __device__ __forceinline__ void iter4_block(const IterArgs& a, int bid) {
   // a block without a tile (grid padding) walks nothing: b0 = bstop = 0
   const int64_t b0 = tile >= 0 ? tile * 4 * kWaveSteps + wave : 0;
   const int64_t bstop = tile >= 0 ? min(nbatch, (tile + 1) * 4 * kWaveSteps) : 0;
+  // the row extent of batch b + 4 is loaded while batch b is computed
+  auto clamp_row = [&](int64_t row) { return (uint32_t)(row >= 0 && row < a.n ? row : a.n - 1); };
+  int32_t nbeg = 0, nend = 0;
+  if (b0 < bstop) {
+    const uint32_t r0 = clamp_row(b0 * RW + g);
+    nbeg = a.row_ptr[r0];
+    nend = a.row_ptr[r0 + 1];
+  }
   for (int64_t b = b0; b < bstop; b += 4) {
     const int64_t row = b * RW + g;
-    const uint32_t rowc = (uint32_t)(row >= 0 && row < a.n ? row : a.n - 1);
-    const int32_t beg = a.row_ptr[rowc], end = a.row_ptr[rowc + 1];
+    const uint32_t rowc = clamp_row(row);
+    const int32_t beg = nbeg, end = nend;
+    if (b + 4 < bstop) {
+      const uint32_t r1 = clamp_row((b + 4) * RW + g);
+      nbeg = a.row_ptr[r1];
+      nend = a.row_ptr[r1 + 1];
+    }
     // heavy rows belong to the work-groups in front of the grid
     const bool valid = row >= 0 && row < a.n && end - beg <= a.heavy_deg;
     Row4 o;
