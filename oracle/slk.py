@@ -209,11 +209,12 @@ def tie_eps(vmax: float) -> float:
     return 64.0 * ulp32(vmax) + 1e-6
 
 
-def byproduct_modes(S: np.ndarray):
+def byproduct_modes(S: np.ndarray, V=None):
     """m_l = x_q with q = argmax_q z_ql  (Eq. (11)), ranked by log-odds, ties to the
     smaller index.  Also returns, per cluster, the tie set of candidates whose
-    log-odds lie within tie_eps of the best."""
-    V = log_odds(S)
+    log-odds lie within tie_eps of the best.  V = log_odds(S) may be passed in when it
+    is already at hand."""
+    V = log_odds(S) if V is None else V
     modes = np.argmax(V, axis=0).astype(np.int64)
     ties = []
     for l in range(S.shape[1]):

@@ -8,6 +8,7 @@ import sys
 
 import numpy as np
 import pytest
+import scipy.sparse as sp
 
 import gen
 from oracle import slk as orc
@@ -146,27 +147,39 @@ def test_inner_step(case, slk, torch, delta, scale, lam, reorder):
 
 # ------------------------------------------------------------------- a5-a8: one outer iteration, lock-step
 
-def fp32_storage_z(A, rp, ci, n_pass, lam, delta=0.0, scale=1.0):
-    """The oracle's z-updates in FP64 arithmetic but with A and every Z^i rounded to FP32,
-    as any implementation that stores them in FP32 must.  Its distance to the plain FP64
-    run measures how much the iteration itself amplifies storage rounding."""
-    W = orc.csr_matrix(rp, ci, A.shape[0])
-    r32 = lambda M: M.astype(np.float32).astype(np.float64)
-    A32 = r32(A)
-    Z = r32(orc.softmax_rows(A32))
+def fp32_reference_z(A, rp, ci, n_pass, lam, delta=0.0, scale=1.0):
+    """A plain float32 implementation of the same z-updates, independent of the GPU code: A
+    rounded to float32, then each pass in float32 NumPy/SciPy arithmetic (CSR product, exp,
+    row sum, division).  Its distance from the FP64 oracle is what FP32 arithmetic itself costs
+    over these passes: the iteration amplifies rounding, so after many passes it can exceed the
+    per-step bound of 1e-5 (30 passes of ragged-1001-L7 reach 1.9e-5)."""
+    N = A.shape[0]
+    W = sp.csr_matrix((np.ones(len(ci), np.float32), np.asarray(ci), np.asarray(rp)), shape=(N, N))
+    A32 = A.astype(np.float32)
+    f = np.float32
+
+    def softmax32(S):
+        e = np.exp(S - S.max(axis=1, keepdims=True))
+        return e / e.sum(axis=1, keepdims=True)
+
+    Z = softmax32(A32)
     for _ in range(n_pass):
-        Z = r32(orc.softmax_rows(A32 + scale * lam * orc.pairwise(W, Z, delta)))
-    return Z
+        B = W @ Z
+        if delta:
+            B = B + f(delta) * Z
+        Z = softmax32(A32 + f(scale * lam) * B)
+    return Z.astype(np.float64)
 
 
-def trajectory_ztol(out, rp, ci, lam):
-    """1e-5 plus 16 times the amplification of FP32 storage rounding over the same passes.
-
-    Storage rounding perturbs each iterate by ~2^-24 relative; an FP32 z-update's own
-    arithmetic (exp, reciprocal, sums) perturbs it by up to ~16 times that, and the iteration
-    amplifies both alike, so 16 x the measured storage spread bounds the arithmetic's share."""
-    spread = np.abs(fp32_storage_z(out["A"], rp, ci, out["n_pass"], lam) - out["Z"]).max()
-    return ZTOL + 16.0 * spread
+def trajectory_ztol(out, rp, ci, lam, dz=None):
+    """Tolerance on Z after a whole outer iteration (many passes from Z^0): 1e-5, or the float32
+    reference's own distance from the oracle where that is larger.  Each single z-update is held
+    to 1e-5 separately (test_stepwise_parity_along_gpu_trajectory, test_inner_step).  With dz given
+    and within 1e-5, the reference is not computed."""
+    if dz is not None and dz <= ZTOL:
+        return ZTOL
+    spread = np.abs(fp32_reference_z(out["A"], rp, ci, out["n_pass"], lam) - out["Z"]).max()
+    return max(ZTOL, float(spread))
 
 
 def check_outer(res, out, inst, rp, ci, lam, ztol=ZTOL):
@@ -190,6 +203,8 @@ def check_outer(res, out, inst, rp, ci, lam, ztol=ZTOL):
     assert agree >= 0.999, agree
     chosen = S[np.arange(len(lab)), lab]
     assert np.all(chosen >= top - slack), "a label outside the oracle's near-tie set"
+    stats = dict(dz=float(dz), resolvable=int(resolvable.sum()), agree_resolvable=float(agree),
+                 agree_all=float(np.mean(lab == out["labels"])))
     r = res["result"]
     # energy of the GPU's labels, evaluated by the oracle at the same modes
     E_at, cut_at = orc.energy(out["A"], lab, rp, ci, lam)
@@ -205,6 +220,7 @@ def check_outer(res, out, inst, rp, ci, lam, ztol=ZTOL):
         vbest = V[out["modes_next"][l], l]
         ok = m in out["ties"][l] or V[m, l] >= vbest - orc.tie_eps(vbest) - vslack
         assert ok, (l, m, out["modes_next"][l], V[m, l], vbest)
+    return stats
 
 
 def test_assign_lockstep(case, slk, torch):
@@ -212,8 +228,9 @@ def test_assign_lockstep(case, slk, torch):
     g = slk.Graph.from_knn(to_dev(torch, case["idx"], torch.int32), to_dev(torch, case["d2"], torch.float64))
     out = orc.assign(inst.X, case["rp"], case["ci"], inst.init_modes, case["s2"], inst.lam)
     res = slk.assign(case["x"], g, inst.init_modes, lam=inst.lam, fixed_inner=out["n_pass"])
-    ztol = trajectory_ztol(out, case["rp"], case["ci"], inst.lam)
-    _say(f"[assign] {inst.name}: passes={out['n_pass']} ztol={ztol:.2e}")
+    dz = float(np.abs(res["z"].cpu().numpy() - out["Z"]).max())
+    ztol = trajectory_ztol(out, case["rp"], case["ci"], inst.lam, dz)
+    _say(f"[assign] {inst.name}: passes={out['n_pass']} max|dZ|={dz:.2e} ztol={ztol:.2e}")
     check_outer(res, out, inst, case["rp"], case["ci"], inst.lam, ztol)
     np.testing.assert_allclose(res["bound_trace"], out["R_trace"], rtol=1e-5, atol=1e-6)
 
@@ -264,8 +281,10 @@ def test_fit_trajectory_lockstep(case, slk, torch):
     for t in range(20):
         out = orc.assign(inst.X, case["rp"], case["ci"], modes, case["s2"], inst.lam)
         res = slk.assign(case["x"], g, modes, lam=inst.lam, fixed_inner=out["n_pass"])
-        check_outer(res, out, inst, case["rp"], case["ci"], inst.lam,
-                    trajectory_ztol(out, case["rp"], case["ci"], inst.lam))
+        dz = float(np.abs(res["z"].cpu().numpy() - out["Z"]).max())
+        ztol = trajectory_ztol(out, case["rp"], case["ci"], inst.lam, dz)
+        _say(f"[lockstep] {inst.name} outer {t}: passes={out['n_pass']} max|dZ|={dz:.2e} ztol={ztol:.2e}")
+        check_outer(res, out, inst, case["rp"], case["ci"], inst.lam, ztol)
         nxt = res["modes_next"].astype(np.int64)
         if np.array_equal(nxt, modes):
             break
@@ -274,25 +293,62 @@ def test_fit_trajectory_lockstep(case, slk, torch):
         pytest.fail("did not converge in 20 outer iterations")
 
 
+def gpu_outer_history(slk, x, g, modes0, lam, max_outer=20):
+    """The GPU's own fit replayed one outer iteration at a time (slk_assign with the fit's stop
+    rule): [(modes used, assign result), ...] up to the first outer iteration whose byproduct
+    modes repeat its modes."""
+    hist = []
+    m = np.asarray(modes0, dtype=np.int64)
+    for _ in range(max_outer):
+        r = slk.assign(x, g, m, lam=lam)
+        hist.append((m, r))
+        nxt = r["modes_next"].astype(np.int64)
+        if np.array_equal(nxt, m):
+            break
+        m = nxt
+    return hist
+
+
 def test_fit_free_running(case, slk, torch):
+    """Both sides run on their own (each its own inner stop); wherever the GPU's byproduct mode lies
+    in the oracle's tie set the oracle takes the GPU's pick (several modes are correct there, R8),
+    elsewhere its own.  The final energies agree to 1e-6 and the labels to 99.9%."""
     inst = case["inst"]
     g = slk.Graph.from_knn(to_dev(torch, case["idx"], torch.int32), to_dev(torch, case["d2"], torch.float64))
-    ref = orc.fit(inst.X, case["rp"], case["ci"], inst.init_modes, case["s2"], inst.lam)
     res = slk.fit(case["x"], g, inst.init_modes, lam=inst.lam)
     r = res["result"]
     assert r["converged"] == 1
-    same_modes = np.array_equal(res["modes"], ref["modes"])
-    _say(f"[fit] {inst.name}: outer gpu={r['outer_iters']} orc={ref['outer_iters']} same_modes={same_modes}")
-    # The GPU's final state must be one the oracle confirms: at the GPU's final modes the
-    # oracle's own outer iteration (same pass count) reproduces labels, Z, energy and the
-    # modes as a fixed point.
-    out = orc.assign(inst.X, case["rp"], case["ci"], res["modes"], case["s2"], inst.lam,
-                     n_inner=r["inner_iters_last"])
-    res = dict(res, modes_next=res["modes"])
-    check_outer(res, out, inst, case["rp"], case["ci"], inst.lam,
-                trajectory_ztol(out, case["rp"], case["ci"], inst.lam))
-    if same_modes:
-        assert rel_gap(r["energy_fp64"], ref["E"]) <= 1e-4
+    hist = gpu_outer_history(slk, case["x"], g, inst.init_modes, inst.lam)
+    last = hist[-1][1]
+    assert len(hist) == r["outer_iters"] and torch.equal(last["labels"], res["labels"])
+    assert np.array_equal(last["modes_next"], res["modes"])
+    picks = [h[1]["modes_next"].astype(np.int64) for h in hist]
+    log = []
+
+    def follow(t, om, ties):
+        gp = picks[t] if t < len(picks) else om
+        nxt = np.array([gp[l] if gp[l] in ties[l] else om[l] for l in range(inst.L)], dtype=np.int64)
+        log.append((t, [len(tl) for tl in ties], int(np.sum(nxt != om))))
+        return nxt
+
+    ref = orc.fit(inst.X, case["rp"], case["ci"], inst.init_modes, case["s2"], inst.lam, choose_modes=follow)
+    lab = res["labels"].cpu().numpy()
+    S = ref["S"]
+    top = S.max(axis=1)
+    second = np.sort(S, axis=1)[:, -2] if inst.L > 1 else np.full(inst.N, -np.inf)
+    ulp = np.spacing(np.abs(top).astype(np.float32)).astype(np.float64)
+    slack = 1e-6 + 64 * ulp + inst.lam * np.diff(case["rp"]) * ZTOL
+    resolvable = (top - second) > slack
+    agree = float(np.mean(lab[resolvable] == ref["labels"][resolvable])) if resolvable.any() else 1.0
+    gap = rel_gap(r["energy_fp64"], ref["E"])
+    _say(f"[fit] {inst.name}: outer gpu={r['outer_iters']} orc={ref['outer_iters']} passes gpu="
+         f"{r['inner_iters_last']} orc={ref['history'][-1]['n_pass']} (outer, tie-set sizes, oracle picks replaced by "
+         f"the GPU's) {log} labels={np.mean(lab == ref['labels']):.5f} resolvable rows={int(resolvable.sum())} "
+         f"agreement there={agree:.5f} E_gap={gap:.2e}")
+    assert ref["converged"] and np.array_equal(ref["modes"], res["modes"])
+    assert agree >= 0.999
+    assert np.all(S[np.arange(inst.N), lab] >= top - slack), "a label outside the oracle's near-tie set"
+    assert gap <= ETOL
 
 
 @pytest.mark.parametrize("max_outer", [1, 2, 20])

@@ -517,3 +517,21 @@ def test_planted_argmin_mode_fails_membership(small):
     out = slk.assign(inst.X, rp, ci, inst.init_modes, s2, 1.0)
     wrong = np.argmin(out["V"], axis=0)
     assert any(wrong[l] not in out["ties"][l] for l in range(inst.L))
+
+
+# ---------------------------------------------------------------- the row-block driver of the full-size tests
+
+@pytest.mark.parametrize("delta,scale", [(0.0, 1.0), (2.0, 2.0)])
+def test_row_block_assign_equals_oracle(small, delta, scale):
+    import par_oracle
+    inst, (_i, _d, rp, ci, s2) = small
+    pool = par_oracle.RowPool(threads=3)
+    try:
+        a = par_oracle.assign(pool, inst.X, rp, ci, inst.init_modes, s2, 0.9, 7, delta=delta, scale=scale)
+    finally:
+        pool.close()
+    b = slk.assign(inst.X, rp, ci, inst.init_modes, s2, 0.9, n_inner=7, delta=delta, scale=scale)
+    for k in ("Z", "Z_in", "S", "A", "labels", "modes_next", "V"):
+        assert np.array_equal(a[k], b[k]), k
+    assert a["R_trace"] == b["R_trace"] and a["E"] == b["E"] and a["cut"] == b["cut"]
+    assert all(np.array_equal(x, y) for x, y in zip(a["ties"], b["ties"]))
