@@ -244,6 +244,30 @@ slk_status slk_inner_step(const slk_graph* g, int32_t L, const float* a, const f
                           double* bound_host);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): the z-update of slk_inner_step without any
+ * allocation, synchronisation or host output, so that it can also be captured into a HIP graph.
+ *  g, L, a, z_in, lambda, delta, pairwise_scale : as in slk_inner_step (a, z_in: device n x L
+ *                 float32, caller's layout and order).
+ *  z_out        : device n x L float32 (may be NULL: bound only); must not alias z_in.
+ *  bound_dev    : device, one double (may be NULL) receiving R(z_in) as in slk_inner_step.
+ * The per-work-group bound partials and the pass state live in a 2 MiB array of device memory
+ * that the library holds on every device it runs on until the process ends, so n is limited:
+ * SLK_ERR_INVALID_ARG if n > slk_inner_step_noalloc_max_rows(L) (4,193,792 rows for 32 < L <= 256,
+ * more for smaller L).  The array is shared by every call on one device and keeps the last
+ * call's contents; the call resets what must start at zero itself.  Calls that overlap on one
+ * device (different streams, or threads) race on the array: order them (one stream, or events).
+ * The result equals slk_inner_step's up to the order of the floating-point sums (the rows are
+ * walked by a different kernel).  The first call on a device looks up the array's address.
+ */
+slk_status slk_inner_step_noalloc(const slk_graph* g, int32_t L, const float* a, const float* z_in, double lambda,
+                                  double delta, int32_t pairwise_scale, void* stream, float* z_out,
+                                  double* bound_dev);
+
+/* Largest n slk_inner_step_noalloc accepts for this L (0 if L is outside 1..256). */
+int64_t slk_inner_step_noalloc_max_rows(int32_t L);
+
+/*
  * Out-of-sample assignment (Section 1: the explicit assignment variables give a direct
  * out-of-sample extension).  Each query y takes the z-update of Eq. (8) once with the fit
  * held fixed:

@@ -235,6 +235,24 @@ def inner_step(graph: Graph, a, z_in, lam=1.0, delta=0.0, scale=1):
     return z_out, b.value
 
 
+def inner_step_noalloc(graph: Graph, a, z_in, z_out, bound=None, lam=1.0, delta=0.0, scale=1):
+    """One z-update from z_in into the caller's z_out (may be None) through the allocation-free
+    entry point; bound (a one-element float64 device tensor, may be None) receives R(z_in).
+    Asynchronous on the current stream."""
+    torch = _torch()
+    lib = _lib.load()
+    n, L = a.shape
+    zo = None if z_out is None else _dev(z_out, torch.float32, "z_out", (n, L))
+    bd = None if bound is None else _dev(bound, torch.float64, "bound", (1,))
+    _lib.check(lib.slk_inner_step_noalloc(graph.handle, L, _dev(a, torch.float32, "a", (n, L)),
+                                          _dev(z_in, torch.float32, "z_in", (n, L)), float(lam), float(delta),
+                                          int(scale), _stream(), zo, bd))
+
+
+def inner_step_noalloc_max_rows(L):
+    return int(_lib.load().slk_inner_step_noalloc_max_rows(int(L)))
+
+
 def predict(x, z, modes, y, k=10, lam=1.0, sigma2=0.0, graph=None, method="auto", prec="fp32"):
     """Out-of-sample assignment of the queries y (m x d) against a fit (x, z, modes).
     sigma2 <= 0 takes the estimate of `graph`.  Returns (z_y, labels_y, knn_idx)."""

@@ -94,6 +94,7 @@ def load(path: str = LIB_PATH):
         "slk_energy": [P, I64, I32, P, I32, P, P, P, D, D, D, P, C.POINTER(EnergyOut)],
         "slk_unary": [P, I64, I32, I32, P, D, I32, P, P, P],
         "slk_inner_step": [P, I32, P, P, D, D, I32, P, P, P],
+        "slk_inner_step_noalloc": [P, I32, P, P, D, D, I32, P, P, P],
         "slk_predict": [P, I64, I32, P, I32, P, P, I64, I32, D, D, I32, I32, P, P, P, P],
         "slk_mean_shift": [P, I64, I32, P, I32, P, D, D, I32, I32, P, P, P],
         "slk_fit_ms": [P, I64, I32, P, I32, P, C.POINTER(Params), D, I32, P, P, P, P, P, P, C.POINTER(Result)],
@@ -104,6 +105,8 @@ def load(path: str = LIB_PATH):
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = C.c_int
+    lib.slk_inner_step_noalloc_max_rows.argtypes = [I32]
+    lib.slk_inner_step_noalloc_max_rows.restype = I64
     lib.slk_pool_trim.argtypes = []
     lib.slk_pool_trim.restype = C.c_int
     lib.slk_timing_enable.argtypes = [I32]

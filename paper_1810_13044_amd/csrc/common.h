@@ -208,6 +208,8 @@ struct IterArgs {
   int32_t n_heavy;
   int32_t hblocks;       // heavy_blocks(n_heavy), or 0
   int32_t heavy_deg;     // rows above this degree belong to the heavy work-groups
+  const int32_t* zperm;  // scalar path only: rows of A, Zin, Zout are in the caller's order, row
+                         // zperm[r] holding internal row r (null = the internal order itself)
 };
 
 struct FinalArgs {
@@ -286,6 +288,11 @@ slk_status launch_reduce_packed(const ReduceJob* jobs, int njobs, hipStream_t s)
 slk_status launch_mode_reduce_packed(const ModeJob* jobs, const int32_t* start, int njobs, int blocks, hipStream_t s);
 int iter_grid(int64_t n, int32_t L, int64_t n_heavy);
 slk_status launch_iter(const IterArgs& a, int grid, hipStream_t s);
+// The row-per-lane-group z-update for any L (no heavy-row split, no col_off), on rows of stride
+// a.ldz, optionally in the caller's order (a.zperm), and its pass reduction.
+int64_t iter_rows_per_group(int32_t L);
+int iter_grid_rows(int64_t n, int32_t L);
+slk_status launch_iter_rows(const IterArgs& a, int grid, hipStream_t s);
 slk_status launch_final(const FinalArgs& a, int grid, hipStream_t s);
 // modes_out: L int32 on the device; mirror (may be null): a second copy, e.g. host-mapped memory;
 // cur and moved (both null or both set): moved[l] = (modes_out[l] != cur[l]).

@@ -88,10 +88,15 @@ __device__ __forceinline__ void load_extent(const IterArgs& a, int64_t row, Curs
   }
 }
 
+// Row of A / Z holding internal row r (the caller's order when zperm is given).
+__device__ __forceinline__ uint32_t zrow(const IterArgs& a, int64_t r) {
+  return a.zperm ? (uint32_t)a.zperm[r] : (uint32_t)r;
+}
+
 template <int S>
 __device__ __forceinline__ void load_chunk(const IterArgs& a, int l0, Cursor& c) {
   const int cnt = min(S, c.end - c.beg);
-  c.myq = (l0 < cnt) ? a.col_idx[c.beg + l0] : 0;
+  c.myq = (l0 < cnt) ? (int)zrow(a, a.col_idx[c.beg + l0]) : 0;
 }
 
 // Computes one row inside its S-lane group.  All lanes of the group must call it together.
@@ -105,7 +110,7 @@ __device__ __forceinline__ void row_update(const IterArgs& a, int64_t row, int l
   const int L = a.L;
   // element offsets fit in 32 bits (n * ldz < 2^32 is checked on the host): one VGPR per address
   const uint32_t uL = (uint32_t)a.ldz;
-  const uint32_t roff = (uint32_t)row * uL;
+  const uint32_t roff = zrow(a, row < a.n ? row : 0) * uL;
   float zp[E], av[E], b[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
@@ -124,7 +129,7 @@ __device__ __forceinline__ void row_update(const IterArgs& a, int64_t row, int l
   bool prefetched = false;
   for (int32_t c = cur.beg; c < cur.end; c += S) {
     const int cnt = min(S, cur.end - c);
-    const int myq = (c == cur.beg) ? cur.myq : ((l0 < cnt) ? a.col_idx[c + l0] : 0);
+    const int myq = (c == cur.beg) ? cur.myq : ((l0 < cnt) ? (int)zrow(a, a.col_idx[c + l0]) : 0);
     for (int t0 = 0; t0 < cnt; t0 += CH) {
       float v[CH][E];
 #pragma unroll
@@ -248,7 +253,7 @@ __global__ __launch_bounds__(kBlock) void iter_kernel(IterArgs a) {
     row_loop<S, E>(a, base + wave * G + g, 4 * G, min(a.n, base + kTileRows), l0,
                    [&](int64_t row, const RowOut<S, E>& o) {
                      if (a.Zout) {
-                       const uint32_t roff = (uint32_t)row * (uint32_t)a.ldz;
+                       const uint32_t roff = zrow(a, row) * (uint32_t)a.ldz;
 #pragma unroll
                        for (int e = 0; e < E; ++e) {
                          const int l = l0 + S * e;
@@ -1404,6 +1409,22 @@ slk_status launch_iter(const IterArgs& a, int grid, hipStream_t s) {
     else SLK_DISPATCH_LANES(a.L, iter_kernel, dim3(grid), dim3(kBlock), 0, s, a);
     SLK_LAUNCHED("iter_kernel");
   }
+  hipLaunchKernelGGL(pass_reduce_kernel, dim3(1), dim3(kRedBlock), 0, s, a.partial, grid, a.state, a.trace, a.bound_out,
+                     a.mirror);
+  SLK_LAUNCHED("pass_reduce_kernel");
+  return SLK_OK;
+}
+
+int64_t iter_rows_per_group(int32_t L) { return 4 * (64 / lanes_for(L)) * kWaveSteps; }
+
+int iter_grid_rows(int64_t n, int32_t L) {
+  const int64_t rows = iter_rows_per_group(L);
+  return (int)tile_grid((n + rows - 1) / rows);
+}
+
+slk_status launch_iter_rows(const IterArgs& a, int grid, hipStream_t s) {
+  SLK_DISPATCH_LANES(a.L, iter_kernel, dim3(grid), dim3(kBlock), 0, s, a);
+  SLK_LAUNCHED("iter_kernel");
   hipLaunchKernelGGL(pass_reduce_kernel, dim3(1), dim3(kRedBlock), 0, s, a.partial, grid, a.state, a.trace, a.bound_out,
                      a.mirror);
   SLK_LAUNCHED("pass_reduce_kernel");
