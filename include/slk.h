@@ -53,8 +53,12 @@ typedef enum {
 
 /* Precision of the points used by the distance computations. */
 typedef enum {
-  SLK_PREC_FP32 = 0, /* X as given (float32)                                            */
-  SLK_PREC_BF16 = 1  /* X rounded to bfloat16 once; all distances use the rounded points */
+  SLK_PREC_FP32 = 0,  /* X as given (float32)                                            */
+  SLK_PREC_BF16 = 1,  /* X rounded to bfloat16 once; all distances use the rounded points */
+  SLK_PREC_BF16X = 2  /* unary distances as a bf16 MFMA contraction with FP32 accumulation of
+                         X split into two bf16 terms (hi + lo, tile-centred); X itself is not
+                         rounded; the kNN graph is built as for FP32 (its candidates are bf16
+                         MFMA products already).  For fits, assignments, slk_unary, slk_predict. */
 } slk_precision;
 
 /* Candidate search used by slk_build_knn. */

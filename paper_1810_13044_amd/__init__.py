@@ -11,7 +11,7 @@ import ctypes as C
 import numpy as np
 
 from . import _lib
-from ._lib import SlkError, PREC_FP32, PREC_BF16, KNN_AUTO, KNN_EXACT, KNN_MFMA  # noqa: F401
+from ._lib import SlkError, PREC_FP32, PREC_BF16, PREC_BF16X, KNN_AUTO, KNN_EXACT, KNN_MFMA  # noqa: F401
 
 __all__ = ["Graph", "fit", "assign", "energy", "unary", "inner_step", "params", "SlkError", "timing_enable",
            "timing_read"]
@@ -46,6 +46,8 @@ def _prec(p) -> int:
         return _lib.PREC_FP32
     if p in (1, "bf16", "bfloat16"):
         return _lib.PREC_BF16
+    if p in (2, "bf16x"):
+        return _lib.PREC_BF16X
     raise ValueError(f"unknown precision {p!r}")
 
 

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(_PKG, "libslk.so")
 SLK_OK = 0
 STATUS = {0: "SLK_OK", 1: "SLK_ERR_INVALID_ARG", 2: "SLK_ERR_OUT_OF_MEMORY", 3: "SLK_ERR_DEVICE",
           4: "SLK_ERR_NUMERIC", 5: "SLK_ERR_UNSUPPORTED"}
-PREC_FP32, PREC_BF16 = 0, 1
+PREC_FP32, PREC_BF16, PREC_BF16X = 0, 1, 2
 KNN_AUTO, KNN_EXACT, KNN_MFMA = 0, 1, 2
 
 

@@ -689,7 +689,7 @@ slk_status run_outer(const float* x, int64_t n, int32_t d, const slk_graph* g, i
                      OuterOut* o) {
   {
     KernelTimer kt("unary_kernel", s);
-    SLK_TRY(launch_unary(x, n, d, g->perm, w.modes, L, ldz_for(L), sigma2, p.prec == SLK_PREC_BF16, w.A, w.Z[0], s,
+    SLK_TRY(launch_unary(x, n, d, g->perm, w.modes, L, ldz_for(L), sigma2, unary_mode(p.prec), w.A, w.Z[0], s,
                          nullptr, w.mvec));
   }
   const int check = p.fixed_inner > 0 ? 0 : 1;
@@ -839,7 +839,7 @@ slk_status check_params(const slk_params* p) {
   if (p->max_inner < 1) return fail(SLK_ERR_INVALID_ARG, "max_inner must be >= 1");
   if (p->fixed_inner < 0) return fail(SLK_ERR_INVALID_ARG, "fixed_inner must be >= 0");
   if (p->pairwise_scale != 1 && p->pairwise_scale != 2) return fail(SLK_ERR_INVALID_ARG, "pairwise_scale must be 1 or 2");
-  if (p->prec != SLK_PREC_FP32 && p->prec != SLK_PREC_BF16) return fail(SLK_ERR_INVALID_ARG, "unknown precision");
+  if (p->prec != SLK_PREC_FP32 && p->prec != SLK_PREC_BF16 && p->prec != SLK_PREC_BF16X) return fail(SLK_ERR_INVALID_ARG, "unknown precision");
   return SLK_OK;
 }
 
@@ -940,7 +940,7 @@ slk_status slk_build_knn(const float* x, int64_t n, int32_t d, const slk_knn_opt
   if (opts) o = *opts;
   else slk_knn_opts_default(&o);
   if (o.k < 1 || o.k > 64 || o.k >= n) return fail(SLK_ERR_INVALID_ARG, "k must satisfy 1 <= k <= 64 and k < n");
-  if (o.prec != SLK_PREC_FP32 && o.prec != SLK_PREC_BF16) return fail(SLK_ERR_INVALID_ARG, "unknown precision");
+  if (o.prec != SLK_PREC_FP32 && o.prec != SLK_PREC_BF16 && o.prec != SLK_PREC_BF16X) return fail(SLK_ERR_INVALID_ARG, "unknown precision");
   if (o.method < SLK_KNN_AUTO || o.method > SLK_KNN_MFMA) return fail(SLK_ERR_INVALID_ARG, "unknown kNN method");
   if (o.candidates < 0) return fail(SLK_ERR_INVALID_ARG, "candidates must be >= 0");
   if ((int64_t)n * 2 * o.k >= (int64_t)INT32_MAX) return fail(SLK_ERR_INVALID_ARG, "n * 2k exceeds the CSR index range");
@@ -1102,13 +1102,13 @@ slk_status slk_unary(const float* x, int64_t n, int32_t d, int32_t L, const int3
   for (int l = 0; l < L; ++l)
     if (modes_host[l] < 0 || modes_host[l] >= n) return fail(SLK_ERR_INVALID_ARG, "mode index out of range");
   if (!(sigma2 > 0.0) || !isfinite(sigma2)) return fail(SLK_ERR_INVALID_ARG, "sigma2 must be > 0");
-  if (prec != SLK_PREC_FP32 && prec != SLK_PREC_BF16) return fail(SLK_ERR_INVALID_ARG, "unknown precision");
+  if (prec != SLK_PREC_FP32 && prec != SLK_PREC_BF16 && prec != SLK_PREC_BF16X) return fail(SLK_ERR_INVALID_ARG, "unknown precision");
   hipStream_t s = (hipStream_t)stream;
   Scratch sc(s);
   int32_t* md;
   SLK_TRY(sc.get(&md, L));
   SLK_HIP(hipMemcpyAsync(md, modes_host, sizeof(int32_t) * L, hipMemcpyHostToDevice, s));
-  SLK_TRY(launch_unary(x, n, d, nullptr, md, L, L, sigma2, prec == SLK_PREC_BF16, a_out, z0_out, s));
+  SLK_TRY(launch_unary(x, n, d, nullptr, md, L, L, sigma2, unary_mode(prec), a_out, z0_out, s));
   SLK_HIP(hipStreamSynchronize(s));
   return SLK_OK;
 }
@@ -1275,7 +1275,7 @@ slk_status slk_fit_ms(const float* x, int64_t n, int32_t d, const slk_graph* g, 
   SLK_HIP(hipMemcpyAsync(cur, init_modes, sizeof(float) * L * d, hipMemcpyDeviceToDevice, s));
   slk_result r{};
   OuterOut o;
-  const int bf16 = p.prec == SLK_PREC_BF16;
+  const int umode = unary_mode(p.prec);
   const double lim = ms_tol * std::sqrt(sigma2);
   int32_t ms_steps = 0;
   SLK_HIP(hipMemsetAsync(w.modes, 0, sizeof(int32_t) * L, s));  // unused: the modes are the vectors
@@ -1292,7 +1292,7 @@ slk_status slk_fit_ms(const float* x, int64_t n, int32_t d, const slk_graph* g, 
     // Eq. (9) with the relaxed assignment of the last z-update (internal order)
     SLK_HIP(hipMemcpyAsync(nxt, cur, sizeof(float) * L * d, hipMemcpyDeviceToDevice, s));
     int32_t its = 0;
-    SLK_TRY(mean_shift_loop(x, n, d, g->perm, w.Z[o.passes & 1], L, ldz_for(L), nxt, sigma2, ms_tol, ms_max_iter, bf16,
+    SLK_TRY(mean_shift_loop(x, n, d, g->perm, w.Z[o.passes & 1], L, ldz_for(L), nxt, sigma2, ms_tol, ms_max_iter, umode,
                             s, &its, nullptr));
     ms_steps += its;
     // how far the modes moved over the whole update

@@ -223,6 +223,13 @@ struct FinalArgs {
   int32_t grid;          // work-groups of this pass (the candidate arrays' row length)
 };
 
+// How the unary term forms its distances: FP32 direct differences of the points as given, of the
+// points rounded to bf16 (SLK_PREC_BF16), or the bf16 split contraction on MFMA (SLK_PREC_BF16X).
+constexpr int32_t kUnaryFp32 = 0, kUnaryRounded = 1, kUnaryMfma = 2;
+inline int32_t unary_mode(int32_t prec) {
+  return prec == SLK_PREC_BF16 ? kUnaryRounded : prec == SLK_PREC_BF16X ? kUnaryMfma : kUnaryFp32;
+}
+
 struct UnaryArgs {
   const float* x;        // n x d, original order
   int64_t n;
@@ -230,7 +237,7 @@ struct UnaryArgs {
   const int32_t* perm;   // internal -> original (null = identity)
   const int32_t* modes;  // L original indices (device)
   float inv2s2;
-  int32_t bf16;
+  int32_t bf16;          // kUnaryFp32, kUnaryRounded or kUnaryMfma
   float* A;              // n x ldz, internal order (may be null)
   float* Z0;             // n x ldz (may be null)
   const float* xm;       // points the mode indices refer to (null = x)
@@ -256,7 +263,7 @@ struct ModeJob {
 
 // xm: the points the mode indices refer to (null = x; the out-of-sample queries use the fit's x)
 slk_status launch_unary(const float* x, int64_t n, int32_t d, const int32_t* perm, const int32_t* modes_dev,
-                        int32_t L, int32_t ldz, double sigma2, int32_t bf16, float* A, float* Z0, hipStream_t s,
+                        int32_t L, int32_t ldz, double sigma2, int32_t umode, float* A, float* Z0, hipStream_t s,
                         const float* xm = nullptr, const float* mvec = nullptr);
 UnaryArgs unary_args(const float* x, int64_t n, int32_t d, const int32_t* perm, const int32_t* modes_dev, int32_t L,
                      int32_t ldz, double sigma2, int32_t bf16, float* A, float* Z0);
@@ -332,7 +339,7 @@ slk_status launch_energy_packed(const EnergyArgs* jobs, const int32_t* start, in
 // SLK-MS: mean-shift of the modes m (L x d, in place) for the assignment Z (internal order,
 // stride ldz) until no mode moves by more than tol * sigma or max_iter steps (meanshift.hip).
 slk_status mean_shift_loop(const float* x, int64_t n, int32_t d, const int32_t* perm, const float* Z, int32_t L,
-                           int32_t ldz, float* m, double sigma2, double tol, int32_t max_iter, int32_t bf16,
+                           int32_t ldz, float* m, double sigma2, double tol, int32_t max_iter, int32_t umode,
                            hipStream_t s, int32_t* iters, double* last_shift);
 
 // argument checks and per-graph settings shared by the C ABI and the served form (api.hip)

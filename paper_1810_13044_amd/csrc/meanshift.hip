@@ -191,7 +191,7 @@ slk_status launch_ms_step(const float* x, int64_t n, int32_t d, const int32_t* p
 // Mean-shift iterated from m (L x d, updated in place) until no mode moves by more than tol * sigma
 // or max_iter steps; Z and the workspace as above.  *iters receives the steps taken.
 slk_status mean_shift_loop(const float* x, int64_t n, int32_t d, const int32_t* perm, const float* Z, int32_t L,
-                           int32_t ldz, float* m, double sigma2, double tol, int32_t max_iter, int32_t bf16,
+                           int32_t ldz, float* m, double sigma2, double tol, int32_t max_iter, int32_t umode,
                            hipStream_t s, int32_t* iters, double* last_shift) {
   if (L > kLmax) return fail(SLK_ERR_UNSUPPORTED, "mean-shift modes take L <= 64");
   Scratch sc(s);
@@ -210,8 +210,8 @@ slk_status mean_shift_loop(const float* x, int64_t n, int32_t d, const int32_t* 
   int it = 0;
   double shift = 0.0;
   for (it = 1; it <= max_iter; ++it) {
-    SLK_TRY(launch_unary(x, n, d, perm, nullptr, L, ldz, sigma2, bf16, A, nullptr, s, nullptr, cur));
-    SLK_TRY(launch_ms_step(x, n, d, perm, Z, A, L, ldz, bf16, cur, nxt, sh, pn, pd, den, s));
+    SLK_TRY(launch_unary(x, n, d, perm, nullptr, L, ldz, sigma2, umode, A, nullptr, s, nullptr, cur));
+    SLK_TRY(launch_ms_step(x, n, d, perm, Z, A, L, ldz, umode == kUnaryRounded, cur, nxt, sh, pn, pd, den, s));
     SLK_HIP(hipMemcpyAsync(h.data(), sh, sizeof(double) * L, hipMemcpyDeviceToHost, s));
     SLK_HIP(hipStreamSynchronize(s));
     shift = std::sqrt(*std::max_element(h.begin(), h.end()));
@@ -238,12 +238,12 @@ extern "C" slk_status slk_mean_shift(const float* x, int64_t n, int32_t d, const
   if (L < 1 || L > 64 || L > n) return fail(SLK_ERR_INVALID_ARG, "L must satisfy 1 <= L <= min(64, n)");
   if (!(sigma2 > 0.0) || !isfinite(sigma2)) return fail(SLK_ERR_INVALID_ARG, "sigma2 must be finite and > 0");
   if (!(tol >= 0.0) || max_iter < 1) return fail(SLK_ERR_INVALID_ARG, "need tol >= 0 and max_iter >= 1");
-  if (prec != SLK_PREC_FP32 && prec != SLK_PREC_BF16) return fail(SLK_ERR_INVALID_ARG, "unknown precision");
+  if (prec != SLK_PREC_FP32 && prec != SLK_PREC_BF16 && prec != SLK_PREC_BF16X) return fail(SLK_ERR_INVALID_ARG, "unknown precision");
   hipStream_t s = (hipStream_t)stream;
   if (modes_out != modes_in)
     SLK_HIP(hipMemcpyAsync(modes_out, modes_in, sizeof(float) * L * d, hipMemcpyDeviceToDevice, s));
   int32_t it = 0;
-  SLK_TRY(mean_shift_loop(x, n, d, nullptr, z, L, L, modes_out, sigma2, tol, max_iter, prec == SLK_PREC_BF16, s, &it,
+  SLK_TRY(mean_shift_loop(x, n, d, nullptr, z, L, L, modes_out, sigma2, tol, max_iter, unary_mode(prec), s, &it,
                           nullptr));
   if (iters_host) *iters_host = it;
   return SLK_OK;

@@ -86,7 +86,7 @@ extern "C" slk_status slk_predict(const float* x, int64_t n, int32_t d, const fl
   if (!(lambda >= 0.0) || !isfinite(lambda)) return fail(SLK_ERR_INVALID_ARG, "lambda must be finite and >= 0");
   if (!(sigma2 > 0.0) || !isfinite(sigma2)) return fail(SLK_ERR_INVALID_ARG, "sigma2 must be finite and > 0");
   if (method < SLK_KNN_AUTO || method > SLK_KNN_MFMA) return fail(SLK_ERR_INVALID_ARG, "unknown kNN method");
-  if (prec != SLK_PREC_FP32 && prec != SLK_PREC_BF16) return fail(SLK_ERR_INVALID_ARG, "unknown precision");
+  if (prec != SLK_PREC_FP32 && prec != SLK_PREC_BF16 && prec != SLK_PREC_BF16X) return fail(SLK_ERR_INVALID_ARG, "unknown precision");
   for (int l = 0; l < L; ++l)
     if (modes_host[l] < 0 || modes_host[l] >= n) return fail(SLK_ERR_INVALID_ARG, "mode index out of range");
   hipStream_t s = (hipStream_t)stream;
@@ -109,7 +109,7 @@ extern "C" slk_status slk_predict(const float* x, int64_t n, int32_t d, const fl
   }
   std::vector<int32_t> mh(modes_host, modes_host + L);
   SLK_HIP(hipMemcpyAsync(modes, mh.data(), sizeof(int32_t) * L, hipMemcpyHostToDevice, s));
-  SLK_TRY(launch_unary(y, m, d, nullptr, modes, L, L, sigma2, bf16, a, nullptr, s, x));
+  SLK_TRY(launch_unary(y, m, d, nullptr, modes, L, L, sigma2, unary_mode(prec), a, nullptr, s, x));
   hipLaunchKernelGGL(predict_kernel, dim3((unsigned)((m + 3) / 4)), dim3(kBlock), 0, s, a, z, nn, m, k, L,
                      (float)lambda, z_out, labels_out);
   SLK_LAUNCHED("predict_kernel");

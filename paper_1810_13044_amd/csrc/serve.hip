@@ -506,7 +506,7 @@ slk_status server_step(slk_server* sv) {
       Job* j = una[i];
       const slk_params& p = j->spec.params;
       ua[i] = unary_args(j->spec.x, j->spec.n, j->spec.d, j->g->perm, SD[j->slot].modes[j->cur], j->L, j->ldz, j->sigma2,
-                         p.prec == SLK_PREC_BF16, j->A, j->Z[0]);
+                         unary_mode(p.prec), j->A, j->Z[0]);
       us[i] = un_blocks;
       un_blocks += unary_grid(ua[i]);
       un_lds = std::max(un_lds, unary_lds(ua[i]));

@@ -25,7 +25,7 @@ template <int DC, bool VEC>
 __device__ __forceinline__ void unary_block(const UnaryArgs& u, int64_t bid) {
   const float* __restrict__ x = u.x;
   const int64_t n = u.n;
-  const int d = u.d, L = u.L, ldz = u.ldz, R = u.R, bf16 = u.bf16;
+  const int d = u.d, L = u.L, ldz = u.ldz, R = u.R, bf16 = u.bf16 == kUnaryRounded;
   const int32_t* __restrict__ perm = u.perm;
   const int32_t* __restrict__ modes = u.modes;
   const float inv2s2 = u.inv2s2;
@@ -184,15 +184,188 @@ __global__ __launch_bounds__(kBlock) void unary_kernel(UnaryArgs u) {
   unary_block<DC, VEC>(u, blockIdx.x);
 }
 
+// ------------------------------------------------------------------------------------------
+// BF16-X: the distance contraction on MFMA (u.bf16 == kUnaryMfma)
+// ------------------------------------------------------------------------------------------
+// ||x_p - m_l||^2 = ||y_p||^2 + ||w_l||^2 - 2 y_p.w_l with y = x - c, w = m - c for a reference
+// point c: the first row of the wave's tile of 32 rows.  With the locality order a tile's rows are
+// neighbours, so |y| is of the order of the within-cluster spread rather than of |x|, and the
+// cancellation of the expansion stays small.  y and w are split into three bf16 terms
+// (h = bf16(v), m = bf16(v - h), l = bf16(v - h - m), each conversion rounding to nearest even;
+// |v - h - m - l| <= 2^-27 |v|), and y.w = h.h + h.m + m.h + h.l + l.h + m.m on
+// v_mfma_f32_32x32x16_bf16 with FP32 accumulation (the dropped products and the residuals are at
+// most 3 * 2^-27 |y_j| |w_j| per coordinate, below the accumulation's own rounding).  The norms
+// are FP32 sums of y^2 and w^2.
+// A wave owns 32 rows and all modes (padded to T tiles of 32): for each 16 coordinates every
+// lane loads the 8 it feeds to the MFMA (row col of the tile and mode 32 t + col, coordinates
+// 8 half .. 8 half + 7), centres and splits them in registers; no LDS, no barrier.  The row
+// softmax runs on the accumulators: for row 8 (r / 4) + 4 half + r % 4 the 32 lanes of one half
+// hold modes 32 t + col, reduced with butterfly shuffles.
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+
+constexpr int kXRows = 128;   // rows per work-group (32 per wave)
+
+// v = h + m + l (+ residual), three bf16 vectors; returns sum v^2
+__device__ __forceinline__ float split8(const float (&v)[8], bf16x8& h, bf16x8& m, bf16x8& l) {
+  float s = 0.f;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const float x = v[i];
+    h[i] = (__bf16)x;
+    const float r1 = x - (float)h[i];
+    m[i] = (__bf16)r1;
+    l[i] = (__bf16)(r1 - (float)m[i]);
+    s += x * x;
+  }
+  return s;
+}
+
+// 8 coordinates k0 .. k0 + 7 of a row (zeros past d)
+template <bool VEC>
+__device__ __forceinline__ void load8(const float* __restrict__ row, int k0, int d, float (&v)[8]) {
+  if (VEC && k0 + 8 <= d) {
+    const float4 a = *reinterpret_cast<const float4*>(row + k0);
+    const float4 b = *reinterpret_cast<const float4*>(row + k0 + 4);
+    v[0] = a.x;
+    v[1] = a.y;
+    v[2] = a.z;
+    v[3] = a.w;
+    v[4] = b.x;
+    v[5] = b.y;
+    v[6] = b.z;
+    v[7] = b.w;
+  } else {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = k0 + i < d ? row[k0 + i] : 0.f;
+  }
+}
+
+template <int T, bool VEC>
+__device__ __forceinline__ void unary_mfma_block(const UnaryArgs& u, int64_t bid) {
+  const int64_t n = u.n;
+  const int d = u.d, L = u.L, ldz = u.ldz;
+  const int32_t* __restrict__ perm = u.perm;
+  const float* __restrict__ xm = u.xm ? u.xm : u.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5, col = lane & 31;
+  const int64_t t0 = bid * kXRows + 32 * wave;  // the wave's first row (internal order)
+  if (t0 >= n) return;                          // the whole wave leaves together
+  const int nr = (int)min<int64_t>(32, n - t0);
+  const float* cref = u.x + (perm ? perm[t0] : t0) * (int64_t)d;
+  const float* xr = u.x + (perm ? perm[t0 + min(col, nr - 1)] : t0 + min(col, nr - 1)) * (int64_t)d;
+  const float* mr[T];
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    const int l = 32 * t + col;
+    mr[t] = l < L ? (u.mvec ? u.mvec + (int64_t)l * d : xm + (int64_t)u.modes[l] * d) : nullptr;
+  }
+  f32x16 acc[T];
+#pragma unroll
+  for (int t = 0; t < T; ++t) acc[t] = f32x16{};
+  float ny = 0.f, nw[T];
+#pragma unroll
+  for (int t = 0; t < T; ++t) nw[t] = 0.f;
+  // the trip count is the same for both halves (every lane takes part in every MFMA); the
+  // coordinates past d load as zeros
+  for (int k = 0; k < d; k += 16) {
+    const int k0 = k + 8 * half;
+    float c[8], v[8];
+    load8<VEC>(cref, k0, d, c);
+    load8<VEC>(xr, k0, d, v);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = col < nr ? v[i] - c[i] : 0.f;
+    bf16x8 ah, am, al;
+    ny += split8(v, ah, am, al);
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      float w[8];
+      if (mr[t]) {
+        load8<VEC>(mr[t], k0, d, w);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) w[i] -= c[i];
+      } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) w[i] = 0.f;
+      }
+      bf16x8 bh, bm, bl;
+      nw[t] += split8(w, bh, bm, bl);
+      acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bm, acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bh, acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bm, acc[t], 0, 0, 0);
+    }
+  }
+  // the two halves hold coordinates 16 s + 0..7 and 16 s + 8..15: add the partner's share
+  ny += __shfl_xor(ny, 32);
+#pragma unroll
+  for (int t = 0; t < T; ++t) nw[t] += __shfl_xor(nw[t], 32);
+  // accumulator entry r of lane (half, col): row 8 (r / 4) + 4 half + r % 4, mode 32 t + col
+  float a[T][16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int row = 8 * (r >> 2) + 4 * half + (r & 3);
+    const float nyr = __shfl(ny, row);
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const float d2 = fmaxf(nyr + nw[t] - 2.f * acc[t][r], 0.f);
+      a[t][r] = 32 * t + col < L ? expf(-d2 * u.inv2s2) : -INFINITY;
+    }
+  }
+  // row softmax: max and sum over the modes of each row (registers, then the 32 lanes of a half)
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    float m = a[0][r];
+#pragma unroll
+    for (int t = 1; t < T; ++t) m = fmaxf(m, a[t][r]);
+#pragma unroll
+    for (int off = 16; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 32));
+    float e[T], sum = 0.f;
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      e[t] = 32 * t + col < L ? expf(a[t][r] - m) : 0.f;
+      sum += e[t];
+    }
+#pragma unroll
+    for (int off = 16; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 32);
+    const int row = 8 * (r >> 2) + 4 * half + (r & 3);
+    if (row < nr) {
+      const int64_t orow = t0 + row;
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        const int l = 32 * t + col;
+        if (l < ldz) {
+          const bool ok = l < L;
+          if (u.A) u.A[orow * ldz + l] = ok ? a[t][r] : 0.f;
+          if (u.Z0) u.Z0[orow * ldz + l] = ok ? e[t] / sum : 0.f;
+        }
+      }
+    }
+  }
+}
+
+template <int T, bool VEC>
+__global__ __launch_bounds__(kBlock) void unary_mfma_kernel(UnaryArgs u) {
+  unary_mfma_block<T, VEC>(u, blockIdx.x);
+}
+
 __global__ __launch_bounds__(kBlock) void unary_packed(const UnaryArgs* __restrict__ jobs,
                                                        const int32_t* __restrict__ start, int njobs) {
   const int j = job_of(start, njobs, blockIdx.x);
   const UnaryArgs& u = jobs[j];
   // 16-byte staging when the job's rows allow it (d % 4 == 0, x 16-byte aligned)
-  if ((u.d & 3) == 0 && ((uintptr_t)u.x & 15) == 0 && ((uintptr_t)(u.xm ? u.xm : u.x) & 15) == 0 &&
-      ((uintptr_t)u.mvec & 15) == 0)
-    unary_block<32, true>(u, (int64_t)blockIdx.x - start[j]);
-  else unary_block<32, false>(u, (int64_t)blockIdx.x - start[j]);
+  const bool vec = (u.d & 3) == 0 && ((uintptr_t)u.x & 15) == 0 && ((uintptr_t)(u.xm ? u.xm : u.x) & 15) == 0 &&
+                   ((uintptr_t)u.mvec & 15) == 0;
+  const int64_t b = (int64_t)blockIdx.x - start[j];
+  if (u.bf16 == kUnaryMfma) {
+    if (vec) unary_mfma_block<2, true>(u, b);
+    else unary_mfma_block<2, false>(u, b);
+  } else if (vec) {
+    unary_block<32, true>(u, b);
+  } else {
+    unary_block<32, false>(u, b);
+  }
 }
 
 }  // namespace
@@ -205,7 +378,7 @@ UnaryArgs unary_args(const float* x, int64_t n, int32_t d, const int32_t* perm, 
   u.d = d;
   u.L = L;
   u.ldz = ldz;
-  u.R = L <= 128 ? 64 : 32;
+  u.R = bf16 == kUnaryMfma ? kXRows : L <= 128 ? 64 : 32;
   u.perm = perm;
   u.modes = modes_dev;
   u.inv2s2 = (float)(1.0 / (2.0 * sigma2));
@@ -218,6 +391,7 @@ UnaryArgs unary_args(const float* x, int64_t n, int32_t d, const int32_t* perm, 
 int unary_grid(const UnaryArgs& u) { return (int)((u.n + u.R - 1) / u.R); }
 
 size_t unary_lds(const UnaryArgs& u) {
+  if (u.bf16 == kUnaryMfma) return 0;
   const int DC = u.L <= 128 ? 32 : 16;
   const int MG = (u.L + kUT - 1) / kUT;
   const size_t staging = (size_t)DC * (u.R + 4) + (size_t)DC * (MG * kUT + 4);
@@ -239,7 +413,18 @@ slk_status launch_unary(const float* x, int64_t n, int32_t d, const int32_t* per
   const size_t lds = unary_lds(u);
   const dim3 grid((unsigned)unary_grid(u));
   const bool vec = vec_ok(u);
-  if (L <= 128) {
+  if (bf16 == kUnaryMfma) {
+#define SLK_UNARY_MFMA(T_)                                                                         \
+  do {                                                                                             \
+    if (vec) hipLaunchKernelGGL((unary_mfma_kernel<T_, true>), grid, dim3(kBlock), 0, s, u);       \
+    else hipLaunchKernelGGL((unary_mfma_kernel<T_, false>), grid, dim3(kBlock), 0, s, u);          \
+  } while (0)
+    if (L <= 32) SLK_UNARY_MFMA(1);
+    else if (L <= 64) SLK_UNARY_MFMA(2);
+    else if (L <= 128) SLK_UNARY_MFMA(4);
+    else SLK_UNARY_MFMA(8);
+#undef SLK_UNARY_MFMA
+  } else if (L <= 128) {
     if (vec) hipLaunchKernelGGL((unary_kernel<32, true>), grid, dim3(kBlock), lds, s, u);
     else hipLaunchKernelGGL((unary_kernel<32, false>), grid, dim3(kBlock), lds, s, u);
   } else {
