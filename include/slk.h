@@ -109,6 +109,25 @@ slk_status slk_knn_opts_default(slk_knn_opts* opts);
 slk_status slk_build_knn(const float* x, int64_t n, int32_t d, const slk_knn_opts* opts,
                          void* stream, slk_graph** g_out);
 
+/* One problem of slk_build_knn_batched. */
+typedef struct {
+  const float* x;     /* n x d float32 points (device)                                      */
+  int64_t n;
+  int32_t d;
+  int32_t reserved;   /* 0                                                                  */
+  slk_knn_opts opts;
+} slk_knn_item;
+
+/*
+ * slk_build_knn for several independent problems at once (the batched form's graph build):
+ * graphs_out[i] receives the graph of items[i], identical to slk_build_knn's for the same
+ * arguments (lists, distances, CSR, sigma^2).  The problems that take the exact search (method
+ * EXACT, or AUTO with n^2 d <= 4e9) share ONE launch of that search, each problem keeping its own
+ * work-groups; the others are built one by one.  On any failure no graph is returned (every
+ * graphs_out[i] is NULL).  Synchronises `stream`.
+ */
+slk_status slk_build_knn_batched(const slk_knn_item* items, int32_t count, void* stream, slk_graph** graphs_out);
+
 /*
  * Build the graph from given kNN lists (device): knn_idx n x k int32 (original indices,
  * each row free of p itself), knn_d2 n x k float64 (their squared distances, used only
@@ -421,12 +440,16 @@ typedef struct {
                                the free memory when the server is created)                     */
   int32_t builders;         /* worker threads building admitted jobs' graphs, each on its own
                                stream, while the resident jobs step; 1 <= builders <= 8        */
-  int32_t reserved;
+  int32_t graph_replay;     /* 1: a step's launch sequence is captured into a HIP graph the
+                               second time its shape (kernels, grids, argument layout) occurs,
+                               and replayed whenever that shape recurs; 0: plain launches.
+                               The same kernels run on the same arguments either way.          */
 } slk_server_opts;
 
 typedef struct slk_server slk_server;
 
-/* Fill *o with defaults: max_jobs 64, passes_per_step 4, memory_budget 0, builders 3. */
+/* Fill *o with defaults: max_jobs 64, passes_per_step 4, memory_budget 0, builders 3,
+   graph_replay 1. */
 slk_status slk_server_opts_default(slk_server_opts* o);
 
 /* Create a server that runs on `stream` (device = the current device).  Release with
@@ -446,6 +469,16 @@ slk_status slk_server_submit(slk_server* sv, const slk_job* job, int64_t* ticket
    the resident and the waiting job counts (queued or in a graph build) after the step. */
 slk_status slk_server_step(slk_server* sv, int64_t* done_host, int32_t cap, int32_t* n_done_host,
                            int32_t* n_active_host, int32_t* n_queued_host);
+
+typedef struct {
+  int64_t steps;            /* slk_server_step calls that ran resident jobs                       */
+  int64_t graph_launches;   /* steps replayed from a captured HIP graph                           */
+  int64_t graph_captures;   /* step shapes captured                                               */
+  int64_t grouped_builds;   /* shared launches of the exact kNN search for several jobs           */
+} slk_server_stats_t;
+
+/* Counters of the server's work so far (host). */
+slk_status slk_server_stats(const slk_server* sv, slk_server_stats_t* out_host);
 
 void slk_server_destroy(slk_server* sv);
 
@@ -474,6 +507,31 @@ slk_status slk_timing_read(const char* kernel, int64_t* launches_host, double* t
    For callers that must bound the device memory the library holds between calls.
    SLK_ERR_DEVICE if the pool cannot be created or trimmed. */
 slk_status slk_pool_trim(void);
+
+/*
+ * Tile shapes.  The z-update and final pass walk each work-group's rows in tiles of
+ * wave_steps row batches per wave; the exact kNN puts knn_exact_width queries in a work-group.
+ * They come from a table the project's autotuner (tune.py) measured on the GPU, keyed by the row
+ * count and the lane-group class of L, and every call - single fits, assignments, the served form
+ * - takes them from there, so a job's results are the same wherever it runs.  Tile shapes change
+ * no result except the order of the relaxed bound's FP64 partial sums.
+ */
+typedef struct {
+  int32_t wave_steps;       /* row batches per wave in a z-update tile (L <= 64; 4 above)       */
+  int32_t knn_exact_width;  /* queries per work-group of the exact kNN over n rows              */
+  int32_t knn_exact;        /* 1 if the AUTO kNN method takes the exact search for (n, d)        */
+  int32_t reserved;
+} slk_tune_params;
+
+/* The tile shapes a problem of n points in d dimensions with L clusters gets (host output). */
+slk_status slk_tune_lookup(int64_t n, int32_t d, int32_t L, slk_tune_params* out_host);
+
+/* For the autotuner's measurements only: force the z-update's wave_steps (1, 2, 4 or 8) for every
+   later call in the process, or go back to the table (0).  Not for use while calls are running. */
+slk_status slk_tune_override(int32_t wave_steps);
+
+/* Where the table came from (the autotuner's run: device and date), for reports. */
+const char* slk_tune_source(void);
 
 /* Text for the last non-OK status returned on this thread. */
 const char* slk_last_error(void);

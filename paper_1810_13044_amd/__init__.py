@@ -91,6 +91,28 @@ class Graph:
         return cls(h)
 
     @classmethod
+    def build_knn_batched(cls, problems):
+        """Graphs of several problems [{"x": tensor, "k": .., "reorder": .., "method": .., "prec": ..}, ...]
+        in one call (slk_build_knn_batched); the exact searches share one launch."""
+        lib = _lib.load()
+        torch = _torch()
+        items = (_lib.KnnItem * len(problems))()
+        for i, pr in enumerate(problems):
+            x = pr["x"]
+            n, d = x.shape
+            o = _lib.KnnOpts()
+            _lib.check(lib.slk_knn_opts_default(C.byref(o)))
+            o.k = int(pr.get("k", 10))
+            o.reorder = int(bool(pr.get("reorder", False)))
+            o.candidates = int(pr.get("candidates", 0))
+            o.method = {"auto": _lib.KNN_AUTO, "exact": _lib.KNN_EXACT, "mfma": _lib.KNN_MFMA}[pr.get("method", "auto")]
+            o.prec = _prec(pr.get("prec", "fp32"))
+            items[i] = _lib.KnnItem(_dev(x, torch.float32, "x").value, n, d, 0, o)
+        hs = (C.c_void_p * len(problems))()
+        _lib.check(lib.slk_build_knn_batched(items, len(problems), _stream(), hs))
+        return [cls(C.c_void_p(h)) for h in hs]
+
+    @classmethod
     def from_knn(cls, knn_idx, knn_d2=None, reorder=False):
         torch = _torch()
         lib = _lib.load()
@@ -255,6 +277,22 @@ def inner_step_noalloc_max_rows(L):
     return int(_lib.load().slk_inner_step_noalloc_max_rows(int(L)))
 
 
+def tune_lookup(n, d, L):
+    """Tile shapes the library takes for a problem of n points, d dimensions and L clusters."""
+    t = _lib.TuneParams()
+    _lib.check(_lib.load().slk_tune_lookup(int(n), int(d), int(L), C.byref(t)))
+    return {f: getattr(t, f) for f, _ in t._fields_ if f != "reserved"}
+
+
+def tune_override(wave_steps):
+    """Measurement only: force the z-update's wave_steps (0 = back to the table)."""
+    _lib.check(_lib.load().slk_tune_override(int(wave_steps)))
+
+
+def tune_source():
+    return _lib.load().slk_tune_source().decode()
+
+
 def predict(x, z, modes, y, k=10, lam=1.0, sigma2=0.0, graph=None, method="auto", prec="fp32"):
     """Out-of-sample assignment of the queries y (m x d) against a fit (x, z, modes).
     sigma2 <= 0 takes the estimate of `graph`.  Returns (z_y, labels_y, knn_idx)."""
@@ -414,11 +452,12 @@ class Server:
     admit what fits and advance every resident job; finished jobs' outcomes are returned by
     step() and kept in .done."""
 
-    def __init__(self, max_jobs=64, passes_per_step=4, memory_budget=0, builders=0):
+    def __init__(self, max_jobs=64, passes_per_step=4, memory_budget=0, builders=0, graph_replay=True):
         self._lib = _lib.load()
         o = _lib.ServerOpts()
         _lib.check(self._lib.slk_server_opts_default(C.byref(o)))
         o.max_jobs, o.passes_per_step, o.memory_budget = int(max_jobs), int(passes_per_step), int(memory_budget)
+        o.graph_replay = int(bool(graph_replay))
         if builders:
             o.builders = int(builders)
         h = C.c_void_p()
@@ -450,6 +489,11 @@ class Server:
 
     def pending(self) -> int:
         return len(self._jobs)
+
+    def stats(self):
+        st = _lib.ServerStats()
+        _lib.check(self._lib.slk_server_stats(self._h, C.byref(st)))
+        return {f: getattr(st, f) for f, _ in st._fields_}
 
     def close(self):
         if self._h:

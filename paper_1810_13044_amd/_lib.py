@@ -66,7 +66,21 @@ class Job(C.Structure):
 
 class ServerOpts(C.Structure):
     _fields_ = [("max_jobs", C.c_int32), ("passes_per_step", C.c_int32), ("memory_budget", C.c_int64),
-                ("builders", C.c_int32), ("reserved", C.c_int32)]
+                ("builders", C.c_int32), ("graph_replay", C.c_int32)]
+
+
+class TuneParams(C.Structure):
+    _fields_ = [("wave_steps", C.c_int32), ("knn_exact_width", C.c_int32), ("knn_exact", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("graph_launches", C.c_int64), ("graph_captures", C.c_int64),
+                ("grouped_builds", C.c_int64)]
+
+
+class KnnItem(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("n", C.c_int64), ("d", C.c_int32), ("reserved", C.c_int32), ("opts", KnnOpts)]
 
 
 _lib = None
@@ -117,12 +131,17 @@ def load(path: str = LIB_PATH):
     lib.slk_graph_destroy.restype = None
     lib.slk_last_error.restype = C.c_char_p
     lib.slk_version.restype = C.c_char_p
+    lib.slk_tune_source.restype = C.c_char_p
     srv = {
         "slk_server_opts_default": [C.POINTER(ServerOpts)],
         "slk_server_create": [C.POINTER(ServerOpts), P, C.POINTER(P)],
         "slk_server_submit": [P, C.POINTER(Job), C.POINTER(C.c_int64)],
         "slk_server_step": [P, P, I32, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32)],
         "slk_fit_batched": [C.POINTER(Job), I32, C.POINTER(ServerOpts), P],
+        "slk_server_stats": [P, C.POINTER(ServerStats)],
+        "slk_build_knn_batched": [C.POINTER(KnnItem), I32, P, C.POINTER(P)],
+        "slk_tune_lookup": [I64, I32, I32, C.POINTER(TuneParams)],
+        "slk_tune_override": [I32],
     }
     for name, args in srv.items():
         fn = getattr(lib, name)

@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libslk.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 SOURCES = ["api.hip", "iter.hip", "unary.hip", "graph.hip", "knn_mfma.hip", "serve.hip", "predict.hip", "meanshift.hip",
-           "kmeanspp.hip", "dmode.hip", "noalloc.hip"]
+           "kmeanspp.hip", "dmode.hip", "noalloc.hip", "tune.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 FLAGS = [

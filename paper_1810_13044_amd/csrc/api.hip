@@ -624,7 +624,7 @@ slk_status prepare_col_off(const slk_graph* g, int32_t L, Scratch& sc, uint32_t*
 slk_status alloc_work(Scratch& sc, const slk_graph* g, int32_t L, int trace_cap, Work& w) {
   const int64_t n = g->n;
   const int ldz = ldz_for(L);
-  w.grid = iter_grid(n, L, heavy_rows_for(g, L));
+  w.grid = iter_grid(n, L, heavy_rows_for(g, L), tune_wave_steps(n, L));
   w.egrid = energy_grid(n, g->n_heavy);
   SLK_TRY(sc.get(&w.A, n * ldz));
   SLK_TRY(sc.get(&w.Z[0], n * ldz));
@@ -674,6 +674,7 @@ IterArgs make_iter(const slk_graph* g, const Work& w, int64_t n, int32_t L, cons
   a.trace = w.trace;
   a.bound_out = nullptr;
   a.mirror = nullptr;
+  a.wsteps = tune_wave_steps(n, L);
   set_heavy(a, g, L);
   return a;
 }
@@ -864,6 +865,22 @@ void set_heavy(EnergyArgs& e, const slk_graph* g) {
 
 void destroy_graph_on(slk_graph* g, hipStream_t s) { free_graph(g, s); }
 
+slk_status check_knn_item(const float* x, int64_t n, int32_t d, const slk_knn_opts& o) {
+  SLK_TRY(check_points(x, n, d));
+  if (o.k < 1 || o.k > 64 || o.k >= n) return fail(SLK_ERR_INVALID_ARG, "k must satisfy 1 <= k <= 64 and k < n");
+  if (o.prec != SLK_PREC_FP32 && o.prec != SLK_PREC_BF16 && o.prec != SLK_PREC_BF16X)
+    return fail(SLK_ERR_INVALID_ARG, "unknown precision");
+  if (o.method < SLK_KNN_AUTO || o.method > SLK_KNN_MFMA) return fail(SLK_ERR_INVALID_ARG, "unknown kNN method");
+  if (o.candidates < 0) return fail(SLK_ERR_INVALID_ARG, "candidates must be >= 0");
+  if ((int64_t)n * 2 * o.k >= (int64_t)INT32_MAX) return fail(SLK_ERR_INVALID_ARG, "n * 2k exceeds the CSR index range");
+  return SLK_OK;
+}
+
+bool knn_takes_exact(int64_t n, int32_t d, const slk_knn_opts& o) {
+  return o.method == SLK_KNN_EXACT || (o.method == SLK_KNN_AUTO && (double)n * (double)n * (double)d <= 4.0e9);
+}
+
+
 }  // namespace slk
 
 using namespace slk;
@@ -956,7 +973,7 @@ slk_status slk_build_knn(const float* x, int64_t n, int32_t d, const slk_knn_opt
   SLK_HIP(graph_alloc((void**)&g->knn_d2, sizeof(double) * n * o.k, s));
   const int bf16 = o.prec == SLK_PREC_BF16;
   int method = o.method;
-  if (method == SLK_KNN_AUTO) method = ((double)n * (double)n * (double)d <= 4.0e9) ? SLK_KNN_EXACT : SLK_KNN_MFMA;
+  if (method == SLK_KNN_AUTO) method = knn_takes_exact(n, d, o) ? SLK_KNN_EXACT : SLK_KNN_MFMA;
   if (method == SLK_KNN_EXACT) {
     SLK_TRY(knn_exact(x, n, d, o.k, bf16, nullptr, n, g->knn_idx, g->knn_d2, s));
     g->rows_certified = 0;
@@ -968,6 +985,59 @@ slk_status slk_build_knn(const float* x, int64_t n, int32_t d, const slk_knn_opt
   }
   SLK_TRY(finish_from_knn(g, o.reorder, s));
   *g_out = gg.release();
+  return SLK_OK;
+}
+
+slk_status slk_build_knn_batched(const slk_knn_item* items, int32_t count, void* stream, slk_graph** graphs_out) {
+  if (!items || !graphs_out || count < 0) return fail(SLK_ERR_INVALID_ARG, "NULL argument or negative count");
+  for (int i = 0; i < count; ++i) graphs_out[i] = nullptr;
+  for (int i = 0; i < count; ++i) {
+    if (items[i].reserved != 0) return fail(SLK_ERR_INVALID_ARG, "reserved must be 0");
+    SLK_TRY(check_knn_item(items[i].x, items[i].n, items[i].d, items[i].opts));
+  }
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<slk_graph*> made(count, nullptr);
+  auto fail_all = [&](slk_status st) {
+    for (slk_graph* g : made) free_graph(g, s);
+    return st;
+  };
+  std::vector<KnnExactJob> ex;
+  std::vector<int> ex_item;
+  for (int i = 0; i < count; ++i) {
+    const slk_knn_item& it = items[i];
+    const slk_knn_opts& o = it.opts;
+    if (!knn_takes_exact(it.n, it.d, o)) {
+      const slk_status st = slk_build_knn(it.x, it.n, it.d, &o, stream, &made[i]);
+      if (st != SLK_OK) return fail_all(st);
+      continue;
+    }
+    slk_status st = check_finite(it.x, it.n * (int64_t)it.d, s);
+    if (st != SLK_OK) return fail_all(st);
+    slk_graph* g = new slk_graph();
+    made[i] = g;
+    g->pooled = graph_pool();
+    if (hipGetDevice(&g->device) != hipSuccess) return fail_all(fail(SLK_ERR_DEVICE, "hipGetDevice"));
+    g->n = it.n;
+    g->k = o.k;
+    if (graph_alloc((void**)&g->knn_idx, sizeof(int32_t) * it.n * o.k, s) != hipSuccess ||
+        graph_alloc((void**)&g->knn_d2, sizeof(double) * it.n * o.k, s) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail_all(fail(SLK_ERR_OUT_OF_MEMORY, "kNN lists"));
+    }
+    g->rows_certified = 0;
+    g->rows_fallback = it.n;
+    ex.push_back(KnnExactJob{it.x, it.n, it.d, o.k, o.prec == SLK_PREC_BF16 ? 1 : 0, g->knn_idx, g->knn_d2});
+    ex_item.push_back(i);
+  }
+  slk_status st = knn_exact_group(ex.data(), (int)ex.size(), s);
+  if (st != SLK_OK) return fail_all(st);
+  for (size_t e = 0; e < ex_item.size(); ++e) {
+    const int i = ex_item[e];
+    st = finish_from_knn(made[i], items[i].opts.reorder, s);
+    if (st != SLK_OK) return fail_all(st);
+  }
+  SLK_HIP(hipStreamSynchronize(s));
+  for (int i = 0; i < count; ++i) graphs_out[i] = made[i];
   return SLK_OK;
 }
 
@@ -1131,7 +1201,7 @@ slk_status slk_inner_step(const slk_graph* g, int32_t L, const float* a, const f
   p.delta = delta;
   p.pairwise_scale = pairwise_scale;
   Work w;
-  w.grid = iter_grid(n, L, heavy_rows_for(g, L));
+  w.grid = iter_grid(n, L, heavy_rows_for(g, L), tune_wave_steps(n, L));
   SLK_TRY(sc.get(&w.partial, w.grid));
   SLK_TRY(sc.get(&w.state, 1));
   SLK_TRY(sc.get(&w.bound, 1));

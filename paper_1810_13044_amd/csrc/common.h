@@ -210,6 +210,7 @@ struct IterArgs {
   int32_t heavy_deg;     // rows above this degree belong to the heavy work-groups
   const int32_t* zperm;  // scalar path only: rows of A, Zin, Zout are in the caller's order, row
                          // zperm[r] holding internal row r (null = the internal order itself)
+  int32_t wsteps;        // float4 path: row batches per wave in a tile (tune_wave_steps; 0 = 4)
 };
 
 struct FinalArgs {
@@ -293,7 +294,11 @@ slk_status launch_final_packed(int G, const FinalArgs* jobs, const int32_t* star
                                hipStream_t s);
 slk_status launch_reduce_packed(const ReduceJob* jobs, int njobs, hipStream_t s);
 slk_status launch_mode_reduce_packed(const ModeJob* jobs, const int32_t* start, int njobs, int blocks, hipStream_t s);
-int iter_grid(int64_t n, int32_t L, int64_t n_heavy);
+int iter_grid(int64_t n, int32_t L, int64_t n_heavy, int32_t wsteps);
+// Tile shapes from the autotuned table (tune.hip): row batches per wave of the float4 z-update and
+// final pass for a problem of n rows and L clusters; queries per work-group of the exact kNN.
+int32_t tune_wave_steps(int64_t n, int32_t L);
+int32_t tune_knn_width(int64_t n, int32_t d, int64_t n_rows);
 slk_status launch_iter(const IterArgs& a, int grid, hipStream_t s);
 // The row-per-lane-group z-update for any L (no heavy-row split, no col_off), on rows of stride
 // a.ldz, optionally in the caller's order (a.zperm), and its pass reduction.
@@ -341,6 +346,20 @@ slk_status launch_energy_packed(const EnergyArgs* jobs, const int32_t* start, in
 slk_status mean_shift_loop(const float* x, int64_t n, int32_t d, const int32_t* perm, const float* Z, int32_t L,
                            int32_t ldz, float* m, double sigma2, double tol, int32_t max_iter, int32_t umode,
                            hipStream_t s, int32_t* iters, double* last_shift);
+
+// One problem of a grouped exact kNN search (all rows of x are queries, the point itself excluded).
+struct KnnExactJob {
+  const float* x;
+  int64_t n;
+  int32_t d, k, bf16;
+  int32_t* out_idx;   // n x k
+  double* out_d2;     // n x k
+};
+// The exact search of several problems in one launch (graph.hip); lists identical to knn_exact's.
+slk_status knn_exact_group(const KnnExactJob* jobs_host, int njobs, hipStream_t s);
+
+// The kNN method AUTO resolves to: the exact search when n^2 d <= 4e9 (api.hip).
+bool knn_takes_exact(int64_t n, int32_t d, const slk_knn_opts& o);
 
 // argument checks and per-graph settings shared by the C ABI and the served form (api.hip)
 slk_status check_points(const float* x, int64_t n, int32_t d);

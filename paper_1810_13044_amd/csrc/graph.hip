@@ -42,8 +42,6 @@ __device__ __forceinline__ bool key_less(double d0, int q0, double d1, int q1) {
 // and twice the blocks (less LDS each, more per CU) hide their latency, or while the wide grid
 // would have fewer than two blocks per CU; otherwise 8, halving the key reads that go past L2.
 constexpr int kQBWide = 8, kQBNarrow = 4;
-constexpr double kQBNarrowKeyBytes = 4.0 * 1024 * 1024;
-constexpr int64_t kQBNarrowMaxRows = 8 * 512;
 constexpr int kQDc = 256;   // query coordinates staged per chunk
 constexpr int kSortP = 512; // bitonic width of a merge (k + 256 <= 320 entries)
 
@@ -73,10 +71,10 @@ __device__ void block_bitonic(double* kd, int* kq, int P) {
 // Queries are rows of x (rows[] or all, the point itself excluded) or, with y, the rows of y
 // (nothing excluded).  The result does not depend on kQB.
 template <int kQB>
-__global__ __launch_bounds__(kBlock) void knn_exact_kernel(const float* __restrict__ x, int64_t n, int d, int k,
-                                                           int bf16, const int32_t* __restrict__ rows,
-                                                           int64_t n_rows, int32_t* __restrict__ out_idx,
-                                                           double* __restrict__ out_d2, const float* __restrict__ y) {
+__device__ __forceinline__ void knn_exact_block(const float* __restrict__ x, int64_t n, int d, int k, int bf16,
+                                                const int32_t* __restrict__ rows, int64_t n_rows,
+                                                int32_t* __restrict__ out_idx, double* __restrict__ out_d2,
+                                                const float* __restrict__ y, int64_t bid) {
   const float* __restrict__ qsrc = y ? y : x;
   const bool vec4 = (d & 3) == 0 && ((uintptr_t)x & 15) == 0;
   __shared__ double qs[kQB][kQDc];
@@ -88,7 +86,7 @@ __global__ __launch_bounds__(kBlock) void knn_exact_kernel(const float* __restri
   __shared__ double sd[kSortP];
   __shared__ int sq[kSortP];
   const int tid = threadIdx.x;
-  const int64_t r0 = (int64_t)blockIdx.x * kQB;
+  const int64_t r0 = bid * kQB;
   const int nq = (int)min<int64_t>(kQB, n_rows - r0);
   __shared__ int64_t qrow[kQB];
   if (tid < kQB) qrow[tid] = (tid < nq) ? (rows ? rows[r0 + tid] : r0 + tid) : -1;
@@ -190,6 +188,25 @@ __global__ __launch_bounds__(kBlock) void knn_exact_kernel(const float* __restri
     out_idx[qrow[i] * k + j] = lq[i][j];
     out_d2[qrow[i] * k + j] = ld[i][j];
   }
+}
+
+template <int kQB>
+__global__ __launch_bounds__(kBlock) void knn_exact_kernel(const float* __restrict__ x, int64_t n, int d, int k,
+                                                           int bf16, const int32_t* __restrict__ rows,
+                                                           int64_t n_rows, int32_t* __restrict__ out_idx,
+                                                           double* __restrict__ out_d2, const float* __restrict__ y) {
+  knn_exact_block<kQB>(x, n, d, k, bf16, rows, n_rows, out_idx, out_d2, y, blockIdx.x);
+}
+
+// Several problems in one launch: start[j] is the first work-group of job j (njobs + 1 entries);
+// every job's work-groups run exactly the single-problem kernel's code on its own points.
+template <int kQB>
+__global__ __launch_bounds__(kBlock) void knn_exact_packed(const KnnExactJob* __restrict__ jobs,
+                                                           const int32_t* __restrict__ start, int njobs) {
+  const int j = job_of(start, njobs, blockIdx.x);
+  const KnnExactJob& J = jobs[j];
+  knn_exact_block<kQB>(J.x, J.n, J.d, J.k, J.bf16, nullptr, J.n, J.out_idx, J.out_d2, nullptr,
+                       (int64_t)blockIdx.x - start[j]);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -486,7 +503,7 @@ slk_status knn_exact(const float* x, int64_t n, int32_t d, int32_t k, int32_t bf
                      int64_t n_rows, int32_t* out_idx, double* out_d2, hipStream_t s, const float* y) {
   if (n_rows <= 0) return SLK_OK;
   if (k > 64) return fail(SLK_ERR_INVALID_ARG, "k > 64");
-  if ((double)n * d * sizeof(float) <= kQBNarrowKeyBytes || n_rows < kQBNarrowMaxRows) {
+  if (tune_knn_width(n, d, n_rows) == kQBNarrow) {
     const int64_t grid = (n_rows + kQBNarrow - 1) / kQBNarrow;
     hipLaunchKernelGGL(knn_exact_kernel<kQBNarrow>, dim3((unsigned)grid), dim3(kBlock), 0, s, x, n, d, k, bf16, rows,
                        n_rows, out_idx, out_d2, y);
@@ -496,6 +513,31 @@ slk_status knn_exact(const float* x, int64_t n, int32_t d, int32_t k, int32_t bf
                        n_rows, out_idx, out_d2, y);
   }
   SLK_LAUNCHED("knn_exact_kernel");
+  return SLK_OK;
+}
+
+slk_status knn_exact_group(const KnnExactJob* jobs_host, int njobs, hipStream_t s) {
+  if (njobs <= 0) return SLK_OK;
+  std::vector<int32_t> start(njobs + 1);
+  int64_t b = 0;
+  for (int j = 0; j < njobs; ++j) {
+    if (jobs_host[j].k > 64) return fail(SLK_ERR_INVALID_ARG, "k > 64");
+    start[j] = (int32_t)b;
+    b += (jobs_host[j].n + kQBNarrow - 1) / kQBNarrow;
+    if (b >= (int64_t)INT32_MAX) return fail(SLK_ERR_INVALID_ARG, "too many rows in one grouped search");
+  }
+  start[njobs] = (int32_t)b;
+  Scratch sc(s);
+  KnnExactJob* jd;
+  int32_t* sd;
+  SLK_TRY(sc.get(&jd, njobs));
+  SLK_TRY(sc.get(&sd, njobs + 1));
+  SLK_HIP(hipMemcpyAsync(jd, jobs_host, sizeof(KnnExactJob) * njobs, hipMemcpyHostToDevice, s));
+  SLK_HIP(hipMemcpyAsync(sd, start.data(), sizeof(int32_t) * (njobs + 1), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(knn_exact_packed<kQBNarrow>, dim3((unsigned)b), dim3(kBlock), 0, s, jd, sd, njobs);
+  SLK_LAUNCHED("knn_exact_packed");
+  // the host arrays above are released when this returns: wait for the copies
+  SLK_HIP(hipStreamSynchronize(s));
   return SLK_OK;
 }
 

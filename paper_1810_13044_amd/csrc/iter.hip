@@ -223,6 +223,55 @@ __device__ __forceinline__ void block_partial(double* partial, int64_t bid, doub
   }
 }
 
+// Fixed-order sum of the bound partials of one z-update, then the loop bookkeeping: bound
+// trace, convergence test (relative change of the bound), pass counter.  A no-op once the
+// loop is done, like the z-updates queued after it.  Each thread sums a strided slice with
+// kRedUnroll independent accumulators (so the loads are all in flight together), then the
+// block combines the slices in a fixed tree.  Run by a whole block of NT threads.
+constexpr int kRedBlock = 1024;
+constexpr int kRedUnroll = 8;
+template <int NT>
+__device__ __forceinline__ void reduce_pass(const double* __restrict__ partial, int nparts, IterState* st,
+                                            double* trace, double* bound_out, IterState* mirror) {
+  if (st->done) return;
+  __shared__ double red[NT];
+  const int tid = threadIdx.x;
+  double acc[kRedUnroll];
+#pragma unroll
+  for (int u = 0; u < kRedUnroll; ++u) acc[u] = 0.0;
+  for (int i0 = tid; i0 < nparts; i0 += NT * kRedUnroll) {
+#pragma unroll
+    for (int u = 0; u < kRedUnroll; ++u) {
+      const int i = i0 + u * NT;
+      if (i < nparts) acc[u] += load_agent(partial + i);
+    }
+  }
+  double v = 0.0;
+#pragma unroll
+  for (int u = 0; u < kRedUnroll; ++u) v += acc[u];
+  red[tid] = v;
+  __syncthreads();
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double R = red[0];
+    const int pass = st->pass;
+    if (trace && pass < st->trace_cap) trace[pass] = R;
+    if (bound_out) *bound_out = R;
+    if (!isfinite(R)) {
+      st->numeric = 1;
+      st->done = 1;
+    } else if (st->check && pass >= 1 && fabs(R - st->last_bound) <= st->tol * fabs(st->last_bound)) {
+      st->done = 1;
+    }
+    st->last_bound = R;
+    st->pass = pass + 1;
+    if (mirror) *mirror = *st;
+  }
+}
+
 // Contiguous work tiles handed out in XCD order.  Workgroups are dispatched to the 8 XCDs
 // round-robin (block b runs on XCD b % 8), so physical block b is given logical tile
 // (b % 8) * ceil(T / 8) + b / 8: each XCD walks its own contiguous range of tiles in
@@ -686,10 +735,11 @@ __device__ __forceinline__ void iter4_block(const IterArgs& a, int bid) {
     return;
   }
   const int64_t nbatch = (a.n + RW - 1) / RW;
-  const int64_t tile = xcd_tile((nbatch + 4 * kWaveSteps - 1) / (4 * kWaveSteps), (int64_t)bid - a.hblocks);
+  const int64_t TB = 4 * (a.wsteps > 0 ? a.wsteps : kWaveSteps);  // batches per tile
+  const int64_t tile = xcd_tile((nbatch + TB - 1) / TB, (int64_t)bid - a.hblocks);
   // a block without a tile (grid padding) walks nothing: b0 = bstop = 0
-  const int64_t b0 = tile >= 0 ? tile * 4 * kWaveSteps + wave : 0;
-  const int64_t bstop = tile >= 0 ? min(nbatch, (tile + 1) * 4 * kWaveSteps) : 0;
+  const int64_t b0 = tile >= 0 ? tile * TB + wave : 0;
+  const int64_t bstop = tile >= 0 ? min(nbatch, (tile + 1) * TB) : 0;
   // the row extent of batch b + 4 is loaded while batch b is computed
   auto clamp_row = [&](int64_t row) { return (uint32_t)(row >= 0 && row < a.n ? row : a.n - 1); };
   int32_t nbeg = 0, nend = 0;
@@ -820,10 +870,11 @@ __device__ __forceinline__ void final4_block(const FinalArgs& f, int bid) {
     if (wave == 0) final_row<G>(f, rowc, valid, g == 0, j, o, bv, bi, acc);
   } else {
     const int64_t nbatch = (a.n + RW - 1) / RW;
-    const int64_t tile = xcd_tile((nbatch + 4 * kWaveSteps - 1) / (4 * kWaveSteps), (int64_t)bid - a.hblocks);
+    const int64_t TB = 4 * (a.wsteps > 0 ? a.wsteps : kWaveSteps);  // batches per tile
+    const int64_t tile = xcd_tile((nbatch + TB - 1) / TB, (int64_t)bid - a.hblocks);
     // a block without a tile (grid padding) walks nothing
-    const int64_t b0 = tile >= 0 ? tile * 4 * kWaveSteps + wave : 0;
-    const int64_t bstop = tile >= 0 ? min(nbatch, (tile + 1) * 4 * kWaveSteps) : 0;
+    const int64_t b0 = tile >= 0 ? tile * TB + wave : 0;
+    const int64_t bstop = tile >= 0 ? min(nbatch, (tile + 1) * TB) : 0;
     for (int64_t b = b0; b < bstop; b += 4) {
       const int64_t row = b * RW + g;
       const uint32_t rowc = (uint32_t)(row >= 0 && row < a.n ? row : a.n - 1);
@@ -1188,64 +1239,16 @@ __global__ __launch_bounds__(kBlock) void energy_reduce_packed(const EnergyArgs*
   energy_reduce_block(e.part_un, e.part_un64, e.part_cut, start[blockIdx.x + 1] - start[blockIdx.x], e.out, e.out_cut);
 }
 
-// Fixed-order sum of the bound partials of one z-update, then the loop bookkeeping: bound
-// trace, convergence test (relative change of the bound), pass counter.  A no-op once the
-// loop is done, like the z-updates queued after it.  Each thread sums a strided slice with
-// kRedUnroll independent accumulators (so the loads are all in flight together), then the
-// block combines the slices in a fixed tree.
-constexpr int kRedBlock = 1024;
-constexpr int kRedUnroll = 8;
-__device__ __forceinline__ void pass_reduce_block(const double* __restrict__ partial, int nparts, IterState* st,
-                                                  double* trace, double* bound_out, IterState* mirror) {
-  if (st->done) return;
-  __shared__ double red[kRedBlock];
-  const int tid = threadIdx.x;
-  double acc[kRedUnroll];
-#pragma unroll
-  for (int u = 0; u < kRedUnroll; ++u) acc[u] = 0.0;
-  for (int i0 = tid; i0 < nparts; i0 += kRedBlock * kRedUnroll) {
-#pragma unroll
-    for (int u = 0; u < kRedUnroll; ++u) {
-      const int i = i0 + u * kRedBlock;
-      if (i < nparts) acc[u] += partial[i];
-    }
-  }
-  double v = 0.0;
-#pragma unroll
-  for (int u = 0; u < kRedUnroll; ++u) v += acc[u];
-  red[tid] = v;
-  __syncthreads();
-  for (int w = kRedBlock / 2; w > 0; w >>= 1) {
-    if (tid < w) red[tid] += red[tid + w];
-    __syncthreads();
-  }
-  if (tid == 0) {
-    const double R = red[0];
-    const int pass = st->pass;
-    if (trace && pass < st->trace_cap) trace[pass] = R;
-    if (bound_out) *bound_out = R;
-    if (!isfinite(R)) {
-      st->numeric = 1;
-      st->done = 1;
-    } else if (st->check && pass >= 1 && fabs(R - st->last_bound) <= st->tol * fabs(st->last_bound)) {
-      st->done = 1;
-    }
-    st->last_bound = R;
-    st->pass = pass + 1;
-    if (mirror) *mirror = *st;
-  }
-}
-
 __global__ __launch_bounds__(kRedBlock) void pass_reduce_kernel(const double* __restrict__ partial, int nparts,
                                                                 IterState* st, double* trace, double* bound_out,
                                                                 IterState* mirror) {
-  pass_reduce_block(partial, nparts, st, trace, bound_out, mirror);
+  reduce_pass<kRedBlock>(partial, nparts, st, trace, bound_out, mirror);
 }
 
 // one block per job
 __global__ __launch_bounds__(kRedBlock) void pass_reduce_packed(const ReduceJob* __restrict__ jobs) {
   const ReduceJob r = jobs[blockIdx.x];
-  pass_reduce_block(r.partial, r.nparts, r.state, r.trace, r.bound_out, nullptr);
+  reduce_pass<kRedBlock>(r.partial, r.nparts, r.state, r.trace, r.bound_out, nullptr);
 }
 
 __global__ void gather_rows_kernel(const float* __restrict__ src, const int32_t* __restrict__ perm, int64_t n, int L,
@@ -1324,11 +1327,12 @@ int groups4(int L) {
 
 inline int64_t tile_grid(int64_t ntiles) { return 8 * ((std::max<int64_t>(ntiles, 1) + 7) / 8); }
 
-int iter_grid(int64_t n, int32_t L, int64_t n_heavy) {
+int iter_grid(int64_t n, int32_t L, int64_t n_heavy, int32_t wsteps) {
   if (L <= 64) {
     const int64_t RW = 64 / groups4(L);
     const int64_t nbatch = (n + RW - 1) / RW;
-    return heavy_blocks(n_heavy) + (int)tile_grid((nbatch + 4 * kWaveSteps - 1) / (4 * kWaveSteps));
+    const int64_t TB = 4 * (wsteps > 0 ? wsteps : kWaveSteps);
+    return heavy_blocks(n_heavy) + (int)tile_grid((nbatch + TB - 1) / TB);
   }
   const int64_t rows = 4 * (64 / lanes_for(L)) * kWaveSteps;
   return (int)tile_grid((n + rows - 1) / rows);

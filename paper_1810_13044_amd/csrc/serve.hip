@@ -19,6 +19,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <condition_variable>
 #include <deque>
 #include <mutex>
@@ -82,7 +83,7 @@ struct Job {
   std::vector<int32_t> cur_modes, next_modes;  // host copies
   slk_graph* g = nullptr;
   double sigma2 = 0.0;
-  int L = 0, ldz = 0, G = 0, grid = 0, egrid = 0, ugrid = 0;
+  int L = 0, ldz = 0, G = 0, grid = 0, egrid = 0, ugrid = 0, wsteps = 0;
   size_t footprint = 0;
   void* mem = nullptr;
   float* A = nullptr;
@@ -116,7 +117,7 @@ size_t job_footprint(const slk_job& j) {
   const size_t nnz = 2 * k * n + kColPad;
   const size_t graph = 4 * (n + 1) + 4 * nnz + 12 * n * k + 12 * n;
   const size_t knn = 4 * n * d + 8 * n * 64 + 16 * n;
-  const size_t grid = (size_t)iter_grid(j.n, j.L, j.n) + 8;
+  const size_t grid = (size_t)iter_grid(j.n, j.L, j.n, 1) + 8;   // the largest grid any tile shape takes
   const size_t work = 12 * n * ldz + 4 * nnz + 4 * n + 16 * grid + 8 * L * grid + 24 * grid;
   return graph + knn + work + (1u << 20);
 }
@@ -150,6 +151,21 @@ struct slk_server {
   std::deque<Job*> built;       // graph built (or failed: build_status)
   int building = 0;             // handed to the builder and not taken back yet
   bool stop = false;
+  std::atomic<int64_t> grouped_builds{0};   // shared launches of the exact kNN search
+  // the step's stream: the caller's, or one of the server's own when the caller passed the null
+  // stream (which cannot be captured); the own stream waits for the null stream at every step
+  hipStream_t own = nullptr;
+  hipEvent_t caller_done = nullptr;
+  // captured step shapes: signature -> executable graph; shapes seen once wait for a second time
+  struct Captured {
+    std::vector<int64_t> sig;
+    hipGraphExec_t exec = nullptr;
+    uint64_t used = 0;
+  };
+  std::vector<Captured> graphs;
+  std::vector<std::vector<int64_t>> seen;   // shapes seen once (bounded, oldest dropped)
+  uint64_t clock = 0;
+  int64_t steps = 0, graph_launches = 0, graph_captures = 0;
 };
 
 namespace slk {
@@ -187,31 +203,71 @@ void release(slk_server* sv, Job* j) {
   delete j;
 }
 
-// A worker: builds the graphs of admitted jobs on its own stream, one at a time, and hands each
-// job back complete (its stream synchronised) with the build's status.
+// A worker: builds the graphs of admitted jobs on its own stream and hands each job back
+// complete (its stream synchronised) with the build's status.  A job whose graph takes the exact
+// search is built together with the other such jobs waiting at that moment (up to kGroupMax):
+// their searches share one launch (slk_build_knn_batched); graphs identical to single builds.
+constexpr size_t kGroupMax = 32;
+constexpr size_t kGraphsMax = 64;   // captured step shapes kept (least recently used dropped)
+constexpr size_t kSeenMax = 256;    // shapes seen once, remembered
+
+bool exact_build(const Job* j) { return knn_takes_exact(j->spec.n, j->spec.d, j->spec.knn); }
+
 void builder_loop(slk_server* sv, int w) {
   (void)hipSetDevice(sv->device);
   set_graph_pool(true);   // graphs freed stream-ordered when their jobs finish
   const hipStream_t bs = sv->bss[w];
   for (;;) {
-    Job* j = nullptr;
+    std::vector<Job*> group;
     {
       std::unique_lock<std::mutex> lk(sv->mu);
       sv->cv_todo.wait(lk, [&] { return sv->stop || !sv->to_build.empty(); });
       if (sv->stop) return;
-      j = sv->to_build.front();
+      group.push_back(sv->to_build.front());
       sv->to_build.pop_front();
+      if (exact_build(group[0])) {
+        for (auto it = sv->to_build.begin(); it != sv->to_build.end() && group.size() < kGroupMax;) {
+          if (exact_build(*it)) {
+            group.push_back(*it);
+            it = sv->to_build.erase(it);
+          } else {
+            ++it;
+          }
+        }
+      }
     }
-    const slk_job& sp = j->spec;
-    slk_status st = slk_build_knn(sp.x, sp.n, sp.d, &sp.knn, bs, &j->g);
-    if (st == SLK_OK && hipStreamSynchronize(bs) != hipSuccess) {
-      (void)hipGetLastError();
-      st = fail(SLK_ERR_DEVICE, "graph build");
+    auto build_one = [&](Job* j) {
+      const slk_job& sp = j->spec;
+      slk_status st = slk_build_knn(sp.x, sp.n, sp.d, &sp.knn, bs, &j->g);
+      if (st == SLK_OK && hipStreamSynchronize(bs) != hipSuccess) {
+        (void)hipGetLastError();
+        st = fail(SLK_ERR_DEVICE, "graph build");
+      }
+      j->build_status = st;
+    };
+    if (group.size() == 1) {
+      build_one(group[0]);
+    } else {
+      std::vector<slk_knn_item> items(group.size());
+      std::vector<slk_graph*> gs(group.size(), nullptr);
+      for (size_t i = 0; i < group.size(); ++i) {
+        const slk_job& sp = group[i]->spec;
+        items[i] = slk_knn_item{sp.x, sp.n, sp.d, 0, sp.knn};
+      }
+      if (slk_build_knn_batched(items.data(), (int32_t)items.size(), bs, gs.data()) == SLK_OK) {
+        for (size_t i = 0; i < group.size(); ++i) {
+          group[i]->g = gs[i];
+          group[i]->build_status = SLK_OK;
+        }
+        ++sv->grouped_builds;
+      } else {
+        // one of them failed: build each alone, so that every job gets its own status
+        for (Job* j : group) build_one(j);
+      }
     }
-    j->build_status = st;
     {
       std::lock_guard<std::mutex> lk(sv->mu);
-      sv->built.push_back(j);
+      for (Job* j : group) sv->built.push_back(j);
     }
     sv->cv_built.notify_all();
   }
@@ -228,7 +284,8 @@ slk_status admit(slk_server* sv, Job* j) {
   const int64_t n = sp.n;
   j->ldz = ldz_for(j->L);
   j->G = groups4(j->L);
-  j->grid = iter_grid(n, j->L, heavy_rows_for(j->g, j->L));
+  j->wsteps = tune_wave_steps(n, j->L);
+  j->grid = iter_grid(n, j->L, heavy_rows_for(j->g, j->L), j->wsteps);
   j->egrid = energy_grid(n, j->g->n_heavy);
   const size_t nz = (size_t)j->g->nnz + kColPad;
   size_t off = 0;
@@ -286,6 +343,7 @@ IterArgs job_iter(const Job* j, const Slot* slot_dev) {
   a.trace = nullptr;
   a.bound_out = nullptr;
   a.mirror = nullptr;
+  a.wsteps = j->wsteps;
   set_heavy(a, j->g, j->L);
   return a;
 }
@@ -313,8 +371,15 @@ EnergyArgs job_energy(const Job* j, Slot* slot_dev, bool fp64) {
   return e;
 }
 
+void drop_graphs(slk_server* sv) {
+  for (auto& c : sv->graphs) (void)hipGraphExecDestroy(c.exec);
+  sv->graphs.clear();
+  sv->seen.clear();
+}
+
 slk_status grow_tables(slk_server* sv, size_t need) {
   if (need <= sv->tab_cap) return SLK_OK;
+  drop_graphs(sv);   // captured launches hold addresses in the old table block
   size_t cap = std::max<size_t>(need, 2 * sv->tab_cap);
   cap = align_up(cap, 1 << 16);
   (void)hipFree(sv->tab_dev);
@@ -330,6 +395,11 @@ slk_status grow_tables(slk_server* sv, size_t need) {
 
 slk_status server_step(slk_server* sv) {
   hipStream_t s = sv->s;
+  if (sv->own) {
+    // order the step after the work queued on the null stream so far
+    SLK_HIP(hipEventRecord(sv->caller_done, nullptr));
+    SLK_HIP(hipStreamWaitEvent(s, sv->caller_done, 0));
+  }
   // ---- admission: a free slot and room in the budget send a queued job to the builder
   {
     std::lock_guard<std::mutex> lk(sv->mu);
@@ -549,37 +619,114 @@ slk_status server_step(slk_server* sv) {
     }
   }
 
-  // ---- launches (stream order: final, energies, unary + reset, z-updates, state copy)
-  SLK_HIP(hipMemcpyAsync(D, H, t.off, hipMemcpyHostToDevice, s));
-  for (int gi = 0; gi < 5; ++gi) {
-    const GroupAt& ga = fin_g[gi];
-    if (ga.count)
-      SLK_TRY(launch_final_packed(Gs[gi], (const FinalArgs*)(D + ga.args), (const int32_t*)(D + ga.start), ga.count,
-                                  ga.blocks, s));
-  }
-  if (!fin.empty()) {
-    SLK_TRY(launch_reduce_packed((const ReduceJob*)(D + fin_red), (int)fin.size(), s));
-    SLK_TRY(launch_mode_reduce_packed((const ModeJob*)(D + mode_args), (const int32_t*)(D + mode_start),
-                                      (int)fin.size(), mode_blocks, s));
-  }
-  if (nen) SLK_TRY(launch_energy_packed((const EnergyArgs*)(D + en_args), (const int32_t*)(D + en_start), (int)nen,
-                                        en_blocks, s));
-  if (!una.empty()) {
-    hipLaunchKernelGGL(init_jobs_kernel, dim3((unsigned)una.size()), dim3(64), 0, s, (const InitJob*)(D + init_args),
-                       (int)una.size());
-    SLK_LAUNCHED("init_jobs_kernel");
-    SLK_TRY(launch_unary_packed((const UnaryArgs*)(D + un_args), (const int32_t*)(D + un_start), (int)una.size(),
-                                un_blocks, un_lds, s));
-  }
+  // ---- launches (stream order: final, energies, unary + reset, z-updates), between the copy of
+  // the argument tables and the copy of the slots.  The kernels' arguments are addresses in the
+  // table block, counts and grid sizes: two steps with equal signatures launch identical
+  // sequences, so a captured graph of one replays the other.
+  std::vector<int64_t> sig;
+  auto note = [&](int64_t kind, int64_t a, int64_t b, int64_t c, int64_t d) {
+    sig.push_back(kind);
+    sig.push_back(a);
+    sig.push_back(b);
+    sig.push_back(c);
+    sig.push_back(d);
+  };
+  for (int gi = 0; gi < 5; ++gi)
+    if (fin_g[gi].count) note(1, gi, (int64_t)fin_g[gi].args, fin_g[gi].count, fin_g[gi].blocks);
+  if (!fin.empty()) note(2, (int64_t)fin_red, (int64_t)mode_args, (int64_t)fin.size(), mode_blocks);
+  if (nen) note(3, (int64_t)en_args, (int64_t)en_start, (int64_t)nen, en_blocks);
+  if (!una.empty()) note(4, (int64_t)init_args, (int64_t)una.size(), un_blocks, (int64_t)un_lds);
   for (int p = 0; p < maxp; ++p) {
     for (int gi = 0; gi < 5; ++gi) {
       const GroupAt& ga = it_g[(size_t)p * 5 + gi];
-      if (ga.count)
-        SLK_TRY(launch_iter_packed(Gs[gi], (const IterArgs*)(D + ga.args), (const int32_t*)(D + ga.start), ga.count,
-                                   ga.blocks, s));
+      if (ga.count) note(5, gi, (int64_t)ga.args, ga.count, ga.blocks);
     }
-    SLK_TRY(launch_reduce_packed((const ReduceJob*)(D + it_red[p]), it_nred[p], s));
+    note(6, p, (int64_t)it_red[p], it_nred[p], 0);
   }
+  auto issue = [&]() -> slk_status {
+    for (int gi = 0; gi < 5; ++gi) {
+      const GroupAt& ga = fin_g[gi];
+      if (ga.count)
+        SLK_TRY(launch_final_packed(Gs[gi], (const FinalArgs*)(D + ga.args), (const int32_t*)(D + ga.start), ga.count,
+                                    ga.blocks, s));
+    }
+    if (!fin.empty()) {
+      SLK_TRY(launch_reduce_packed((const ReduceJob*)(D + fin_red), (int)fin.size(), s));
+      SLK_TRY(launch_mode_reduce_packed((const ModeJob*)(D + mode_args), (const int32_t*)(D + mode_start),
+                                        (int)fin.size(), mode_blocks, s));
+    }
+    if (nen) SLK_TRY(launch_energy_packed((const EnergyArgs*)(D + en_args), (const int32_t*)(D + en_start), (int)nen,
+                                          en_blocks, s));
+    if (!una.empty()) {
+      hipLaunchKernelGGL(init_jobs_kernel, dim3((unsigned)una.size()), dim3(64), 0, s, (const InitJob*)(D + init_args),
+                         (int)una.size());
+      SLK_LAUNCHED("init_jobs_kernel");
+      SLK_TRY(launch_unary_packed((const UnaryArgs*)(D + un_args), (const int32_t*)(D + un_start), (int)una.size(),
+                                  un_blocks, un_lds, s));
+    }
+    for (int p = 0; p < maxp; ++p) {
+      for (int gi = 0; gi < 5; ++gi) {
+        const GroupAt& ga = it_g[(size_t)p * 5 + gi];
+        if (ga.count)
+          SLK_TRY(launch_iter_packed(Gs[gi], (const IterArgs*)(D + ga.args), (const int32_t*)(D + ga.start),
+                                     ga.count, ga.blocks, s));
+      }
+      SLK_TRY(launch_reduce_packed((const ReduceJob*)(D + it_red[p]), it_nred[p], s));
+    }
+    return SLK_OK;
+  };
+  SLK_HIP(hipMemcpyAsync(D, H, t.off, hipMemcpyHostToDevice, s));
+  ++sv->steps;
+  bool ran = false;
+  if (sv->o.graph_replay) {
+    ++sv->clock;
+    for (auto& c : sv->graphs) {
+      if (c.sig == sig) {
+        SLK_HIP(hipGraphLaunch(c.exec, s));
+        c.used = sv->clock;
+        ++sv->graph_launches;
+        ran = true;
+        break;
+      }
+    }
+    if (!ran) {
+      auto it = std::find(sv->seen.begin(), sv->seen.end(), sig);
+      if (it == sv->seen.end()) {
+        if (sv->seen.size() >= kSeenMax) sv->seen.erase(sv->seen.begin());
+        sv->seen.push_back(sig);
+      } else {
+        sv->seen.erase(it);
+        // second occurrence of this shape: capture it
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        bool ok = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        slk_status ist = SLK_OK;
+        if (ok) {
+          ist = issue();
+          ok = hipStreamEndCapture(s, &graph) == hipSuccess && ist == SLK_OK;
+        }
+        if (ok) ok = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();
+        if (ok) {
+          if (sv->graphs.size() >= kGraphsMax) {
+            auto lru = std::min_element(sv->graphs.begin(), sv->graphs.end(),
+                                        [](const auto& a, const auto& b) { return a.used < b.used; });
+            (void)hipGraphExecDestroy(lru->exec);
+            sv->graphs.erase(lru);
+          }
+          sv->graphs.push_back({sig, exec, sv->clock});
+          ++sv->graph_captures;
+          SLK_HIP(hipGraphLaunch(exec, s));
+          ++sv->graph_launches;
+          ran = true;
+        } else if (exec) {
+          (void)hipGraphExecDestroy(exec);
+        }
+      }
+    }
+  }
+  if (!ran) SLK_TRY(issue());
   SLK_HIP(hipMemcpyAsync(sv->slots_host, sv->slots_dev, sizeof(Slot) * sv->o.max_jobs, hipMemcpyDeviceToHost, s));
   SLK_HIP(hipStreamSynchronize(s));
 
@@ -669,7 +816,7 @@ slk_status slk_server_opts_default(slk_server_opts* o) {
   o->passes_per_step = 4;
   o->memory_budget = 0;
   o->builders = 3;
-  o->reserved = 0;
+  o->graph_replay = 1;
   return SLK_OK;
 }
 
@@ -683,6 +830,7 @@ slk_status slk_server_create(const slk_server_opts* opts, void* stream, slk_serv
   if (o.passes_per_step < 1) return fail(SLK_ERR_INVALID_ARG, "passes_per_step must be >= 1");
   if (o.memory_budget < 0) return fail(SLK_ERR_INVALID_ARG, "memory_budget must be >= 0");
   if (o.builders < 1 || o.builders > 8) return fail(SLK_ERR_INVALID_ARG, "builders must be in [1, 8]");
+  if (o.graph_replay != 0 && o.graph_replay != 1) return fail(SLK_ERR_INVALID_ARG, "graph_replay must be 0 or 1");
   slk_server* sv = new slk_server();
   sv->o = o;
   sv->s = (hipStream_t)stream;
@@ -690,6 +838,12 @@ slk_status slk_server_create(const slk_server_opts* opts, void* stream, slk_serv
     slk_server_destroy(sv);
     return st;
   };
+  if (!sv->s) {
+    if (hipStreamCreateWithFlags(&sv->own, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&sv->caller_done, hipEventDisableTiming) != hipSuccess)
+      return bail(fail(SLK_ERR_DEVICE, "server stream"));
+    sv->s = sv->own;
+  }
   if (hipGetDevice(&sv->device) != hipSuccess) return bail(fail(SLK_ERR_DEVICE, "hipGetDevice"));
   size_t fr = 0, tot = 0;
   if (hipMemGetInfo(&fr, &tot) != hipSuccess) return bail(fail(SLK_ERR_DEVICE, "hipMemGetInfo"));
@@ -767,11 +921,23 @@ void slk_server_destroy(slk_server* sv) {
   }
   for (Job* j : sv->queue) delete j;
   (void)hipStreamSynchronize(sv->s);
+  drop_graphs(sv);
+  if (sv->own) (void)hipStreamDestroy(sv->own);
+  if (sv->caller_done) (void)hipEventDestroy(sv->caller_done);
   (void)hipFree(sv->slots_dev);
   (void)hipHostFree(sv->slots_host);
   (void)hipFree(sv->tab_dev);
   (void)hipHostFree(sv->tab_host);
   delete sv;
+}
+
+slk_status slk_server_stats(const slk_server* sv, slk_server_stats_t* out) {
+  if (!sv || !out) return fail(SLK_ERR_INVALID_ARG, "NULL argument");
+  out->steps = sv->steps;
+  out->graph_launches = sv->graph_launches;
+  out->graph_captures = sv->graph_captures;
+  out->grouped_builds = sv->grouped_builds.load();
+  return SLK_OK;
 }
 
 slk_status slk_fit_batched(const slk_job* jobs, int32_t n_jobs, const slk_server_opts* opts, void* stream) {

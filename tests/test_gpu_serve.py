@@ -117,3 +117,54 @@ def test_server_rejects_bad_jobs(slk, torch):
         outs = sv.step()
     assert outs[t]["status"] == 0
     sv.close()
+
+
+def test_build_knn_batched_identical_to_single_builds(slk, torch):
+    """slk_build_knn_batched: the exact searches of several problems share one launch; every graph
+    equals its own slk_build_knn (lists, FP64 distances, CSR, sigma^2), also with the locality
+    order, bf16 points and a problem large enough for the MFMA path in the same call."""
+    probs = []
+    rng = np.random.default_rng(3)
+    for j, (n, d, k) in enumerate([(300, 8, 5), (1777, 16, 10), (64, 3, 7), (2500, 40, 10), (999, 12, 6)]):
+        inst = gen.gaussian_mixture(n=n, d=d, L=3, K=k, seed=40 + j)
+        probs.append(dict(x=to_dev(torch, inst.X, torch.float32), k=k, reorder=bool(j % 2),
+                          prec="bf16" if j == 4 else "fp32"))
+    big = gen.gaussian_mixture(n=12000, d=64, L=4, K=10, seed=49)
+    probs.append(dict(x=to_dev(torch, big.X, torch.float32), k=10, method="auto"))
+    graphs = slk.Graph.build_knn_batched(probs)
+    for pr, g in zip(probs, graphs):
+        ref = slk.Graph.build_knn(pr["x"], k=pr["k"], reorder=pr.get("reorder", False), prec=pr.get("prec", "fp32"),
+                                  method=pr.get("method", "auto"))
+        a, b = g.export(), ref.export()
+        for key in ("knn_idx", "knn_d2", "row_ptr", "col_idx", "perm"):
+            assert torch.equal(a[key], b[key]), key
+        assert g.info() == ref.info()
+        g.close()
+        ref.close()
+
+
+@pytest.mark.parametrize("replay", [True, False])
+def test_server_graph_replay_and_grouped_builds(slk, torch, replay):
+    """Twelve small jobs submitted together: their graphs are built in shared exact-search
+    launches, and with graph replay the steps whose launch sequence repeats run from captured HIP
+    graphs (replayed many times, with the server's own copies and synchronisations in between);
+    every result equals the job's solo fit either way."""
+    insts = [gen.gaussian_mixture(n=1500, d=16, L=6, K=10, seed=60 + j) for j in range(12)]
+    xs = [to_dev(torch, i.X, torch.float32) for i in insts]
+    kw = dict(fixed_inner=24, max_outer=2)   # the jobs step in lock-step through 12 equal inner steps
+    sv = slk.Server(max_jobs=16, passes_per_step=2, builders=1, graph_replay=replay)
+    tickets = {sv.submit(x, i.init_modes, lam=i.lam, k=i.K, **kw): j for j, (x, i) in enumerate(zip(xs, insts))}
+    outs = {}
+    while len(outs) < len(insts):
+        outs.update(sv.step())
+    st = sv.stats()
+    sv.close()
+    assert st["grouped_builds"] >= 1, st
+    if replay:
+        assert st["graph_captures"] >= 1 and st["graph_launches"] >= st["graph_captures"] + 10, st
+    else:
+        assert st["graph_launches"] == 0
+    for t, k in tickets.items():
+        x = xs[k]
+        g = slk.Graph.build_knn(x, k=insts[k].K)
+        same(slk.fit(x, g, insts[k].init_modes, lam=insts[k].lam, **kw), outs[t])
