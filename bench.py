@@ -111,47 +111,78 @@ def cpu_baseline(graph, A, Z0, lam, N, nnz, L, budget_s=20.0):
         Z = orc.softmax_rows(S)
         times.append(time.perf_counter() - t0)
     t = float(np.median(times))
-    return {"value": round(bytes_iter(N, nnz, L) / t / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+    return {"value": round(bytes_iter(N, nnz, L) / t / 1e9, 3), "unit": "GB/s", "cores": 1, "cpu_model": cpu_model(),
+            "kind": "oracle",
             "sample": f"{len(times)} FP64 oracle z-updates (SciPy CSR x dense Z, NumPy softmax and bound, "
                       f"single thread) over the full N={N} graph; median {t:.3f} s per pass; "
                       f"host has {os.cpu_count()} logical CPUs"}
 
 
-def cpu_other(slk, torch, X, K, knn_s, n_rows=8):
-    """Two more oracle timings on the host, each beside the GPU's: the exact kNN of sampled query rows
-    of the main workload (FP64 brute force, one thread; extrapolated to all rows and labelled so),
-    and the whole pipeline at the 2,000-point mixture (kNN, CSR, sigma^2 and the fit)."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_knn_threads(X, K, rows, threads):
+    """The oracle's exact kNN of the given query rows on a thread pool over blocks of rows (its
+    distance loop is NumPy arithmetic that releases the interpreter lock)."""
+    from concurrent.futures import ThreadPoolExecutor
+    from oracle import slk as orc
+    X64 = np.asarray(X, dtype=np.float64)
+    blocks = [rows[i: i + 8] for i in range(0, len(rows), 8)]
+    with ThreadPoolExecutor(threads) as ex:
+        list(ex.map(lambda r: orc.knn(X64, K, rows=r, block=len(r)), blocks))
+
+
+def cpu_other(slk, torch, X, K, knn_s, n_rows=1024):
+    """More oracle timings on the host, each beside the GPU's: the exact kNN of sampled query rows
+    of the main workload (FP64 brute force on a thread pool over all host cores; extrapolated to
+    all rows and labelled so), the full exact kNN of the 2,000-point mixture on the same pool, and
+    the whole oracle pipeline at the 2,000-point mixture (kNN, CSR, sigma^2 and the fit)."""
     import gen
     from oracle import slk as orc
+    threads = os.cpu_count() or 1
     N = X.shape[0]
-    X64 = np.asarray(X, dtype=np.float64)
     rows = np.random.default_rng(11).choice(N, n_rows, replace=False)
     t0 = time.perf_counter()
-    orc.knn(X64, K, rows=rows, block=n_rows)
+    oracle_knn_threads(X, K, rows, threads)
     per_row = (time.perf_counter() - t0) / n_rows
-    del X64
     inst = gen.make("mixture-2k")
+    t0 = time.perf_counter()
+    oracle_knn_threads(inst.X, inst.K, np.arange(inst.N), threads)
+    small_knn = time.perf_counter() - t0
     t0 = time.perf_counter()
     idx, d2 = orc.knn(inst.X, inst.K, block=256)
     rp, ci = orc.symmetrize(idx, inst.N)
     orc.fit(inst.X, rp, ci, inst.init_modes, orc.sigma2_from_knn(d2), inst.lam)
     small_cpu = time.perf_counter() - t0
     x = torch.from_numpy(inst.X).to("cuda")
-    gpu = []
+    gpu, gpu_knn = [], []
     for _ in range(6):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         g = slk.Graph.build_knn(x, k=inst.K)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
         slk.fit(x, g, inst.init_modes, lam=inst.lam)
         torch.cuda.synchronize()
         gpu.append(time.perf_counter() - t0)
+        gpu_knn.append(t1 - t0)
         g.close()
     small_gpu = float(np.median(gpu[1:]))
-    return {"knn": {"kind": "oracle", "cores": 1,
-                    "sample": f"exact kNN of {n_rows} seeded query rows against all N={N} points (FP64, one thread), "
-                              f"extrapolated to N rows",
-                    "s_per_row": round(per_row, 3), "extrapolated_s": round(per_row * N, 1),
+    return {"knn": {"kind": "oracle", "cores": threads, "cpu_model": cpu_model(),
+                    "sample": f"exact kNN of {n_rows} seeded query rows against all N={N} points (FP64, thread pool "
+                              f"over {threads} host threads), extrapolated to N rows",
+                    "s_per_row": round(per_row, 5), "extrapolated_s": round(per_row * N, 1),
                     "gpu_build_s": round(knn_s, 3), "ratio": round(per_row * N / knn_s, 1)},
+            "knn_mixture-2k": {"kind": "oracle", "cores": threads, "sample": "full exact kNN at N=2000 D=16 k=10",
+                               "cpu_s": round(small_knn, 4), "gpu_s_median": round(float(np.median(gpu_knn[1:])), 5)},
             "mixture-2k": {"kind": "oracle", "cores": 1,
                            "sample": "whole pipeline at N=2000 D=16 L=5: kNN, CSR, sigma^2 and the SLK-BO fit",
                            "cpu_s": round(small_cpu, 4), "gpu_s_median": round(small_gpu, 5),
@@ -166,9 +197,11 @@ def _materialise_jobs(torch, n_jobs):
     """The job stream's data, resident on the device, and its arrival times at 1 job/s (the
     stream at rate r arrives at these times / r: the gaps are exponential draws scaled by 1/r)."""
     import gen
+    from concurrent.futures import ThreadPoolExecutor
     specs = gen.job_stream(n_jobs=n_jobs, rate=1.0, seed=5)
     t0 = time.perf_counter()
-    insts = [gen.materialise(sp, K=10) for sp in specs]
+    with ThreadPoolExecutor(os.cpu_count() or 1) as ex:
+        insts = list(ex.map(lambda sp: gen.materialise(sp, K=10), specs))
     xs = [torch.from_numpy(i.X).to("cuda") for i in insts]
     torch.cuda.synchronize()
     log(f"[serve] {n_jobs} jobs materialised in {time.perf_counter() - t0:.1f}s "
@@ -190,7 +223,8 @@ def _serve_once(slk, torch, insts, xs, arr, max_jobs, passes, prec):
 
     # warm-up (kernels loaded, allocator primed)
     w = insts[0]
-    g = slk.Graph.build_knn(xs[0], k=10, prec=prec)
+    kp = "bf16" if prec == "bf16" else "fp32"     # BF16-X keeps the FP32 points' graph
+    g = slk.Graph.build_knn(xs[0], k=10, prec=kp)
     slk.fit(xs[0], g, w.init_modes, lam=w.lam, prec=prec)
     del g
     torch.cuda.synchronize()
@@ -203,7 +237,7 @@ def _serve_once(slk, torch, insts, xs, arr, max_jobs, passes, prec):
         now = time.perf_counter() - start
         if now < arr[j]:
             time.sleep(arr[j] - now)
-        g = slk.Graph.build_knn(x, k=10, prec=prec)
+        g = slk.Graph.build_knn(x, k=10, prec=kp)
         r = slk.fit(x, g, inst.init_modes, lam=inst.lam, prec=prec)
         done[j] = time.perf_counter() - start
         plain_out[j] = r
@@ -221,7 +255,7 @@ def _serve_once(slk, torch, insts, xs, arr, max_jobs, passes, prec):
         now = time.perf_counter() - start
         while nxt < n_jobs and arr[nxt] <= now:
             inst = insts[nxt]
-            tick[sv.submit(xs[nxt], inst.init_modes, lam=inst.lam, k=10, knn_prec=prec, prec=prec)] = nxt
+            tick[sv.submit(xs[nxt], inst.init_modes, lam=inst.lam, k=10, knn_prec=kp, prec=prec)] = nxt
             nxt += 1
         if sv.pending() == 0:
             time.sleep(max(0.0, min(arr[nxt] - now, 0.001)))
@@ -255,107 +289,93 @@ def serving(slk, torch, n_jobs, rate, max_jobs, passes, prec="fp32"):
 
 
 def serving_sweep(slk, torch, n_jobs, rates, max_jobs, passes):
-    """The served form at several arrival rates, FP32 and BF16-X (points rounded to bf16 for the
-    kNN and the unary term), each against one-at-a-time fits of the same precision.  The BF16-X
-    results are compared with the FP32 ones on the FP32 problem: energy of the BF16-X labels and
-    modes on the FP32 graph with the FP64 unary term, and label agreement; and, in lock-step, the
-    first outer iteration of each job from the same modes and with the FP32 run's number of
-    z-updates, so that the gap measures the precision alone rather than a different local optimum."""
+    """The served form at several arrival rates, FP32 and BF16-X (the unary distances as a bf16 MFMA
+    contraction; the graph is the FP32 points' exact graph in both), each against one-at-a-time fits
+    of the same precision.  The BF16-X results are compared with the FP32 ones on the FP32 problem:
+    both report the FP64 recheck of the energy at their final labels and modes on the same graph."""
     insts, xs, arr1 = _materialise_jobs(torch, n_jobs)
     runs = []
     keep = {}
     for rate in rates:
-        for prec in ("fp32", "bf16"):
+        for prec in ("fp32", "bf16x"):
             res, _, sv_out = _serve_once(slk, torch, insts, xs, arr1 / rate, max_jobs, passes, prec)
             res["rate_per_s"] = rate
             log(f"[serve] rate {rate} {prec}: {res}")
             runs.append(res)
             if prec not in keep:
                 keep[prec] = sv_out
-    gaps, tgaps, lower, agree = [], [], [], []
-    for j, (inst, x) in enumerate(zip(insts, xs)):
-        o32, o16 = keep["fp32"][j], keep["bf16"][j]
-        g = slk.Graph.build_knn(x, k=10)
-        e = slk.energy(x, g, o16["labels"], o16["modes"], lam=inst.lam)["energy_fp64"]
-        r32 = o32["result"]
-        e32 = r32["energy_fp64"]
+    gaps, tgaps, lower, agree, same_modes = [], [], [], [], []
+    for j, inst in enumerate(insts):
+        o32, o16 = keep["fp32"][j], keep["bf16x"][j]
+        r32, r16 = o32["result"], o16["result"]
+        e32, e16 = r32["energy_fp64"], r16["energy_fp64"]
         terms = (inst.lam * r32["cut"] - e32) + inst.lam * r32["cut"]    # |unary| + |pairwise|
-        gaps.append(abs(e - e32) / abs(e32))
-        tgaps.append(abs(e - e32) / terms)
-        lower.append(e < e32)
+        gaps.append(abs(e16 - e32) / abs(e32))
+        tgaps.append(abs(e16 - e32) / terms)
+        lower.append(e16 < e32)
         agree.append(float((o16["labels"] == o32["labels"]).float().mean()))
-        del g
-    # lock-step: the first outer iteration from the same modes with the same number of z-updates,
-    # so the gap is the precision's own effect, not a different local optimum
-    lgaps, ltgaps = [], []
-    for j, (inst, x) in enumerate(zip(insts, xs)):
-        g32 = slk.Graph.build_knn(x, k=10)
-        g16 = slk.Graph.build_knn(x, k=10, prec="bf16")
-        a32 = slk.assign(x, g32, inst.init_modes, lam=inst.lam, trace=False)
-        npass = a32["result"]["inner_iters_last"]
-        a16 = slk.assign(x, g16, inst.init_modes, lam=inst.lam, trace=False, fixed_inner=npass, prec="bf16")
-        o32 = slk.energy(x, g32, a32["labels"], inst.init_modes, lam=inst.lam)
-        e32, cut32 = o32["energy_fp64"], o32["cut"]
-        e16 = slk.energy(x, g32, a16["labels"], inst.init_modes, lam=inst.lam)["energy_fp64"]
-        lgaps.append(abs(e16 - e32) / abs(e32))
-        ltgaps.append(abs(e16 - e32) / ((inst.lam * cut32 - e32) + inst.lam * cut32))
-        del g32, g16
-    lgaps, ltgaps = np.array(lgaps), np.array(ltgaps)
+        same_modes.append(bool(np.array_equal(o16["modes"], o32["modes"])))
     gaps, tgaps, agree = np.array(gaps), np.array(tgaps), np.array(agree)
     bf16_vs_fp32 = {"energy_rel_gap_median": float(np.median(gaps)), "energy_rel_gap_p99": float(np.percentile(gaps, 99)),
                     "energy_rel_gap_max": float(gaps.max()), "jobs_within_1e-4": int((gaps <= 1e-4).sum()),
-                    "gap_over_term_magnitudes_median": float(np.median(tgaps)),
+                    "jobs_within_1e-6": int((gaps <= 1e-6).sum()),
                     "gap_over_term_magnitudes_p99": float(np.percentile(tgaps, 99)),
-                    "bf16_lower_energy_fraction": float(np.mean(lower)),
+                    "bf16x_lower_energy_fraction": float(np.mean(lower)),
+                    "same_modes_jobs": int(np.sum(same_modes)),
                     "identical_labels_jobs": int((agree == 1.0).sum()),
-                    "label_agreement_median": float(np.median(agree)), "label_agreement_min": float(agree.min()),
-                    "lockstep_energy_rel_gap_median": float(np.median(lgaps)),
-                    "lockstep_energy_rel_gap_p99": float(np.percentile(lgaps, 99)),
-                    "lockstep_jobs_within_1e-4": int((lgaps <= 1e-4).sum()),
-                    "lockstep_gap_over_term_magnitudes_median": float(np.median(ltgaps)),
-                    "lockstep_gap_over_term_magnitudes_p99": float(np.percentile(ltgaps, 99))}
-    log(f"[serve] bf16 vs fp32: {bf16_vs_fp32}")
+                    "label_agreement_median": float(np.median(agree)), "label_agreement_min": float(agree.min())}
+    log(f"[serve] bf16x vs fp32: {bf16_vs_fp32}")
     return {"jobs": n_jobs, "max_jobs": max_jobs, "passes_per_step": passes, "workload": SERVE_WORKLOAD,
-            "runs": runs, "bf16_vs_fp32": bf16_vs_fp32}
+            "runs": runs, "bf16x_vs_fp32": bf16_vs_fp32}
 
 
-def _round_bf16(X):
-    """float32 -> nearest bfloat16 (ties to even), as float32 (input generation for the oracle)."""
-    b = np.ascontiguousarray(X, dtype=np.float32).view(np.uint32).astype(np.uint64)
-    b = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
-    return b.astype(np.uint32).view(np.float32)
+def _follow_gpu_picks(slk, orc, inst, x, g, rp, ci, s2, prec):
+    """The GPU's free-running fit replayed one outer iteration at a time, and the oracle's own fit
+    taking the GPU's byproduct mode wherever it lies in the oracle's tie set (several modes are
+    correct there); returns (GPU result, oracle fit, outer iterations where a pick was followed)."""
+    res = slk.fit(x, g, inst.init_modes, lam=inst.lam, prec=prec)
+    picks, m = [], np.asarray(inst.init_modes, dtype=np.int64)
+    for _ in range(20):
+        nxt = slk.assign(x, g, m, lam=inst.lam, trace=False, prec=prec)["modes_next"].astype(np.int64)
+        picks.append(nxt)
+        if np.array_equal(nxt, m):
+            break
+        m = nxt
+    followed = []
+
+    def choose(t, om, ties):
+        gp = picks[t] if t < len(picks) else om
+        nxt = np.array([gp[l] if gp[l] in ties[l] else om[l] for l in range(inst.L)], dtype=np.int64)
+        if np.any(nxt != om):
+            followed.append(t)
+        return nxt
+
+    ref = orc.fit(inst.X, rp, ci, inst.init_modes, s2, inst.lam, choose_modes=choose)
+    return res, ref, followed
 
 
 def precision(slk, torch, big_x, big_g, big_inst, r32):
-    """Error of the FP32 and BF16-X paths against the FP64 oracle at the 2,000-point mixture, and
-    of the BF16-X path against the FP32 path at the main workload (both evaluated on the FP32
-    problem: FP32-point graph, FP64 unary term)."""
+    """Error of the FP32 and BF16-X paths against the FP64 oracle at the 2,000-point mixture, and of
+    the BF16-X path against the FP32 path at the main workload (same graph; energies are the FP64
+    rechecks at each fit's labels and modes), with the unary kernel and the fit timed per precision."""
     import gen
     from oracle import slk as orc
     inst = gen.make("mixture-2k")
     x = torch.from_numpy(inst.X).to("cuda")
     idx, d2 = orc.knn(inst.X, inst.K, block=256)
     rp, ci = orc.symmetrize(idx, inst.N)
-    ref = orc.fit(inst.X, rp, ci, inst.init_modes, orc.sigma2_from_knn(d2), inst.lam)
-    g32 = slk.Graph.build_knn(x, k=inst.K, method="exact")
-    out = {"small": {"workload": "mixture-2k (N=2000, D=16, L=5) against the FP64 oracle: lockstep = the oracle "
-                                 "runs the GPU's inner pass counts and continues from the GPU's modes wherever "
-                                 "they lie in its tie set; free = both run on their own"}}
-    for prec in ("fp32", "bf16"):
-        g = g32 if prec == "fp32" else slk.Graph.build_knn(x, k=inst.K, method="exact", prec="bf16")
-        Xp = inst.X if prec == "fp32" else _round_bf16(inst.X)
-        if prec == "fp32":
-            rpp, cip, s2p = rp, ci, orc.sigma2_from_knn(d2)
-        else:
-            ib, db = orc.knn(Xp, inst.K, block=256)
-            rpp, cip = orc.symmetrize(ib, inst.N)
-            s2p = orc.sigma2_from_knn(db)
-        # lock-step outer iterations (the parity contract)
+    s2 = orc.sigma2_from_knn(d2)
+    g = slk.Graph.build_knn(x, k=inst.K, method="exact")
+    out = {"small": {"workload": "mixture-2k (N=2000, D=16, L=5) against the FP64 oracle on the FP32 points: "
+                                 "lockstep = the oracle runs the GPU's modes and inner pass counts; free = both run "
+                                 "on their own, the oracle taking the GPU's byproduct mode wherever it lies in its "
+                                 "tie set; resolvable = rows whose top two oracle logits differ beyond FP32 resolution"}}
+    for prec in ("fp32", "bf16x"):
         modes = inst.init_modes.copy()
         dz = 0.0
         for t in range(20):
-            o = orc.assign(Xp, rpp, cip, modes, s2p, inst.lam)
-            r = slk.assign(x, g, modes, lam=inst.lam, fixed_inner=o["n_pass"], prec=prec)
+            r = slk.assign(x, g, modes, lam=inst.lam, prec=prec)
+            o = orc.assign(inst.X, rp, ci, modes, s2, inst.lam, n_inner=r["result"]["inner_iters_last"])
             dz = max(dz, float(np.abs(r["z"].cpu().numpy() - o["Z"]).max()))
             nxt = r["modes_next"].astype(np.int64)
             if np.array_equal(nxt, modes):
@@ -364,39 +384,87 @@ def precision(slk, torch, big_x, big_g, big_inst, r32):
         lab = r["labels"].cpu().numpy()
         srt = np.sort(o["S"], axis=1)
         resolvable = (srt[:, -1] - srt[:, -2]) > 1e-6 + 64 * np.spacing(np.abs(srt[:, -1]).astype(np.float32)) \
-            + inst.lam * np.diff(rpp) * 1e-5
-        E_orc = orc.energy_of(inst.X, rpp, cip, lab, modes, s2p, inst.lam)[0]
-        E_orc_own = o["E"] if prec == "fp32" else orc.energy_of(inst.X, rpp, cip, o["labels"], modes, s2p, inst.lam)[0]
-        free = slk.fit(x, g, inst.init_modes, lam=inst.lam, prec=prec)
-        ef = slk.energy(x, g32, free["labels"], free["modes"], lam=inst.lam)
+            + inst.lam * np.diff(rp) * 1e-5
+        E_orc = orc.energy_of(inst.X, rp, ci, lab, modes, s2, inst.lam)[0]
+        fr, ref, followed = _follow_gpu_picks(slk, orc, inst, x, g, rp, ci, s2, prec)
+        flab = fr["labels"].cpu().numpy()
+        fsrt = np.sort(ref["S"], axis=1)
+        fres = (fsrt[:, -1] - fsrt[:, -2]) > 1e-6 + 64 * np.spacing(np.abs(fsrt[:, -1]).astype(np.float32)) \
+            + inst.lam * np.diff(rp) * 1e-5
         out["small"][prec] = {
             "lockstep": {"outer": t + 1, "max_abs_dz": dz,
                          "label_agreement": float(np.mean(lab == o["labels"])),
                          "label_agreement_resolvable": float(np.mean(lab[resolvable] == o["labels"][resolvable])),
                          "rows_resolvable": int(resolvable.sum()),
-                         "rel_energy_gap_fp64": float(abs(r["result"]["energy_fp64"] - E_orc_own) / abs(E_orc_own)),
-                         "rel_energy_gap_at_gpu_labels": float(abs(r["result"]["energy_fp64"] - E_orc) / abs(E_orc))},
-            "free": {"same_modes_as_oracle": bool(np.array_equal(free["modes"], ref["modes"])),
-                     "energy": float(ef["energy_fp64"]), "oracle_energy": float(ref["E"]),
-                     "label_agreement": float(np.mean(free["labels"].cpu().numpy() == ref["labels"]))}}
-    # main workload: BF16-X graph and fit against the FP32 ones
-    t0 = time.perf_counter()
-    gb = slk.Graph.build_knn(big_x, k=big_inst.K, method="mfma", reorder=True, prec="bf16")
-    torch.cuda.synchronize()
-    tb = time.perf_counter() - t0
-    rb = slk.fit(big_x, gb, big_inst.init_modes, lam=big_inst.lam, prec="bf16")
-    ea = slk.energy(big_x, big_g, r32["labels"], r32["modes"], lam=big_inst.lam)
-    eb = slk.energy(big_x, big_g, rb["labels"], rb["modes"], lam=big_inst.lam)
-    terms = (ea["energy_fp64"] - big_inst.lam * ea["cut"]) * -1.0 + big_inst.lam * ea["cut"]
-    out["large"] = {"workload": "the main workload, BF16-X against FP32 (both on the FP32 problem)",
-                    "energy_fp32": ea["energy_fp64"], "energy_bf16": eb["energy_fp64"],
-                    "cut_fp32": ea["cut"], "cut_bf16": eb["cut"],
-                    "same_modes": bool(np.array_equal(rb["modes"], r32["modes"])),
-                    "rel_energy_gap": float(abs(eb["energy_fp64"] - ea["energy_fp64"]) / abs(ea["energy_fp64"])),
-                    "rel_energy_gap_of_terms": float(abs(eb["energy_fp64"] - ea["energy_fp64"]) / terms),
-                    "label_agreement": float((rb["labels"] == r32["labels"]).float().mean().item()),
-                    "bf16_graph_s": round(tb, 3), "bf16_outer": rb["result"]["outer_iters"],
-                    "bf16_inner_total": rb["result"]["inner_iters_total"]}
+                         "rel_energy_gap_fp64": float(abs(r["result"]["energy_fp64"] - E_orc) / abs(E_orc))},
+            "free": {"same_modes_as_oracle": bool(np.array_equal(fr["modes"], ref["modes"])),
+                     "outer_iterations_with_a_followed_pick": followed,
+                     "energy": float(fr["result"]["energy_fp64"]), "oracle_energy": float(ref["E"]),
+                     "rel_energy_gap": float(abs(fr["result"]["energy_fp64"] - ref["E"]) / abs(ref["E"])),
+                     "label_agreement": float(np.mean(flab == ref["labels"])),
+                     "label_agreement_resolvable": float(np.mean(flab[fres] == ref["labels"][fres]))}}
+    # main workload: BF16-X fit against the FP32 fit on the same graph, both timed
+    timing = {}
+    fits = {}
+    for prec in ("fp32", "bf16x"):
+        slk.fit(big_x, big_g, big_inst.init_modes, lam=big_inst.lam, prec=prec)
+        torch.cuda.synchronize()
+        slk.timing_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(3):
+            fits[prec] = slk.fit(big_x, big_g, big_inst.init_modes, lam=big_inst.lam, prec=prec)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / 3
+        nu, ums = slk.timing_read("unary_kernel")
+        slk.timing_enable(False)
+        timing[prec] = {"fit_ms": round(wall * 1e3, 3), "unary_kernel_us": round(ums / max(nu, 1) * 1e3, 2)}
+    a, b = fits["fp32"], fits["bf16x"]
+    ea, eb = a["result"]["energy_fp64"], b["result"]["energy_fp64"]
+    terms = (big_inst.lam * a["result"]["cut"] - ea) + big_inst.lam * a["result"]["cut"]
+    out["large"] = {"workload": "the main workload, BF16-X against FP32 (same graph, FP64 energy rechecks)",
+                    "energy_fp32": ea, "energy_bf16x": eb, "cut_fp32": a["result"]["cut"], "cut_bf16x": b["result"]["cut"],
+                    "same_modes": bool(np.array_equal(a["modes"], b["modes"])),
+                    "rel_energy_gap": float(abs(eb - ea) / abs(ea)),
+                    "rel_energy_gap_of_terms": float(abs(eb - ea) / terms),
+                    "label_agreement": float((a["labels"] == b["labels"]).float().mean().item()),
+                    "outer": [a["result"]["outer_iters"], b["result"]["outer_iters"]],
+                    "inner_total": [a["result"]["inner_iters_total"], b["result"]["inner_iters_total"]],
+                    "timing": timing}
+    return out
+
+
+def other_workloads(slk, torch, names=("images-70k", "embeddings-100k"), steps=3):
+    """The z-update's roofline on the other named workloads (MFMA graph, locality order): HIP-event
+    time of the z-updates that ran, over the fits' passes, against their algorithmic bytes."""
+    import gen
+    out = {}
+    for name in names:
+        inst = gen.make(name)
+        x = torch.from_numpy(inst.X).to("cuda")
+        g = slk.Graph.build_knn(x, k=inst.K, method="mfma", reorder=True)
+        nnz = g.info()["nnz"]
+        r = slk.fit(x, g, inst.init_modes, lam=inst.lam)
+        torch.cuda.synchronize()
+        slk.timing_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            r = slk.fit(x, g, inst.init_modes, lam=inst.lam)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / steps
+        n_it, it_ms = slk.timing_read("iter_kernel")
+        slk.timing_enable(False)
+        avg = it_ms / max(n_it, 1)
+        alg = bytes_iter(inst.N, nnz, inst.L)
+        ach = alg / (avg / 1e3) / 1e9
+        out[name] = {"N": inst.N, "D": inst.D, "L": inst.L, "k": inst.K, "nnz": nnz, "fit_ms": round(wall * 1e3, 3),
+                     "outer_iters": r["result"]["outer_iters"], "inner_iters_total": r["result"]["inner_iters_total"],
+                     "roofline": {"kernel": "iter_kernel", "bound": "hbm", "achieved": round(ach, 1),
+                                  "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                                  "traffic": traffic_entry("iter_kernel", name), "alg_bytes_per_launch": alg,
+                                  "avg_launch_us": round(avg * 1e3, 2), "launches": n_it}}
+        log(f"[other] {name}: {out[name]}")
+        g.close()
+        del x
     return out
 
 
@@ -506,14 +574,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--reorder", type=int, default=1)
     ap.add_argument("--precision", type=int, default=1, help="report FP32/BF16-X errors (0 = skip)")
-    ap.add_argument("--serve-jobs", type=int, default=300, help="jobs in the served-form run (0 = skip)")
-    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-jobs", type=int, default=2000, help="jobs in the served-form run (0 = skip)")
+    ap.add_argument("--serve-rate", type=float, default=800.0)
     ap.add_argument("--serve-slots", type=int, default=64)
-    ap.add_argument("--serve-sweep", default="",
+    ap.add_argument("--serve-sweep", default="800",
                     help="comma-separated arrival rates: the served form at each, FP32 and BF16-X (replaces the "
                          "single-rate run)")
     ap.add_argument("--extensions", type=int, default=1,
                     help="time seeding, exact modes, mean-shift and out-of-sample assignment (0 = skip)")
+    ap.add_argument("--other", type=int, default=1, help="z-update roofline on images-70k and embeddings-100k (0 = skip)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -599,6 +668,10 @@ def main():
         ext = extensions(slk, torch, x, g, inst, fr["z"], fr["modes"], args.workload)
         del fr
 
+    other = None
+    if args.other:
+        other = other_workloads(slk, torch)
+
     serve = None
     if args.serve_jobs > 0 and args.serve_sweep:
         rates = [float(v) for v in args.serve_sweep.split(",")]
@@ -664,6 +737,7 @@ def main():
             "rows_fallback": info["rows_fallback"],
         },
         "precision": prec,
+        "other_workloads": other,
         "serving": serve,
         "extensions": ext,
         "fit": {k: r0[k] for k in ("energy", "energy_fp64", "bound", "cut", "n_distinct_modes", "converged")},
