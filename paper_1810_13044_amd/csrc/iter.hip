@@ -359,7 +359,7 @@ __global__ __launch_bounds__(kBlock) void final_kernel(FinalArgs f) {
         ti = oi;
       }
     }
-    const int jt = ti;
+    const int jt = ti < L ? ti : 0;  // a valid index whatever the logits (see final_row)
     // second largest logit (over j != jt) and the sums needed by the log-odds
     float m2 = -INFINITY, T = 0.f;
 #pragma unroll
@@ -699,6 +699,8 @@ __device__ __forceinline__ bool heavy_row(const IterArgs& a, int hb, int wave, i
   __syncthreads();
   if (wave == 0) {
     float4 b = make_float4(0.f, 0.f, 0.f, 0.f);
+    // a short unroll: a full one holds every group's share in registers at once
+#pragma unroll 4
     for (int q = 0; q < NG; ++q) {
       const float4 v = hsum[q * G + j];
       b.x += v.x;
@@ -798,7 +800,9 @@ __device__ __forceinline__ void final_row(const FinalArgs& f, int64_t row, bool 
       ti = 4 * j + e;
     }
   gargmax4<G>(tv, ti);
-  const int jt = ti;
+  // every logit is finite when the bound of the pass was (the loop stops on a non-finite bound),
+  // so ti < L; the clamp keeps the label a valid index regardless
+  const int jt = ti < L ? ti : 0;
   float m2 = -INFINITY, T = 0.f;
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
