@@ -66,13 +66,20 @@ def bytes_energy(N, nnz, D, fp64):
     return 4 * (N + 1) + 4 * nnz + 8 * N + (4 * N * D if fp64 else 0)
 
 
+def emits(L):
+    """Whether a fit's z-updates also write the labels and mode candidates (8 < L <= 64), in
+    place of a final pass per outer iteration."""
+    return 8 < L <= 64
+
+
 def fit_bytes(N, D, L, nnz, inner_total, outer):
-    """Every launch of a fit: per outer iteration the unary term, the z-updates and the final
-    pass; once per fit the energy of the last outer iteration with its FP64 recheck in the same
-    pass (the earlier ones are skipped on the device: a mode moved, so another outer iteration
-    follows) and the scatter of Z to the caller's order."""
-    return (inner_total * bytes_iter(N, nnz, L)
-            + outer * (bytes_final(N, nnz, L) + bytes_unary(N, D, L))
+    """Every launch of a fit: per outer iteration the unary term, the z-updates and either the
+    final pass or, where the z-updates carry it, the labels they write; once per fit the energy of
+    the last outer iteration with its FP64 recheck in the same pass (the earlier ones are skipped
+    on the device: a mode moved, so another outer iteration follows) and the scatter of Z to the
+    caller's order."""
+    per_outer = bytes_unary(N, D, L) + (4 * N if emits(L) else bytes_final(N, nnz, L))
+    return (inner_total * bytes_iter(N, nnz, L) + outer * per_outer
             + bytes_energy(N, nnz, D, True) + bytes_scatter(N, L))
 
 

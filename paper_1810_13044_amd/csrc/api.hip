@@ -305,7 +305,7 @@ slk_status watch_for_device(Watch** out) {
 // kernels local to this file ----------------------------------------------------------------
 namespace {
 
-__global__ void init_state_kernel(IterState* st, double tol, int check, int cap) {
+__global__ void init_state_kernel(IterState* st, double tol, int check, int cap, int last_pass) {
   st->pass = 0;
   st->done = 0;
   st->numeric = 0;
@@ -313,6 +313,10 @@ __global__ void init_state_kernel(IterState* st, double tol, int check, int cap)
   st->check = check;
   st->trace_cap = cap;
   st->last_bound = 0.0;
+  st->rel = 0.0;
+  st->rel_prev = 0.0;
+  st->last_pass = last_pass;
+  st->emit_pass = -1;
 }
 
 __global__ void check_indices_kernel(const int32_t* __restrict__ v, int64_t count, int64_t n, int32_t* bad) {
@@ -694,19 +698,41 @@ slk_status run_outer(const float* x, int64_t n, int32_t d, const slk_graph* g, i
                          nullptr, w.mvec));
   }
   const int check = p.fixed_inner > 0 ? 0 : 1;
-  hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(1), 0, s, w.state, p.bound_tol, check, trace_cap);
-  hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(1), 0, s, w.state2, 0.0, 0, 0);
+  hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(1), 0, s, w.state, p.bound_tol, check, trace_cap,
+                     (check ? p.max_inner : p.fixed_inner) - 1);
+  hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(1), 0, s, w.state2, 0.0, 0, 0, -1);
   SLK_LAUNCHED("init_state_kernel");
   IterArgs a = make_iter(g, w, n, L, p);
   IterState hs{};
   int launched = 0;
   Watch* wt = nullptr;
   SLK_TRY(watch_for_device(&wt));
+  // For 8 < L <= 64 the z-update that the device expects to end the loop (the last pass allowed,
+  // or the relative change of the bound predicted below the tolerance from the two passes
+  // before) also leaves the labels and byproduct-mode candidates of its input, which is what the
+  // final pass computes from it, and records its index in the state; the bound of every pass
+  // goes to the host-mapped results.  The final pass then runs only if the pass that ended the
+  // loop was not that one.  (For L <= 8 the extra registers would cost the z-update a wave per
+  // SIMD.)
+  const bool emit = L > 8 && L <= 64;
+  FinalArgs fe{};
+  if (emit) {
+    a.bound_out = &wt->oh_dev->bound;
+    fe.perm = g->perm;
+    fe.labels_int = w.labels_int;
+    fe.cand_v = w.cand_v;
+    fe.cand_i = w.cand_i;
+  }
+  auto launch_pass = [&]() -> slk_status {
+    if (!emit) return launch_iter(a, w.grid, s);
+    fe.it = a;
+    return launch_iter_emit(fe, w.grid, s);
+  };
   if (!check) {
     for (; launched < p.fixed_inner; ++launched) {
       a.Zin = w.Z[launched & 1];
       a.Zout = w.Z[(launched + 1) & 1];
-      SLK_TRY(launch_iter(a, w.grid, s));
+      SLK_TRY(launch_pass());
     }
     SLK_HIP(hipMemcpyAsync(&hs, w.state, sizeof(IterState), hipMemcpyDeviceToHost, s));
     SLK_HIP(hipStreamSynchronize(s));
@@ -719,7 +745,7 @@ slk_status run_outer(const float* x, int64_t n, int32_t d, const slk_graph* g, i
       a.Zin = w.Z[k & 1];
       a.Zout = w.Z[(k + 1) & 1];
       a.mirror = wt->dev + (k & 1);
-      SLK_TRY(launch_iter(a, w.grid, s));
+      SLK_TRY(launch_pass());
       SLK_HIP(hipEventRecord(wt->ev[k & 1], s));
       return SLK_OK;
     };
@@ -746,22 +772,25 @@ slk_status run_outer(const float* x, int64_t n, int32_t d, const slk_graph* g, i
   if (passes < 1) return fail(SLK_ERR_INVALID_ARG, "at least one z-update is needed");
   o->passes = passes;
   o->converged = check ? hs.done : 1;
-  // final pass on the input of the last z-update: labels, modes, Z in the caller's order
-  FinalArgs f{};
-  f.it = a;
-  f.it.Zin = w.Z[(passes - 1) & 1];
-  f.it.Zout = nullptr;
-  f.it.state = w.state2;
-  f.it.partial = w.partial2;
-  f.it.trace = nullptr;
-  f.it.bound_out = &wt->oh_dev->bound;
-  f.perm = g->perm;
-  f.z_user = nullptr;
-  f.labels_int = w.labels_int;
-  f.labels_user = nullptr;
-  f.cand_v = w.cand_v;
-  f.cand_i = w.cand_i;
-  SLK_TRY(launch_final(f, w.grid, s));
+  if (!emit || hs.emit_pass != passes - 1) {
+    // final pass on the input of the last z-update: its labels, modes candidates and bound
+    FinalArgs f{};
+    f.it = a;
+    f.it.Zin = w.Z[(passes - 1) & 1];
+    f.it.Zout = nullptr;
+    f.it.state = w.state2;
+    f.it.partial = w.partial2;
+    f.it.trace = nullptr;
+    f.it.bound_out = &wt->oh_dev->bound;
+    f.it.mirror = nullptr;
+    f.perm = g->perm;
+    f.z_user = nullptr;
+    f.labels_int = w.labels_int;
+    f.labels_user = nullptr;
+    f.cand_v = w.cand_v;
+    f.cand_i = w.cand_i;
+    SLK_TRY(launch_final(f, w.grid, s));
+  }
   {
     KernelTimer kt("mode_reduce_kernel", s);
     SLK_TRY(launch_mode_reduce(w.cand_v, w.cand_i, w.grid, L, w.modes_next, s, wt->oh_dev->modes_next,
@@ -1222,7 +1251,7 @@ slk_status slk_inner_step(const slk_graph* g, int32_t L, const float* a, const f
     Zi = tz;
     Zo = z_out ? to : nullptr;
   }
-  hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(1), 0, s, w.state, 0.0, 0, 0);
+  hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(1), 0, s, w.state, 0.0, 0, 0, -1);
   SLK_LAUNCHED("init_state_kernel");
   IterArgs ia = make_iter(g, w, n, L, p);
   ia.A = A;
@@ -1476,7 +1505,7 @@ slk_status slk_energy(const float* x, int64_t n, int32_t d, const slk_graph* g, 
       SLK_TRY(launch_gather_rows(z, g->perm, n, L, ldz_for(L), w.Z[0], s));
       Zi = w.Z[0];
     }
-    hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(1), 0, s, w.state, 0.0, 0, 0);
+    hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(1), 0, s, w.state, 0.0, 0, 0, -1);
     SLK_LAUNCHED("init_state_kernel");
     IterArgs ia = make_iter(g, w, n, L, p);
     ia.Zin = Zi;

@@ -173,6 +173,10 @@ struct IterState {
   int32_t check;       // 1: test convergence; 0: fixed pass count
   int32_t trace_cap;
   double last_bound;
+  double rel;          // relative change of the bound in the last pass (0 before two passes)
+  double rel_prev;     // the same, one pass earlier
+  int32_t last_pass;   // index of the last pass allowed (-1: no z-update writes labels)
+  int32_t emit_pass;   // the pass that wrote labels and mode candidates (-1: none yet)
 };
 
 // Internal row stride of A and Z: L rounded up to a multiple of 4 (float4 rows) when L <= 64.
@@ -306,6 +310,9 @@ int64_t iter_rows_per_group(int32_t L);
 int iter_grid_rows(int64_t n, int32_t L);
 slk_status launch_iter_rows(const IterArgs& a, int grid, hipStream_t s);
 slk_status launch_final(const FinalArgs& a, int grid, hipStream_t s);
+// The z-update (L <= 64) that also writes the labels and byproduct-mode candidates of its input,
+// as launch_final would from the same input, and its pass reduction.
+slk_status launch_iter_emit(const FinalArgs& f, int grid, hipStream_t s);
 // modes_out: L int32 on the device; mirror (may be null): a second copy, e.g. host-mapped memory;
 // cur and moved (both null or both set): moved[l] = (modes_out[l] != cur[l]).
 slk_status launch_mode_reduce(const float* cand_v, const int32_t* cand_i, int grid, int32_t L, int32_t* modes_out,

@@ -266,6 +266,8 @@ __device__ __forceinline__ void reduce_pass(const double* __restrict__ partial, 
     } else if (st->check && pass >= 1 && fabs(R - st->last_bound) <= st->tol * fabs(st->last_bound)) {
       st->done = 1;
     }
+    st->rel_prev = st->rel;
+    st->rel = pass >= 1 ? fabs(R - st->last_bound) / fabs(st->last_bound) : 0.0;
     st->last_bound = R;
     st->pass = pass + 1;
     if (mirror) *mirror = *st;
@@ -716,14 +718,34 @@ __device__ __forceinline__ bool heavy_row(const IterArgs& a, int hb, int wave, i
 }
 
 template <int G>
-__device__ __forceinline__ void iter4_block(const IterArgs& a, int bid) {
+__device__ __forceinline__ void final_row(const FinalArgs& f, int64_t row, bool valid, bool store, int j, const Row4& o,
+                                          float (&bv)[4], int (&bi)[4], double& acc);
+template <int G>
+__device__ __forceinline__ void block_candidates(const FinalArgs& f, int bid, float (&bv)[4], int (&bi)[4], int g, int j,
+                                                 int wave);
+
+// One work-group of the z-update.  With EMIT it also produces what the final pass would produce
+// from the same input (labels in f->labels_int, the work-group's byproduct-mode candidates in
+// f->cand_v / f->cand_i), with the same per-row arithmetic: the pass that ends the loop then
+// leaves them behind and no separate final pass is needed.
+template <int G, bool EMIT>
+__device__ __forceinline__ void iter4_body(const IterArgs& a, const FinalArgs* f, int bid) {
   if (a.state->done) return;
   constexpr int RW = 64 / G;  // rows per wave
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane / G, j = lane % G;
   const uint32_t L4 = (uint32_t)(a.ldz >> 2);
   float4* __restrict__ O4 = reinterpret_cast<float4*>(a.Zout);
-  double acc = 0.0;
+  double acc = 0.0, unused = 0.0;
+  float bv[4];
+  int bi[4];
+  if constexpr (EMIT) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      bv[e] = -INFINITY;
+      bi[e] = INT32_MAX;
+    }
+  }
   if (bid < a.hblocks) {
     uint32_t rowc;
     Row4 o;
@@ -732,6 +754,11 @@ __device__ __forceinline__ void iter4_block(const IterArgs& a, int bid) {
       if (O4 && (uint32_t)j < L4)
         __builtin_nontemporal_store(vf4{o.z[0], o.z[1], o.z[2], o.z[3]}, reinterpret_cast<vf4*>(O4) + (rowc * L4 + j));
       if (j == 0) acc = (double)o.r;
+    }
+    // every group of wave 0 holds the same row: all offer the same candidates, group 0 stores
+    if constexpr (EMIT) {
+      if (wave == 0) final_row<G>(*f, rowc, valid, g == 0, j, o, bv, bi, unused);
+      block_candidates<G>(*f, bid, bv, bi, g, j, wave);
     }
     block_partial<RW>(a.partial, bid, acc, g, j);
     return;
@@ -768,20 +795,52 @@ __device__ __forceinline__ void iter4_block(const IterArgs& a, int bid) {
         __builtin_nontemporal_store(vf4{o.z[0], o.z[1], o.z[2], o.z[3]}, reinterpret_cast<vf4*>(O4) + (rowc * L4 + j));
       if (j == 0) acc += (double)o.r;
     }
+    if constexpr (EMIT) final_row<G>(*f, row, valid, true, j, o, bv, bi, unused);
   }
+  if constexpr (EMIT) block_candidates<G>(*f, bid, bv, bi, g, j, wave);
   block_partial<RW>(a.partial, bid, acc, g, j);
 }
 
 template <int G>
 __global__ __launch_bounds__(kBlock) void iter4_kernel(IterArgs a) {
-  iter4_block<G>(a, blockIdx.x);
+  iter4_body<G, false>(a, nullptr, blockIdx.x);
+}
+
+// Whether the z-update about to run (index st->pass) is expected to end the loop: it is the last
+// pass allowed, or, testing convergence, the relative change of the bound predicted for it from
+// the two passes before (geometric decay, ratio at most 1) is within twice the tolerance.  Every
+// work-group reads the same state, so all take the same branch.
+__device__ __forceinline__ bool expect_last_pass(const IterState* st) {
+  const int k = st->pass;
+  if (k >= st->last_pass) return true;
+  if (!st->check || k < 2) return false;
+  const double r1 = st->rel, r0 = st->rel_prev;
+  const double pred = r0 > 0.0 ? r1 * fmin(r1 / r0, 1.0) : r1;
+  return pred <= 2.0 * st->tol;
+}
+
+// The z-update that writes the labels and byproduct-mode candidates of its input when it expects
+// to end the loop (work-group 0 records the pass in st->emit_pass), and is the plain z-update
+// otherwise.  Four waves per SIMD (at most 128 registers) where that needs no spills, as for the
+// plain z-update; the host uses this form for L > 8 only.
+template <int G>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(G >= 4 ? 4 : 1))) void iter4_emit_kernel(
+    FinalArgs f) {
+  IterState* st = f.it.state;
+  if (st->done) return;
+  if (expect_last_pass(st)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->emit_pass = st->pass;
+    iter4_body<G, true>(f.it, &f, blockIdx.x);
+  } else {
+    iter4_body<G, false>(f.it, nullptr, blockIdx.x);
+  }
 }
 
 template <int G>
 __global__ __launch_bounds__(kBlock) void iter4_packed(const IterArgs* __restrict__ jobs,
                                                        const int32_t* __restrict__ start, int njobs) {
   const int j = job_of(start, njobs, blockIdx.x);
-  iter4_block<G>(jobs[j], blockIdx.x - start[j]);
+  iter4_body<G, false>(jobs[j], nullptr, blockIdx.x - start[j]);
 }
 
 // Labels, byproduct-mode candidates and caller-order outputs of one finished row.  `valid`
@@ -851,6 +910,51 @@ __device__ __forceinline__ void final_row(const FinalArgs& f, int64_t row, bool 
   }
 }
 
+// The work-group's best byproduct-mode candidate per cluster (largest log-odds, ties to the
+// smaller index) from the lanes' candidates, to cand_v / cand_i[l * grid + bid].  Reached by the
+// whole work-group.
+template <int G>
+__device__ __forceinline__ void block_candidates(const FinalArgs& f, int bid, float (&bv)[4], int (&bi)[4], int g, int j,
+                                                 int wave) {
+  // combine the candidates of the groups of this wave (same j in every group)
+#pragma unroll
+  for (int off = G; off < 64; off <<= 1) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const float ov = __shfl_xor(bv[e], off);
+      const int oi = __shfl_xor(bi[e], off);
+      if (ov > bv[e] || (ov == bv[e] && oi < bi[e])) {
+        bv[e] = ov;
+        bi[e] = oi;
+      }
+    }
+  }
+  __shared__ float cv[4][64];
+  __shared__ int ci[4][64];
+  if (g == 0) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      if (4 * j + e < 64) {
+        cv[wave][4 * j + e] = bv[e];
+        ci[wave][4 * j + e] = bi[e];
+      }
+    }
+  }
+  __syncthreads();
+  for (int l = threadIdx.x; l < f.it.L; l += kBlock) {
+    float v = cv[0][l];
+    int i = ci[0][l];
+    for (int w = 1; w < 4; ++w) {
+      if (cv[w][l] > v || (cv[w][l] == v && ci[w][l] < i)) {
+        v = cv[w][l];
+        i = ci[w][l];
+      }
+    }
+    f.cand_v[(int64_t)l * f.grid + bid] = v;
+    f.cand_i[(int64_t)l * f.grid + bid] = i;
+  }
+}
+
 template <int G>
 __device__ __forceinline__ void final4_block(const FinalArgs& f, int bid) {
   const IterArgs& a = f.it;
@@ -889,43 +993,7 @@ __device__ __forceinline__ void final4_block(const FinalArgs& f, int bid) {
       final_row<G>(f, row, valid, true, j, o, bv, bi, acc);
     }
   }
-  // combine the candidates of the groups of this wave (same j in every group)
-#pragma unroll
-  for (int off = G; off < 64; off <<= 1) {
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const float ov = __shfl_xor(bv[e], off);
-      const int oi = __shfl_xor(bi[e], off);
-      if (ov > bv[e] || (ov == bv[e] && oi < bi[e])) {
-        bv[e] = ov;
-        bi[e] = oi;
-      }
-    }
-  }
-  __shared__ float cv[4][64];
-  __shared__ int ci[4][64];
-  if (g == 0) {
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      if (4 * j + e < 64) {
-        cv[wave][4 * j + e] = bv[e];
-        ci[wave][4 * j + e] = bi[e];
-      }
-    }
-  }
-  __syncthreads();
-  for (int l = threadIdx.x; l < L; l += kBlock) {
-    float v = cv[0][l];
-    int i = ci[0][l];
-    for (int w = 1; w < 4; ++w) {
-      if (cv[w][l] > v || (cv[w][l] == v && ci[w][l] < i)) {
-        v = cv[w][l];
-        i = ci[w][l];
-      }
-    }
-    f.cand_v[(int64_t)l * f.grid + bid] = v;
-    f.cand_i[(int64_t)l * f.grid + bid] = i;
-  }
+  block_candidates<G>(f, bid, bv, bi, g, j, wave);
   block_partial<RW>(a.partial, bid, acc, g, j);
 }
 
@@ -1433,6 +1501,21 @@ int iter_grid_rows(int64_t n, int32_t L) {
 slk_status launch_iter_rows(const IterArgs& a, int grid, hipStream_t s) {
   SLK_DISPATCH_LANES(a.L, iter_kernel, dim3(grid), dim3(kBlock), 0, s, a);
   SLK_LAUNCHED("iter_kernel");
+  hipLaunchKernelGGL(pass_reduce_kernel, dim3(1), dim3(kRedBlock), 0, s, a.partial, grid, a.state, a.trace, a.bound_out,
+                     a.mirror);
+  SLK_LAUNCHED("pass_reduce_kernel");
+  return SLK_OK;
+}
+
+slk_status launch_iter_emit(const FinalArgs& f0, int grid, hipStream_t s) {
+  FinalArgs f = f0;
+  f.grid = grid;
+  const IterArgs& a = f.it;
+  {
+    KernelTimer kt("iter_kernel", s);
+    SLK_DISPATCH_G4(a.L, iter4_emit_kernel, dim3(grid), dim3(kBlock), 0, s, f);
+    SLK_LAUNCHED("iter_kernel");
+  }
   hipLaunchKernelGGL(pass_reduce_kernel, dim3(1), dim3(kRedBlock), 0, s, a.partial, grid, a.state, a.trace, a.bound_out,
                      a.mirror);
   SLK_LAUNCHED("pass_reduce_kernel");

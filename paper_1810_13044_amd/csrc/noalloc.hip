@@ -32,6 +32,10 @@ __global__ void noalloc_init_state(IterState* st) {
   st->check = 0;
   st->trace_cap = 0;
   st->last_bound = 0.0;
+  st->rel = 0.0;
+  st->rel_prev = 0.0;
+  st->last_pass = -1;
+  st->emit_pass = -1;
 }
 
 // Device address of this device's scratch array (looked up once per device).

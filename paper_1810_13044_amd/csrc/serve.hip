@@ -64,6 +64,10 @@ __global__ void init_jobs_kernel(const InitJob* __restrict__ jobs, int count) {
     j.st->check = j.check;
     j.st->trace_cap = 0;
     j.st->last_bound = 0.0;
+    j.st->rel = 0.0;
+    j.st->rel_prev = 0.0;
+    j.st->last_pass = -1;
+    j.st->emit_pass = -1;
     j.st2->pass = 0;
     j.st2->done = 0;
     j.st2->numeric = 0;
@@ -71,6 +75,10 @@ __global__ void init_jobs_kernel(const InitJob* __restrict__ jobs, int count) {
     j.st2->check = 0;
     j.st2->trace_cap = 0;
     j.st2->last_bound = 0.0;
+    j.st2->rel = 0.0;
+    j.st2->rel_prev = 0.0;
+    j.st2->last_pass = -1;
+    j.st2->emit_pass = -1;
   }
   for (int l = threadIdx.x; l < j.L; l += blockDim.x) j.dst[l] = j.modes[l];
 }
