@@ -173,7 +173,10 @@ typedef struct {
   int32_t pairwise_scale; /* 1: z = softmax(a + lambda b) as in Eq. (8); 2: softmax(a + 2 lambda b),
                              the exact minimiser for Eq. (2) as printed                          */
   slk_precision prec;     /* precision of X in the unary distances                              */
-  int32_t reserved;
+  int32_t final_pass;     /* 0: for 8 < L <= 64 the z-update expected to end the inner loop also
+                             writes the labels and mode candidates of its input, and a separate
+                             final pass runs only if another pass ended it; 1: always the separate
+                             final pass.  The results are identical.                            */
 } slk_params;
 
 typedef struct {
@@ -182,7 +185,7 @@ typedef struct {
   int32_t inner_iters_last;   /* z-updates of the last outer iteration                      */
   int32_t converged;          /* fit: modes unchanged; assign: bound settled (or fixed count) */
   int32_t n_distinct_modes;
-  int32_t reserved;
+  int32_t final_passes;       /* outer iterations that ran a separate final pass             */
   double energy;              /* E(l, M) of Eq. (1) at the hard labels, unary term from FP32 A  */
   double energy_fp64;         /* the same with the unary term recomputed in FP64 from X         */
   double bound;               /* relaxed bound R(Z^i) of the last z-update's input              */

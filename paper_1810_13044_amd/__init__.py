@@ -52,7 +52,7 @@ def _prec(p) -> int:
 
 
 def params(lam=1.0, sigma2=0.0, delta=0.0, tol=1e-8, max_outer=20, max_inner=1000, fixed_inner=0,
-           scale=1, prec="fp32") -> _lib.Params:
+           scale=1, prec="fp32", final_pass=0) -> _lib.Params:
     lib = _lib.load()
     p = _lib.Params()
     _lib.check(lib.slk_params_default(C.byref(p)))
@@ -65,6 +65,7 @@ def params(lam=1.0, sigma2=0.0, delta=0.0, tol=1e-8, max_outer=20, max_inner=100
     p.fixed_inner = int(fixed_inner)
     p.pairwise_scale = int(scale)
     p.prec = _prec(prec)
+    p.final_pass = int(final_pass)
     return p
 
 

@@ -39,13 +39,13 @@ class Params(C.Structure):
     _fields_ = [("lambda_", C.c_double), ("sigma2", C.c_double), ("delta", C.c_double),
                 ("bound_tol", C.c_double), ("max_outer", C.c_int32), ("max_inner", C.c_int32),
                 ("fixed_inner", C.c_int32), ("pairwise_scale", C.c_int32), ("prec", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("final_pass", C.c_int32)]
 
 
 class Result(C.Structure):
     _fields_ = [("outer_iters", C.c_int32), ("inner_iters_total", C.c_int32),
                 ("inner_iters_last", C.c_int32), ("converged", C.c_int32),
-                ("n_distinct_modes", C.c_int32), ("reserved", C.c_int32), ("energy", C.c_double),
+                ("n_distinct_modes", C.c_int32), ("final_passes", C.c_int32), ("energy", C.c_double),
                 ("energy_fp64", C.c_double), ("bound", C.c_double), ("cut", C.c_int64)]
 
     def as_dict(self):

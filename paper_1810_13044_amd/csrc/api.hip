@@ -659,6 +659,7 @@ struct OuterOut {
   double energy = 0, energy64 = 0, bound = 0;
   long long cut = 0;
   int32_t modes_next[256] = {};  // the byproduct modes (also in Work::modes_next on the device)
+  int final_pass = 0;            // 1 if the separate final pass ran
 };
 
 IterArgs make_iter(const slk_graph* g, const Work& w, int64_t n, int32_t L, const slk_params& p) {
@@ -714,7 +715,7 @@ slk_status run_outer(const float* x, int64_t n, int32_t d, const slk_graph* g, i
   // goes to the host-mapped results.  The final pass then runs only if the pass that ended the
   // loop was not that one.  (For L <= 8 the extra registers would cost the z-update a wave per
   // SIMD.)
-  const bool emit = L > 8 && L <= 64;
+  const bool emit = L > 8 && L <= 64 && p.final_pass == 0;
   FinalArgs fe{};
   if (emit) {
     a.bound_out = &wt->oh_dev->bound;
@@ -772,7 +773,8 @@ slk_status run_outer(const float* x, int64_t n, int32_t d, const slk_graph* g, i
   if (passes < 1) return fail(SLK_ERR_INVALID_ARG, "at least one z-update is needed");
   o->passes = passes;
   o->converged = check ? hs.done : 1;
-  if (!emit || hs.emit_pass != passes - 1) {
+  o->final_pass = !emit || hs.emit_pass != passes - 1;
+  if (o->final_pass) {
     // final pass on the input of the last z-update: its labels, modes candidates and bound
     FinalArgs f{};
     f.it = a;
@@ -870,6 +872,7 @@ slk_status check_params(const slk_params* p) {
   if (p->fixed_inner < 0) return fail(SLK_ERR_INVALID_ARG, "fixed_inner must be >= 0");
   if (p->pairwise_scale != 1 && p->pairwise_scale != 2) return fail(SLK_ERR_INVALID_ARG, "pairwise_scale must be 1 or 2");
   if (p->prec != SLK_PREC_FP32 && p->prec != SLK_PREC_BF16 && p->prec != SLK_PREC_BF16X) return fail(SLK_ERR_INVALID_ARG, "unknown precision");
+  if (p->final_pass != 0 && p->final_pass != 1) return fail(SLK_ERR_INVALID_ARG, "final_pass must be 0 or 1");
   return SLK_OK;
 }
 
@@ -974,6 +977,7 @@ slk_status slk_params_default(slk_params* p) {
   p->fixed_inner = 0;
   p->pairwise_scale = 1;
   p->prec = SLK_PREC_FP32;
+  p->final_pass = 0;
   return SLK_OK;
 }
 
@@ -1297,6 +1301,7 @@ static slk_status assign_or_fit(bool fit, const float* x, int64_t n, int32_t d, 
     r.outer_iters = t + 1;
     r.inner_iters_total += o.passes;
     r.inner_iters_last = o.passes;
+    r.final_passes += o.final_pass;
     r.energy = o.energy;
     r.energy_fp64 = o.energy64;
     r.bound = o.bound;
@@ -1384,6 +1389,7 @@ slk_status slk_fit_ms(const float* x, int64_t n, int32_t d, const slk_graph* g, 
     r.outer_iters = t + 1;
     r.inner_iters_total += o.passes;
     r.inner_iters_last = o.passes;
+    r.final_passes += o.final_pass;
     r.energy = o.energy;
     r.energy_fp64 = o.energy64;
     r.bound = o.bound;

@@ -750,6 +750,7 @@ slk_status server_step(slk_server* sv) {
       done = true;
     } else if (j->phase == Phase::kFinal) {
       j->r.outer_iters += 1;
+      j->r.final_passes += 1;  // the served form always runs the final pass
       j->r.inner_iters_total += j->passes;
       j->r.inner_iters_last = j->passes;
       j->r.cut = sl.cut;

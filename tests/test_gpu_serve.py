@@ -28,7 +28,10 @@ def solo(slk, torch, inst, method="auto"):
 
 def same(a, b):
     assert b["status"] == 0, b["status"]
-    assert a["result"] == b["result"], (a["result"], b["result"])
+    # the served form always runs the separate final pass; everything else is identical
+    ra = {k: v for k, v in a["result"].items() if k != "final_passes"}
+    rb = {k: v for k, v in b["result"].items() if k != "final_passes"}
+    assert ra == rb, (a["result"], b["result"])
     assert np.array_equal(a["modes"], b["modes"])
     assert a["z"].equal(b["z"]) and a["labels"].equal(b["labels"])
 
