@@ -275,9 +275,11 @@ def _serve_once(slk, torch, insts, xs, arr, max_jobs, passes, prec):
             done[tick[tk]] = t
             served_out[tick[tk]] = o
             finished += 1
+    counters = sv.stats()
     sv.close()
     served = stats(done, done.max() - arr[0])
     served["steps"] = steps
+    served["server"] = counters     # step graphs captured / replayed, grouped kNN launches
     same = sum(1 for a, b in zip(plain_out, served_out)
                if a["result"]["energy_fp64"] == b["result"]["energy_fp64"] and torch.equal(a["labels"], b["labels"]))
     res = {"precision": prec, "plain": plain, "served": served,
@@ -331,6 +333,26 @@ def serving_sweep(slk, torch, n_jobs, rates, max_jobs, passes):
                     "same_modes_jobs": int(np.sum(same_modes)),
                     "identical_labels_jobs": int((agree == 1.0).sum()),
                     "label_agreement_median": float(np.median(agree)), "label_agreement_min": float(agree.min())}
+    # Precision alone: one outer iteration of each job from the FP32 fit's final modes, FP32 and
+    # BF16-X on the same graph (same modes, each to its own convergence), for every job whose
+    # free-running fits differ by more than 1e-4 and for the first 200 jobs.
+    pick = sorted(set(np.nonzero(gaps > 1e-4)[0].tolist()) | set(range(min(200, n_jobs))))
+    lgaps = {}
+    for j in pick:
+        inst, x = insts[j], xs[j]
+        g = slk.Graph.build_knn(x, k=10)
+        m = keep["fp32"][j]["modes"]
+        e = [slk.assign(x, g, m, lam=inst.lam, prec=pr, trace=False)["result"]["energy_fp64"] for pr in ("fp32", "bf16x")]
+        lgaps[j] = abs(e[1] - e[0]) / abs(e[0])
+        del g
+    lg = np.array([lgaps[j] for j in pick])
+    div = [j for j in pick if gaps[j] > 1e-4]
+    bf16_vs_fp32["lockstep"] = {
+        "what": "one outer iteration from the FP32 fit's final modes, FP32 and BF16-X, FP64 energy rechecks",
+        "jobs": len(pick), "within_1e-4": int((lg <= 1e-4).sum()), "within_1e-6": int((lg <= 1e-6).sum()),
+        "rel_gap_max": float(lg.max()),
+        "jobs_diverging_free": len(div),
+        "of_those_within_1e-4_lockstep": int(sum(lgaps[j] <= 1e-4 for j in div))}
     log(f"[serve] bf16x vs fp32: {bf16_vs_fp32}")
     return {"jobs": n_jobs, "max_jobs": max_jobs, "passes_per_step": passes, "workload": SERVE_WORKLOAD,
             "runs": runs, "bf16x_vs_fp32": bf16_vs_fp32}

@@ -193,13 +193,14 @@ __device__ __forceinline__ bf16x8 gload8(const uint16_t* __restrict__ p) {
 }
 
 // Candidate search.  A work-group owns kQT = 128 query rows, 32 per wave; keys stream past in
-// tiles of kKT = 64, each tile one 32-coordinate chunk at a time through a double-buffered LDS
-// stage (one barrier per chunk).  A wave multiplies its 32 rows by the 64 keys of a tile as two
-// 32 x 32 MFMA tiles; the query operands (bf16 hi and lo slices) stay in registers for the
-// whole scan when d <= 32 RES, else they are loaded with each chunk.  Each wave keeps the C
-// best lower bounds of each of its rows, sorted by (bound, index), in its own part of LDS, so
-// candidate merges need no barrier: a row with a few new candidates inserts them one by one, a
-// row with many merges them with a 128-wide bitonic sort.
+// tiles of kKT = 64, one 32-coordinate chunk at a time through an LDS stage (one barrier per
+// chunk).  For d <= 128 a stage holds two tiles (128 keys) and a wave multiplies its 32 rows by
+// them as four 32 x 32 MFMA tiles, 24 MFMAs between barriers with the bf16 split; above, one tile
+// per stage.  The query operands (bf16 hi and lo slices) stay in registers for the whole scan
+// when d <= 32 RES, else they are loaded with each chunk.  Each wave keeps the C best lower
+// bounds of each of its rows, sorted by (bound, index), in its own part of LDS, so candidate
+// merges need no barrier: a row with a few new candidates inserts them one by one, a row with
+// many merges them with a 128-wide bitonic sort.
 template <int I, int N, class F>
 __device__ __forceinline__ void static_for(F&& f) {
   if constexpr (I < N) {
@@ -233,19 +234,28 @@ __device__ __forceinline__ float list_insert(float* lv, int* li, int C, float v,
 }
 
 // Two waves per SIMD (at most 256 registers per lane): the scan is latency-bound below that.
+template <int RES>
+constexpr int cand_tiles() { return RES > 0 ? 2 : 1; }   // 64-key tiles per LDS stage
+template <int RES>
+constexpr int cand_ring() { return RES > 0 ? 2 : 3; }    // LDS stages in the ring
+
 template <bool SPLIT, int RES>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void cand_kernel(
     const uint16_t* __restrict__ xh, const uint16_t* __restrict__ xl, const float* __restrict__ nrm, int64_t n, int dp,
     int C, float c1, int32_t* __restrict__ cand, float* __restrict__ tau_out, const uint16_t* __restrict__ qh,
     const uint16_t* __restrict__ ql, const float* __restrict__ qn, int64_t nq, int self) {
+  constexpr int P = cand_tiles<RES>();       // tiles per stage
+  constexpr int NJ = 2 * P;                  // 32-key MFMA column tiles per stage
+  constexpr int RING = cand_ring<RES>();
   extern __shared__ unsigned char smraw[];
-  // key stage ring: [3 buffers][hi/lo][key][kRow] bf16, then the candidate lists [wave][row][C]
+  // key stage ring: [RING][hi/lo][key][kRow] bf16, then the candidate lists [wave][row][C]
   uint16_t* kst = reinterpret_cast<uint16_t*>(smraw);
-  constexpr int kStage = kKT * kRow;  // bf16 per array
+  constexpr int kStage = P * kKT * kRow;  // bf16 per array
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int half = lane >> 5, col = lane & 31;
-  float* lvw = reinterpret_cast<float*>(smraw + sizeof(uint16_t) * 6 * kStage) + wave * 32 * C;
-  int* liw = reinterpret_cast<int*>(smraw + sizeof(uint16_t) * 6 * kStage + sizeof(float) * 4 * 32 * C) + wave * 32 * C;
+  float* lvw = reinterpret_cast<float*>(smraw + sizeof(uint16_t) * 2 * RING * kStage) + wave * 32 * C;
+  int* liw = reinterpret_cast<int*>(smraw + sizeof(uint16_t) * 2 * RING * kStage + sizeof(float) * 4 * 32 * C) +
+             wave * 32 * C;
   const int64_t q0 = (int64_t)blockIdx.x * kQT + 32 * wave;
   const int nch = RES > 0 ? RES : dp / kDK;
   for (int e = lane; e < 32 * C; e += 64) {
@@ -275,23 +285,27 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
         al[c][s2] = SPLIT ? gload8(apl + kDK * c + 16 * s2) : ah[c][s2];
       }
   }
-  // staging: thread tid moves key tid / 4, 8 coordinates at (tid % 4) * 8, hi and lo, through
-  // two register slots (loads in flight two chunks ahead) into a ring of three LDS buffers
+  // staging: thread tid moves keys tid / 4 + 64 t (t < P), 8 coordinates at (tid % 4) * 8, hi
+  // and lo, through two register slots (loads in flight two chunks ahead) into the LDS ring
   const int skey = tid >> 2, spiece = (tid & 3) * 8;
   const int64_t nkt = (n + kKT - 1) / kKT;
-  const int64_t steps = nkt * nch;
-  uint4 ph[2], pl[2];
+  const int64_t nst = (nkt + P - 1) / P;   // stages of keys
+  const int64_t steps = nst * nch;
+  uint4 ph[2][P], pl[2][P];
   bf16x8 sah[2][2], sal[2][2];  // query operands in flight (RES == 0)
-  // positions (key tile kt, chunk c) and ring slots are passed in: no divisions by the runtime
+  // positions (stage st, chunk c) and ring slots are passed in: no divisions by the runtime
   // chunk count in the loop
-  auto fetch = [&](auto slot_c, int64_t kt, int c) __attribute__((always_inline)) {
+  auto fetch = [&](auto slot_c, int64_t st, int c) __attribute__((always_inline)) {
     constexpr int SL = decltype(slot_c)::value;
-    const int64_t kr = kt * kKT + skey;
-    ph[SL] = make_uint4(0, 0, 0, 0);
-    pl[SL] = ph[SL];
-    if (kr < n) {
-      ph[SL] = *reinterpret_cast<const uint4*>(xh + kr * dp + kDK * c + spiece);
-      if (SPLIT) pl[SL] = *reinterpret_cast<const uint4*>(xl + kr * dp + kDK * c + spiece);
+#pragma unroll
+    for (int t = 0; t < P; ++t) {
+      const int64_t kr = st * (P * kKT) + kKT * t + skey;
+      ph[SL][t] = make_uint4(0, 0, 0, 0);
+      pl[SL][t] = ph[SL][t];
+      if (kr < n) {
+        ph[SL][t] = *reinterpret_cast<const uint4*>(xh + kr * dp + kDK * c + spiece);
+        if (SPLIT) pl[SL][t] = *reinterpret_cast<const uint4*>(xl + kr * dp + kDK * c + spiece);
+      }
     }
     if constexpr (RES == 0) {
 #pragma unroll
@@ -304,8 +318,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   auto stash = [&](auto slot_c, int ring) __attribute__((always_inline)) {
     constexpr int SL = decltype(slot_c)::value;
     uint16_t* b = kst + ring * 2 * kStage;
-    *reinterpret_cast<uint4*>(b + skey * kRow + spiece) = ph[SL];
-    if (SPLIT) *reinterpret_cast<uint4*>(b + kStage + skey * kRow + spiece) = pl[SL];
+#pragma unroll
+    for (int t = 0; t < P; ++t) {
+      *reinterpret_cast<uint4*>(b + (kKT * t + skey) * kRow + spiece) = ph[SL][t];
+      if (SPLIT) *reinterpret_cast<uint4*>(b + kStage + (kKT * t + skey) * kRow + spiece) = pl[SL][t];
+    }
     if constexpr (RES == 0) {
       ah[0][0] = sah[SL][0];
       ah[0][1] = sah[SL][1];
@@ -313,10 +330,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
       al[0][1] = sal[SL][1];
     }
   };
-  f32x16 tot[2], part[2];
-  float nk[2] = {0.f, 0.f};
-  // lower bounds of tile kt; rows with a bound below their C-th bound merge (wave-local)
-  auto epilogue = [&](int64_t kt) __attribute__((always_inline)) {
+  f32x16 tot[NJ], part[NJ];
+  float nk[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) nk[j] = 0.f;
+  // lower bounds of tile kt (column tiles j0, j0 + 1 of the stage); rows with a bound below their
+  // C-th bound merge (wave-local)
+  auto epilogue = [&](int64_t kt, auto j0_c) __attribute__((always_inline)) {
+    constexpr int j0 = decltype(j0_c)::value;
     const int64_t k0 = kt * kKT;
     // only the last tile has keys past n, only the tiles holding this wave's rows hold a self
     // pair, only the last work-group has rows past n: other tiles need no masking
@@ -327,7 +348,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
       float lb[2];
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        lb[j] = qv[r] + nk[j] - 2.0f * tot[j][r];
+        lb[j] = qv[r] + nk[j0 + j] - 2.0f * tot[j0 + j][r];
         if (!clean) {
           const int64_t key = k0 + 32 * j + col;
           if (key >= n || (self && key == q) || q >= nq) lb[j] = INFINITY;
@@ -380,30 +401,30 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   };
   // step i: loads for step i + 2 go out, chunk i is multiplied from the ring, step i + 1's
   // registers land in the ring, one barrier
-  auto step = [&](auto slot_c, int64_t i, int64_t kt, int c, int ring, int64_t kt2, int c2, auto ai_c)
+  auto step = [&](auto slot_c, int64_t i, int64_t st, int c, int ring, int64_t st2, int c2, auto ai_c)
                   __attribute__((always_inline)) {
     constexpr int ai = decltype(ai_c)::value;
     constexpr int SL = decltype(slot_c)::value;
     if (c == 0) {
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int64_t key = kt * kKT + 32 * j + col;
+      for (int j = 0; j < NJ; ++j) {
+        const int64_t key = st * (P * kKT) + 32 * j + col;
         nk[j] = key < n ? c1 * nrm[key] : 0.f;
       }
     }
-    if (i + 2 < steps) fetch(slot_c, kt2, c2);
+    if (i + 2 < steps) fetch(slot_c, st2, c2);
     const uint16_t* b = kst + ring * 2 * kStage;
     // d <= 128 (RES > 0): one accumulator over all coordinates; else a fresh one per chunk,
     // added to the total (the error constant of the bound follows the same structure)
     f32x16* acc = RES > 0 ? tot : part;
     if (RES == 0 || c == 0) {
 #pragma unroll
-      for (int j = 0; j < 2; ++j) acc[j] = f32x16{};
+      for (int j = 0; j < NJ; ++j) acc[j] = f32x16{};
     }
 #pragma unroll
     for (int s2 = 0; s2 < 2; ++s2) {
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
+      for (int j = 0; j < NJ; ++j) {
         const int o = (32 * j + col) * kRow + 16 * s2 + 8 * half;
         const bf16x8 bh = load8(b + o);
         acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[ai][s2], bh, acc[j], 0, 0, 0);
@@ -416,12 +437,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     }
     if constexpr (RES == 0) {
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < NJ; ++j)
 #pragma unroll
         for (int r = 0; r < 16; ++r) tot[j][r] = c == 0 ? part[j][r] : tot[j][r] + part[j][r];
     }
-    if (c == nch - 1) epilogue(kt);
-    if (i + 1 < steps) stash(std::integral_constant<int, 1 - SL>{}, ring == 2 ? 0 : ring + 1);
+    if (c == nch - 1) {
+      epilogue(st * P, std::integral_constant<int, 0>{});
+      if constexpr (P == 2) {
+        if (st * P + 1 < nkt) epilogue(st * P + 1, std::integral_constant<int, 2>{});
+      }
+    }
+    if (i + 1 < steps) stash(std::integral_constant<int, 1 - SL>{}, ring + 1 == RING ? 0 : ring + 1);
     __syncthreads();
   };
   using S0 = std::integral_constant<int, 0>;
@@ -431,21 +457,21 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   if (steps > 1) fetch(S1{}, nch > 1 ? 0 : 1, nch > 1 ? 1 : 0);
   __syncthreads();
   if constexpr (RES > 0) {
-    // two tiles per iteration, so every step's register slot, query chunk and the chunk two
+    // two stages per iteration, so every step's register slot, query chunk and the chunk two
     // steps ahead are static
-    for (int64_t kt = 0; kt < nkt; kt += 2) {
+    for (int64_t s0 = 0; s0 < nst; s0 += 2) {
       static_for<0, 2 * RES>([&](auto tc) __attribute__((always_inline)) {
-        constexpr int u = decltype(tc)::value;   // step within the pair of tiles
+        constexpr int u = decltype(tc)::value;   // step within the pair of stages
         constexpr int t = u / RES, c = u % RES;
         constexpr int t2 = (u + 2) / RES, c2 = (u + 2) % RES;
-        const int64_t i = (kt + t) * RES + c;
-        if (kt + t < nkt)
-          step(std::integral_constant<int, u & 1>{}, i, kt + t, c, (int)(i % 3), kt + t2, c2,
+        const int64_t i = (s0 + t) * RES + c;
+        if (s0 + t < nst)
+          step(std::integral_constant<int, u & 1>{}, i, s0 + t, c, (int)(i % RING), s0 + t2, c2,
                std::integral_constant<int, c>{});
       });
     }
   } else {
-    int64_t kt = 0, kt2 = 0;
+    int64_t st = 0, st2 = 0;
     int c = 0, c2 = 0, ring = 0;
     auto advance = [&](int64_t& tt, int& cc) __attribute__((always_inline)) {
       if (++cc == nch) {
@@ -453,18 +479,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
         ++tt;
       }
     };
-    advance(kt2, c2);
-    advance(kt2, c2);   // two steps ahead
+    advance(st2, c2);
+    advance(st2, c2);   // two steps ahead
     for (int64_t i = 0; i < steps; i += 2) {
-      step(S0{}, i, kt, c, ring, kt2, c2, S0{});
-      advance(kt, c);
-      advance(kt2, c2);
-      ring = ring == 2 ? 0 : ring + 1;
+      step(S0{}, i, st, c, ring, st2, c2, S0{});
+      advance(st, c);
+      advance(st2, c2);
+      ring = ring + 1 == RING ? 0 : ring + 1;
       if (i + 1 < steps) {
-        step(S1{}, i + 1, kt, c, ring, kt2, c2, S0{});
-        advance(kt, c);
-        advance(kt2, c2);
-        ring = ring == 2 ? 0 : ring + 1;
+        step(S1{}, i + 1, st, c, ring, st2, c2, S0{});
+        advance(st, c);
+        advance(st2, c2);
+        ring = ring + 1 == RING ? 0 : ring + 1;
       }
     }
   }
@@ -638,8 +664,10 @@ slk_status knn_mfma(const float* x, int64_t n, int32_t d, int32_t k, int32_t can
   const double c = 2.0 * (cG + 8 * u);
   const float c1 = (float)(1.0 - c);
   const unsigned grid = (unsigned)((nq + kQT - 1) / kQT);
-  const size_t lds = sizeof(uint16_t) * 6 * kKT * kRow + (sizeof(float) + sizeof(int)) * (size_t)kQT * C;
   const int res = dp <= 4 * kDK ? dp / kDK : 0;
+  // the ring of key stages (hi and lo), then the candidate lists
+  const int tiles = res > 0 ? cand_tiles<1>() : cand_tiles<0>(), ring = res > 0 ? cand_ring<1>() : cand_ring<0>();
+  const size_t lds = sizeof(uint16_t) * 2 * ring * tiles * kKT * kRow + (sizeof(float) + sizeof(int)) * (size_t)kQT * C;
   const int selfi = self ? 1 : 0;
   {
     KernelTimer kt("cand_kernel", s);
