@@ -335,24 +335,33 @@ def serving_sweep(slk, torch, n_jobs, rates, max_jobs, passes):
                     "label_agreement_median": float(np.median(agree)), "label_agreement_min": float(agree.min())}
     # Precision alone: one outer iteration of each job from the FP32 fit's final modes, FP32 and
     # BF16-X on the same graph (same modes, each to its own convergence), for every job whose
-    # free-running fits differ by more than 1e-4 and for the first 200 jobs.
+    # free-running fits differ by more than 1e-4 and for the first 200 jobs.  Beside it, FP32
+    # against FP32 with the rows in the locality order (the same sums in another order): how far
+    # rounding alone moves the same jobs.
     pick = sorted(set(np.nonzero(gaps > 1e-4)[0].tolist()) | set(range(min(200, n_jobs))))
-    lgaps = {}
+    lgaps, ogaps = {}, {}
     for j in pick:
         inst, x = insts[j], xs[j]
         g = slk.Graph.build_knn(x, k=10)
+        go = slk.Graph.build_knn(x, k=10, reorder=True)
         m = keep["fp32"][j]["modes"]
         e = [slk.assign(x, g, m, lam=inst.lam, prec=pr, trace=False)["result"]["energy_fp64"] for pr in ("fp32", "bf16x")]
+        eo = slk.assign(x, go, m, lam=inst.lam, trace=False)["result"]["energy_fp64"]
         lgaps[j] = abs(e[1] - e[0]) / abs(e[0])
-        del g
+        ogaps[j] = abs(eo - e[0]) / abs(e[0])
+        del g, go
     lg = np.array([lgaps[j] for j in pick])
+    og = np.array([ogaps[j] for j in pick])
     div = [j for j in pick if gaps[j] > 1e-4]
     bf16_vs_fp32["lockstep"] = {
         "what": "one outer iteration from the FP32 fit's final modes, FP32 and BF16-X, FP64 energy rechecks",
         "jobs": len(pick), "within_1e-4": int((lg <= 1e-4).sum()), "within_1e-6": int((lg <= 1e-6).sum()),
         "rel_gap_max": float(lg.max()),
         "jobs_diverging_free": len(div),
-        "of_those_within_1e-4_lockstep": int(sum(lgaps[j] <= 1e-4 for j in div))}
+        "of_those_within_1e-4_lockstep": int(sum(lgaps[j] <= 1e-4 for j in div)),
+        "fp32_reordered_within_1e-4": int((og <= 1e-4).sum()),
+        "fp32_reordered_within_1e-4_of_the_diverging": int(sum(ogaps[j] <= 1e-4 for j in div)),
+        "both_beyond_1e-4": int(sum(lgaps[j] > 1e-4 and ogaps[j] > 1e-4 for j in pick))}
     log(f"[serve] bf16x vs fp32: {bf16_vs_fp32}")
     return {"jobs": n_jobs, "max_jobs": max_jobs, "passes_per_step": passes, "workload": SERVE_WORKLOAD,
             "runs": runs, "bf16x_vs_fp32": bf16_vs_fp32}
