@@ -142,3 +142,15 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr and r.stdout == ""
+
+
+@pytest.mark.parametrize("n,d,width", [(12289, 20, 4), (9001, 128, 8), (16411, 72, 8), (4095, 2000, 4),
+                                       (4096, 2000, 8), (262144, 4, 4), (262145, 4, 8)])
+def test_exact_knn_width_rule(n, d, width):
+    """The exact kNN's queries per work-group as the library reports them (host lookup, no GPU):
+    4 while the points take at most 4 MiB (n d 4 bytes) or there are fewer than 4,096 query rows,
+    else 8 - the rule the GPU tests exercise on both sides of each clause."""
+    import paper_1810_13044_amd as slk
+    t = slk.tune_lookup(n, d, 10)
+    assert t["knn_exact_width"] == width
+    assert t["wave_steps"] in (1, 2, 4, 8)

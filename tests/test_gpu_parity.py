@@ -81,12 +81,13 @@ def test_knn_exact_bit_identical(case, slk, torch):
     assert info["max_degree"] == int(np.max(np.diff(case["rp"])))
 
 
-@pytest.mark.parametrize("n,d", [(12289, 20), (9001, 128), (16411, 72)])
-def test_knn_exact_block_widths(n, d, slk, torch):
+@pytest.mark.parametrize("n,d,width", [(12289, 20, 4), (9001, 128, 8), (16411, 72, 8)])
+def test_knn_exact_block_widths(n, d, width, slk, torch):
     """The exact search runs 4 queries per work-group while the points take at most 4 MiB
-    (12289 x 20) and 8 above (9001 x 128, 16411 x 72); both widths, with a ragged last
-    work-group, give the oracle's lists bit for bit, checked on sampled rows: the first and
-    last 40, and 200 drawn at random."""
+    (12289 x 20) and 8 above (9001 x 128, 16411 x 72), as the library reports for the problem;
+    both widths, with a ragged last work-group, give the oracle's lists bit for bit, checked on
+    sampled rows: the first and last 40, and 200 drawn at random."""
+    assert slk.tune_lookup(n, d, 5)["knn_exact_width"] == width
     inst = gen.gaussian_mixture(n=n, d=d, L=5, K=9, seed=n % 97)
     g = slk.Graph.build_knn(to_dev(torch, inst.X, torch.float32), k=inst.K, method="exact")
     ex = g.export()
