@@ -35,6 +35,11 @@ BF16_PEAK_TFLOPS = 2500.0      # MI355X dense bf16 MFMA
 METRIC = "SLK-iteration GB/s (% HBM peak) at N=1M; batched solves/s + p99 latency"
 
 
+def host_threads():
+    """Worker threads for host-side work: the host's logical CPUs, at most 16 (a GPU machine's share)."""
+    return min(16, os.cpu_count() or 1)
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -154,7 +159,7 @@ def cpu_other(slk, torch, X, K, knn_s, n_rows=1024):
     the whole oracle pipeline at the 2,000-point mixture (kNN, CSR, sigma^2 and the fit)."""
     import gen
     from oracle import slk as orc
-    threads = os.cpu_count() or 1
+    threads = host_threads()
     N = X.shape[0]
     rows = np.random.default_rng(11).choice(N, n_rows, replace=False)
     t0 = time.perf_counter()
@@ -207,7 +212,7 @@ def _materialise_jobs(torch, n_jobs):
     from concurrent.futures import ThreadPoolExecutor
     specs = gen.job_stream(n_jobs=n_jobs, rate=1.0, seed=5)
     t0 = time.perf_counter()
-    with ThreadPoolExecutor(os.cpu_count() or 1) as ex:
+    with ThreadPoolExecutor(host_threads()) as ex:
         insts = list(ex.map(lambda sp: gen.materialise(sp, K=10), specs))
     xs = [torch.from_numpy(i.X).to("cuda") for i in insts]
     torch.cuda.synchronize()

@@ -502,6 +502,229 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   if (lane < 32 && q0 + lane < nq) tau_out[q0 + lane] = lvw[lane * C + C - 1];
 }
 
+// Candidate search for small query sets (d <= 128), where cand_kernel's grid of one work-group
+// per 128 queries would leave most CUs idle: a work-group owns 64 query rows and streams the same
+// two-tile stages, but every row's keys are split between two waves - waves 0 and 1 take rows
+// 0-31 and 32-63 against the first tile of each stage, waves 2 and 3 the same rows against the
+// second - so the grid has twice the work-groups.  Each wave keeps its own C best bounds per row;
+// the two waves of a row prune with the smaller of their two C-th bounds (shared through LDS: a
+// bound above either list's C-th cannot be among the union's C best, and a stale value is only
+// larger) and merge their lists at the end.  The candidate lists and bounds are those of
+// cand_kernel.
+constexpr int kQS = 64;   // query rows per work-group of the split search
+constexpr int64_t kSplitBelow = 256;   // split while cand_kernel would have fewer work-groups (one per CU)
+
+template <bool SPLIT, int RES>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void cand_split_kernel(
+    const uint16_t* __restrict__ xh, const uint16_t* __restrict__ xl, const float* __restrict__ nrm, int64_t n, int dp,
+    int C, float c1, int32_t* __restrict__ cand, float* __restrict__ tau_out, const uint16_t* __restrict__ qh,
+    const uint16_t* __restrict__ ql, const float* __restrict__ qn, int64_t nq, int self) {
+  static_assert(RES > 0, "the split search keeps the query operands in registers (d <= 128)");
+  constexpr int P = 2;                      // tiles per stage, one per key half
+  constexpr int RING = 2;
+  extern __shared__ unsigned char smraw[];
+  uint16_t* kst = reinterpret_cast<uint16_t*>(smraw);
+  constexpr int kStage = P * kKT * kRow;  // bf16 per array
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int half = lane >> 5, col = lane & 31;
+  const int rh = wave & 1, kh = wave >> 1;   // row half of the work-group, key half of the stage
+  float* lvw = reinterpret_cast<float*>(smraw + sizeof(uint16_t) * 2 * RING * kStage) + wave * 32 * C;
+  int* liw = reinterpret_cast<int*>(smraw + sizeof(uint16_t) * 2 * RING * kStage + sizeof(float) * 4 * 32 * C) +
+             wave * 32 * C;
+  __shared__ float tshare[2][kQS];   // [key half][row]: that wave's C-th bound of the row
+  const int64_t q0 = (int64_t)blockIdx.x * kQS + 32 * rh;
+  constexpr int nch = RES;
+  for (int e = lane; e < 32 * C; e += 64) {
+    lvw[e] = INFINITY;
+    liw[e] = INT32_MAX;
+  }
+  if (lane < 32) tshare[kh][32 * rh + lane] = INFINITY;
+  float qv[16], tau[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int64_t q = q0 + 8 * (r >> 2) + 4 * half + (r & 3);
+    qv[r] = q < nq ? c1 * qn[q] : 0.f;
+    tau[r] = INFINITY;
+  }
+  const int64_t arow = min<int64_t>(q0 + col, nq - 1);
+  const uint16_t* aph = qh + arow * dp + 8 * half;
+  const uint16_t* apl = ql + arow * dp + 8 * half;
+  bf16x8 ah[RES][2], al[RES][2];
+#pragma unroll
+  for (int c = 0; c < RES; ++c)
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2) {
+      ah[c][s2] = gload8(aph + kDK * c + 16 * s2);
+      al[c][s2] = SPLIT ? gload8(apl + kDK * c + 16 * s2) : ah[c][s2];
+    }
+  const int skey = tid >> 2, spiece = (tid & 3) * 8;
+  const int64_t nkt = (n + kKT - 1) / kKT;
+  const int64_t nst = (nkt + P - 1) / P;
+  const int64_t steps = nst * nch;
+  uint4 ph[2][P], pl[2][P];
+  auto fetch = [&](auto slot_c, int64_t st, int c) __attribute__((always_inline)) {
+    constexpr int SL = decltype(slot_c)::value;
+#pragma unroll
+    for (int t = 0; t < P; ++t) {
+      const int64_t kr = st * (P * kKT) + kKT * t + skey;
+      ph[SL][t] = make_uint4(0, 0, 0, 0);
+      pl[SL][t] = ph[SL][t];
+      if (kr < n) {
+        ph[SL][t] = *reinterpret_cast<const uint4*>(xh + kr * dp + kDK * c + spiece);
+        if (SPLIT) pl[SL][t] = *reinterpret_cast<const uint4*>(xl + kr * dp + kDK * c + spiece);
+      }
+    }
+  };
+  auto stash = [&](auto slot_c, int ring) __attribute__((always_inline)) {
+    constexpr int SL = decltype(slot_c)::value;
+    uint16_t* b = kst + ring * 2 * kStage;
+#pragma unroll
+    for (int t = 0; t < P; ++t) {
+      *reinterpret_cast<uint4*>(b + (kKT * t + skey) * kRow + spiece) = ph[SL][t];
+      if (SPLIT) *reinterpret_cast<uint4*>(b + kStage + (kKT * t + skey) * kRow + spiece) = pl[SL][t];
+    }
+  };
+  f32x16 tot[2];
+  float nk[2] = {0.f, 0.f};
+  // lower bounds of tile kt against this wave's rows; a row merges where a bound is below the
+  // smaller of its two waves' C-th bounds
+  auto epilogue = [&](int64_t kt) __attribute__((always_inline)) {
+    const int64_t k0 = kt * kKT;
+    const bool clean = k0 + kKT <= n && (!self || k0 >= q0 + 32 || k0 + kKT <= q0) && q0 + 32 <= nq;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int rrow = 8 * (r >> 2) + 4 * half + (r & 3);
+      const int64_t q = q0 + rrow;
+      const float thr = fminf(tau[r], tshare[1 - kh][32 * rh + rrow]);
+      float lb[2];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        lb[j] = qv[r] + nk[j] - 2.0f * tot[j][r];
+        if (!clean) {
+          const int64_t key = k0 + 32 * j + col;
+          if (key >= n || (self && key == q) || q >= nq) lb[j] = INFINITY;
+        }
+      }
+      const uint64_t m0 = __ballot(lb[0] < thr), m1 = __ballot(lb[1] < thr);
+      if ((m0 | m1) == 0ull) continue;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const uint32_t b0 = (uint32_t)(m0 >> (32 * h)), b1 = (uint32_t)(m1 >> (32 * h));
+        const int cnt = __popc(b0) + __popc(b1);
+        if (cnt == 0) continue;
+        const int rho = 8 * (r >> 2) + 4 * h + (r & 3);
+        float* lv = lvw + rho * C;
+        int* li = liw + rho * C;
+        float nt;
+        if (cnt <= kBulk) {
+          nt = INFINITY;
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            uint32_t bb = j == 0 ? b0 : b1;
+            while (bb) {
+              const int bit = __builtin_ctz(bb);
+              bb &= bb - 1;
+              const float v =
+                  __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, lb[j]), 32 * h + bit));
+              nt = list_insert(lv, li, C, v, (int)(k0 + 32 * j + bit));
+            }
+          }
+        } else {
+          const int src = 32 * h + col;
+          const float v0 = __shfl(lb[0], src), v1 = __shfl(lb[1], src);
+          float vv[2];
+          int ii[2];
+          vv[0] = lane < C ? lv[lane] : INFINITY;
+          ii[0] = lane < C ? li[lane] : INT32_MAX;
+          vv[1] = half == 0 ? v0 : v1;
+          ii[1] = vv[1] == INFINITY ? INT32_MAX : (int)(k0 + lane);
+          wave_sort128(vv, ii);
+          if (lane < C) {
+            lv[lane] = vv[0];
+            li[lane] = ii[0];
+          }
+          nt = __shfl(vv[0], C - 1);
+        }
+        if (half == h) tau[r] = nt;
+        if (lane == 0) tshare[kh][32 * rh + rho] = nt;
+      }
+    }
+  };
+  auto step = [&](auto slot_c, int64_t i, int64_t st, int c, int ring, int64_t st2, int c2, auto ai_c)
+                  __attribute__((always_inline)) {
+    constexpr int ai = decltype(ai_c)::value;
+    constexpr int SL = decltype(slot_c)::value;
+    if (c == 0) {
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int64_t key = st * (P * kKT) + kKT * kh + 32 * j + col;
+        nk[j] = key < n ? c1 * nrm[key] : 0.f;
+      }
+    }
+    if (i + 2 < steps) fetch(slot_c, st2, c2);
+    const uint16_t* b = kst + ring * 2 * kStage + kKT * kh * kRow;
+    if (c == 0) {
+#pragma unroll
+      for (int j = 0; j < 2; ++j) tot[j] = f32x16{};
+    }
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2) {
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int o = (32 * j + col) * kRow + 16 * s2 + 8 * half;
+        const bf16x8 bh = load8(b + o);
+        tot[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[ai][s2], bh, tot[j], 0, 0, 0);
+        if (SPLIT) {
+          const bf16x8 bl = load8(b + kStage + o);
+          tot[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[ai][s2], bl, tot[j], 0, 0, 0);
+          tot[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[ai][s2], bh, tot[j], 0, 0, 0);
+        }
+      }
+    }
+    if (c == nch - 1 && st * P + kh < nkt) epilogue(st * P + kh);
+    if (i + 1 < steps) stash(std::integral_constant<int, 1 - SL>{}, ring + 1 == RING ? 0 : ring + 1);
+    __syncthreads();
+  };
+  using S0 = std::integral_constant<int, 0>;
+  using S1 = std::integral_constant<int, 1>;
+  fetch(S0{}, 0, 0);
+  stash(S0{}, 0);
+  if (steps > 1) fetch(S1{}, nch > 1 ? 0 : 1, nch > 1 ? 1 : 0);
+  __syncthreads();
+  for (int64_t s0 = 0; s0 < nst; s0 += 2) {
+    static_for<0, 2 * RES>([&](auto tc) __attribute__((always_inline)) {
+      constexpr int u = decltype(tc)::value;
+      constexpr int t = u / RES, c = u % RES;
+      constexpr int t2 = (u + 2) / RES, c2 = (u + 2) % RES;
+      const int64_t i = (s0 + t) * RES + c;
+      if (s0 + t < nst)
+        step(std::integral_constant<int, u & 1>{}, i, s0 + t, c, (int)(i % RING), s0 + t2, c2,
+             std::integral_constant<int, c>{});
+    });
+  }
+  // merge the two waves' lists of each row: waves 0 and 1 take rows 0-15 of their row half,
+  // waves 2 and 3 rows 16-31 (the last barrier of the scan made every list visible)
+  const int pw = (wave & 1);   // the row half's first wave; its partner is pw + 2
+  const float* lva = reinterpret_cast<const float*>(smraw + sizeof(uint16_t) * 2 * RING * kStage) + pw * 32 * C;
+  const float* lvb = lva + 2 * 32 * C;
+  const int* lia = reinterpret_cast<const int*>(smraw + sizeof(uint16_t) * 2 * RING * kStage +
+                                                sizeof(float) * 4 * 32 * C) + pw * 32 * C;
+  const int* lib = lia + 2 * 32 * C;
+  for (int rho = 16 * kh; rho < 16 * kh + 16; ++rho) {
+    const int64_t q = q0 + rho;
+    float vv[2];
+    int ii[2];
+    vv[0] = lane < C ? lva[rho * C + lane] : INFINITY;
+    ii[0] = lane < C ? lia[rho * C + lane] : INT32_MAX;
+    vv[1] = lane < C ? lvb[rho * C + lane] : INFINITY;
+    ii[1] = lane < C ? lib[rho * C + lane] : INT32_MAX;
+    wave_sort128(vv, ii);
+    if (q < nq && lane < C) cand[q * C + lane] = ii[0];
+    const float last = __shfl(vv[0], C - 1);
+    if (q < nq && lane == 0) tau_out[q] = last;
+  }
+}
+
 // ------------------------------------------------------------------------------------------
 // 3. exact FP64 re-rank of the candidates, certificate, fallback list
 // ------------------------------------------------------------------------------------------
@@ -663,7 +886,9 @@ slk_status knn_mfma(const float* x, int64_t n, int32_t d, int32_t k, int32_t can
   const double cG = (bf16 ? 0.0 : 3.05 * std::ldexp(1.0, -16)) + 1.01 * (terms + 2) * u;
   const double c = 2.0 * (cG + 8 * u);
   const float c1 = (float)(1.0 - c);
-  const unsigned grid = (unsigned)((nq + kQT - 1) / kQT);
+  // the split search when the plain one's grid would leave CUs idle (d <= 128 only)
+  const bool split_search = dp <= 4 * kDK && (nq + kQT - 1) / kQT < kSplitBelow;
+  const unsigned grid = (unsigned)(split_search ? (nq + kQS - 1) / kQS : (nq + kQT - 1) / kQT);
   const int res = dp <= 4 * kDK ? dp / kDK : 0;
   // the ring of key stages (hi and lo), then the candidate lists
   const int tiles = res > 0 ? cand_tiles<1>() : cand_tiles<0>(), ring = res > 0 ? cand_ring<1>() : cand_ring<0>();
@@ -672,8 +897,12 @@ slk_status knn_mfma(const float* x, int64_t n, int32_t d, int32_t k, int32_t can
   {
     KernelTimer kt("cand_kernel", s);
 #define SLK_CAND(SPL, R)                                                                                          \
-  hipLaunchKernelGGL((cand_kernel<SPL, R>), dim3(grid), dim3(kBlock), lds, s, xh, xl, nrm, n, dp, C, c1, cidx, tau, \
-                     qh, ql, qn, nq, selfi)
+  if (R > 0 && split_search)                                                                                    \
+    hipLaunchKernelGGL((cand_split_kernel<SPL, (R > 0 ? R : 1)>), dim3(grid), dim3(kBlock), lds, s, xh, xl, nrm, n, \
+                       dp, C, c1, cidx, tau, qh, ql, qn, nq, selfi);                                              \
+  else                                                                                                          \
+    hipLaunchKernelGGL((cand_kernel<SPL, R>), dim3(grid), dim3(kBlock), lds, s, xh, xl, nrm, n, dp, C, c1, cidx,   \
+                       tau, qh, ql, qn, nq, selfi)
 #define SLK_CAND_RES(SPL)                  \
     switch (res) {                         \
       case 1: SLK_CAND(SPL, 1); break;     \

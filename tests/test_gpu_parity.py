@@ -101,6 +101,28 @@ def test_knn_exact_block_widths(n, d, width, slk, torch):
     assert np.array_equal(d2[rows], od)
 
 
+@pytest.mark.parametrize("n,d", [(20011, 64), (31, 8), (32769, 32)])
+def test_knn_mfma_split_and_plain_search(n, d, slk, torch):
+    """The MFMA candidate search below 256 work-groups of 128 queries (20011 x 64, 31 x 8) splits
+    each row's keys between two waves that share their pruning bound and merge their lists; above
+    (32769 x 32) it does not.  Either way the certified lists equal the oracle's bit for bit on
+    sampled rows (the first and last 40, 200 at random), and the candidates certify every row."""
+    inst = gen.gaussian_mixture(n=n, d=d, L=5, K=10, seed=n % 89)
+    g = slk.Graph.build_knn(to_dev(torch, inst.X, torch.float32), k=inst.K, method="mfma")
+    info = g.info()
+    ex = g.export()
+    idx, d2 = ex["knn_idx"].cpu().numpy(), ex["knn_d2"].cpu().numpy()
+    g.close()
+    rng = np.random.default_rng(n)
+    rows = np.unique(np.concatenate([np.arange(min(40, n)), np.arange(max(0, n - 40), n),
+                                     rng.integers(0, n, 200)]))
+    _say(f"[mfma split] n={n} d={d}: certified={info['rows_certified']} fallback={info['rows_fallback']}")
+    oi, od = orc.knn(inst.X, inst.K, rows=rows, block=64)
+    assert np.array_equal(idx[rows], oi)
+    assert np.array_equal(d2[rows], od)
+    assert info["rows_fallback"] == 0
+
+
 def test_graph_from_knn_and_reorder(case, slk, torch):
     inst = case["inst"]
     for reorder in (False, True):
