@@ -1014,7 +1014,8 @@ slk_status slk_build_knn(const float* x, int64_t n, int32_t d, const slk_knn_opt
   } else {
     int cand = o.candidates > 0 ? o.candidates : std::max(2 * o.k, 32);
     cand = std::min(std::max(cand, o.k), 256);
-    SLK_TRY(knn_mfma(x, n, d, o.k, cand, bf16, g->knn_idx, g->knn_d2, &g->rows_certified, &g->rows_fallback, s));
+    SLK_TRY(knn_mfma(x, n, d, o.k, cand, bf16, g->knn_idx, g->knn_d2, &g->rows_certified, &g->rows_fallback, s,
+                     nullptr, 0, /*split_ok=*/!g->pooled));
   }
   SLK_TRY(finish_from_knn(g, o.reorder, s));
   *g_out = gg.release();

@@ -392,9 +392,12 @@ slk_status launch_labels_to_user(const int32_t* labels_int, const int32_t* perm,
 // excluded) or, if y is given, the n_rows rows of y (nothing excluded).
 slk_status knn_exact(const float* x, int64_t n, int32_t d, int32_t k, int32_t bf16, const int32_t* rows,
                      int64_t n_rows, int32_t* out_idx, double* out_d2, hipStream_t s, const float* y = nullptr);
+// With split_ok, small query sets (d <= 128) take the split candidate search, which lowers one
+// search's latency on an otherwise idle device; the served form's graph builders, whose searches
+// run beside other work, pass false (the split search's extra work-groups cost throughput there).
 slk_status knn_mfma(const float* x, int64_t n, int32_t d, int32_t k, int32_t cand, int32_t bf16,
                     int32_t* out_idx, double* out_d2, int64_t* n_certified, int64_t* n_fallback, hipStream_t s,
-                    const float* y = nullptr, int64_t m = 0);
+                    const float* y = nullptr, int64_t m = 0, bool split_ok = true);
 // Graph arrays.  A thread that enables the pooled mode (the served form's graph builders)
 // allocates them from the stream-ordered pool; such a graph is released with destroy_graph_on,
 // stream-ordered, without the device-wide synchronisation that freeing plain allocations implies.

@@ -825,7 +825,7 @@ slk_status split_points(const float* x, int64_t n, int32_t d, int32_t dp, int32_
 
 slk_status knn_mfma(const float* x, int64_t n, int32_t d, int32_t k, int32_t cand, int32_t bf16, int32_t* out_idx,
                     double* out_d2, int64_t* n_certified, int64_t* n_fallback, hipStream_t s, const float* y,
-                    int64_t m) {
+                    int64_t m, bool split_ok) {
   // queries: the points themselves (each excluded from its own list) or the m rows of y
   const bool self = y == nullptr;
   const float* qx = self ? x : y;
@@ -887,7 +887,7 @@ slk_status knn_mfma(const float* x, int64_t n, int32_t d, int32_t k, int32_t can
   const double c = 2.0 * (cG + 8 * u);
   const float c1 = (float)(1.0 - c);
   // the split search when the plain one's grid would leave CUs idle (d <= 128 only)
-  const bool split_search = dp <= 4 * kDK && (nq + kQT - 1) / kQT < kSplitBelow;
+  const bool split_search = split_ok && dp <= 4 * kDK && (nq + kQT - 1) / kQT < kSplitBelow;
   const unsigned grid = (unsigned)(split_search ? (nq + kQS - 1) / kQS : (nq + kQT - 1) / kQT);
   const int res = dp <= 4 * kDK ? dp / kDK : 0;
   // the ring of key stages (hi and lo), then the candidate lists
