@@ -446,7 +446,9 @@ typedef struct {
   int32_t graph_replay;     /* 1: a step's launch sequence is captured into a HIP graph the
                                second time its shape (kernels, grids, argument layout) occurs,
                                and replayed whenever that shape recurs; 0: plain launches.
-                               The same kernels run on the same arguments either way.          */
+                               The same kernels run on the same arguments either way.  Takes
+                               effect for a server created on a non-null stream (the null
+                               stream cannot be captured).                                     */
 } slk_server_opts;
 
 typedef struct slk_server slk_server;

@@ -160,10 +160,6 @@ struct slk_server {
   int building = 0;             // handed to the builder and not taken back yet
   bool stop = false;
   std::atomic<int64_t> grouped_builds{0};   // shared launches of the exact kNN search
-  // the step's stream: the caller's, or one of the server's own when the caller passed the null
-  // stream (which cannot be captured); the own stream waits for the null stream at every step
-  hipStream_t own = nullptr;
-  hipEvent_t caller_done = nullptr;
   // captured step shapes: signature -> executable graph; shapes seen once wait for a second time
   struct Captured {
     std::vector<int64_t> sig;
@@ -403,11 +399,6 @@ slk_status grow_tables(slk_server* sv, size_t need) {
 
 slk_status server_step(slk_server* sv) {
   hipStream_t s = sv->s;
-  if (sv->own) {
-    // order the step after the work queued on the null stream so far
-    SLK_HIP(hipEventRecord(sv->caller_done, nullptr));
-    SLK_HIP(hipStreamWaitEvent(s, sv->caller_done, 0));
-  }
   // ---- admission: a free slot and room in the budget send a queued job to the builder
   {
     std::lock_guard<std::mutex> lk(sv->mu);
@@ -686,7 +677,8 @@ slk_status server_step(slk_server* sv) {
   SLK_HIP(hipMemcpyAsync(D, H, t.off, hipMemcpyHostToDevice, s));
   ++sv->steps;
   bool ran = false;
-  if (sv->o.graph_replay) {
+  // the null stream cannot be captured: a server created on it launches every step directly
+  if (sv->o.graph_replay && s != nullptr) {
     ++sv->clock;
     for (auto& c : sv->graphs) {
       if (c.sig == sig) {
@@ -847,12 +839,6 @@ slk_status slk_server_create(const slk_server_opts* opts, void* stream, slk_serv
     slk_server_destroy(sv);
     return st;
   };
-  if (!sv->s) {
-    if (hipStreamCreateWithFlags(&sv->own, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&sv->caller_done, hipEventDisableTiming) != hipSuccess)
-      return bail(fail(SLK_ERR_DEVICE, "server stream"));
-    sv->s = sv->own;
-  }
   if (hipGetDevice(&sv->device) != hipSuccess) return bail(fail(SLK_ERR_DEVICE, "hipGetDevice"));
   size_t fr = 0, tot = 0;
   if (hipMemGetInfo(&fr, &tot) != hipSuccess) return bail(fail(SLK_ERR_DEVICE, "hipMemGetInfo"));
@@ -931,8 +917,6 @@ void slk_server_destroy(slk_server* sv) {
   for (Job* j : sv->queue) delete j;
   (void)hipStreamSynchronize(sv->s);
   drop_graphs(sv);
-  if (sv->own) (void)hipStreamDestroy(sv->own);
-  if (sv->caller_done) (void)hipEventDestroy(sv->caller_done);
   (void)hipFree(sv->slots_dev);
   (void)hipHostFree(sv->slots_host);
   (void)hipFree(sv->tab_dev);

@@ -148,20 +148,24 @@ def test_build_knn_batched_identical_to_single_builds(slk, torch):
 
 @pytest.mark.parametrize("replay", [True, False])
 def test_server_graph_replay_and_grouped_builds(slk, torch, replay):
-    """Twelve small jobs submitted together: their graphs are built in shared exact-search
-    launches, and with graph replay the steps whose launch sequence repeats run from captured HIP
-    graphs (replayed many times, with the server's own copies and synchronisations in between);
-    every result equals the job's solo fit either way."""
+    """Twelve small jobs submitted together on a server created on a (capturable) torch stream:
+    their graphs are built in shared exact-search launches, and with graph replay the steps whose
+    launch sequence repeats run from captured HIP graphs (replayed many times, with the server's
+    own copies and synchronisations in between); every result equals the job's solo fit either
+    way.  A server on the null stream launches directly (the null stream cannot be captured)."""
     insts = [gen.gaussian_mixture(n=1500, d=16, L=6, K=10, seed=60 + j) for j in range(12)]
     xs = [to_dev(torch, i.X, torch.float32) for i in insts]
     kw = dict(fixed_inner=24, max_outer=2)   # the jobs step in lock-step through 12 equal inner steps
-    sv = slk.Server(max_jobs=16, passes_per_step=2, builders=1, graph_replay=replay)
-    tickets = {sv.submit(x, i.init_modes, lam=i.lam, k=i.K, **kw): j for j, (x, i) in enumerate(zip(xs, insts))}
-    outs = {}
-    while len(outs) < len(insts):
-        outs.update(sv.step())
-    st = sv.stats()
-    sv.close()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(torch.cuda.Stream()):   # replay needs a stream that can be captured
+        sv = slk.Server(max_jobs=16, passes_per_step=2, builders=1, graph_replay=replay)
+        tickets = {sv.submit(x, i.init_modes, lam=i.lam, k=i.K, **kw): j for j, (x, i) in enumerate(zip(xs, insts))}
+        outs = {}
+        while len(outs) < len(insts):
+            outs.update(sv.step())
+        st = sv.stats()
+        sv.close()
+    torch.cuda.synchronize()
     assert st["grouped_builds"] >= 1, st
     if replay:
         assert st["graph_captures"] >= 1 and st["graph_launches"] >= st["graph_captures"] + 10, st
