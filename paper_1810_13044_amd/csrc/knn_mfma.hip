@@ -192,6 +192,36 @@ __device__ __forceinline__ bf16x8 gload8(const uint16_t* __restrict__ p) {
   return __builtin_bit_cast(bf16x8, u);
 }
 
+// Key rows reach the scan through buffer loads: a load at or past the end of the resource returns
+// zeros without a memory access, so the loads of a stage need no per-lane branch.  With no branch
+// the compiler can count the loads in flight and wait only for the oldest ones; a branch around a
+// load had made it drain every load (and so the two-stage prefetch) at each step.
+typedef unsigned int vu4 __attribute__((ext_vector_type(4)));
+
+// Resource over the first `rows` (clamped to [0, cap]) rows of `row_bytes` bytes at p.  Both are
+// the same in every lane; the first lane's values are taken so that the descriptor sits in scalar
+// registers (a descriptor the compiler cannot prove uniform is applied lane group by lane group in
+// a loop).  Plain comparisons: the min/max templates lower 64-bit integers through FP64.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_of(const void* p, int64_t rows, int cap, int row_bytes) {
+  const int r = rows <= 0 ? 0 : (rows >= cap ? cap : (int)rows);
+  const int nb = __builtin_amdgcn_readfirstlane(r * row_bytes);
+  const uint64_t a = (uint64_t)(uintptr_t)p;
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)a);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(a >> 32));
+  void* base = (void*)(uintptr_t)(((uint64_t)hi << 32) | lo);
+  return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, nb, 0x00020000);
+}
+
+// voff: the lane's byte offset; soff: a byte offset common to the wave (kept in a scalar register)
+__device__ __forceinline__ uint4 bload16(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  const vu4 v = __builtin_bit_cast(vu4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+
+__device__ __forceinline__ float bloadf(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
 // Candidate search.  A work-group owns kQT = 128 query rows, 32 per wave; keys stream past in
 // tiles of kKT = 64, one 32-coordinate chunk at a time through an LDS stage (one barrier per
 // chunk).  For d <= 128 a stage holds two tiles (128 keys) and a wave multiplies its 32 rows by
@@ -264,11 +294,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   }
   // this lane's rows (accumulator r): 8 (r / 4) + 4 half + r % 4; qv = c1 |y_q|^2, tau = C-th bound
   float qv[16], tau[16];
+  {
+    const __amdgpu_buffer_rsrc_t rq = rsrc_of(qn + q0, nq - q0, 32, 4);   // zero past the last query
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int64_t q = q0 + 8 * (r >> 2) + 4 * half + (r & 3);
-    qv[r] = q < nq ? c1 * qn[q] : 0.f;
-    tau[r] = INFINITY;
+    for (int r = 0; r < 16; ++r) {
+      qv[r] = __fmul_rn(c1, bloadf(rq, 4 * (4 * half), 4 * (8 * (r >> 2) + (r & 3))));
+      tau[r] = INFINITY;
+    }
   }
   // query operands: row q0 + col, coordinates 16 s + 8 half .. + 7 of each chunk
   const int64_t arow = min<int64_t>(q0 + col, nq - 1);
@@ -288,6 +320,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   // staging: thread tid moves keys tid / 4 + 64 t (t < P), 8 coordinates at (tid % 4) * 8, hi
   // and lo, through two register slots (loads in flight two chunks ahead) into the LDS ring
   const int skey = tid >> 2, spiece = (tid & 3) * 8;
+  const int svoff = 2 * (skey * dp + spiece);   // this thread's byte offset inside a key stage
   const int64_t nkt = (n + kKT - 1) / kKT;
   const int64_t nst = (nkt + P - 1) / P;   // stages of keys
   const int64_t steps = nst * nch;
@@ -297,15 +330,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   // chunk count in the loop
   auto fetch = [&](auto slot_c, int64_t st, int c) __attribute__((always_inline)) {
     constexpr int SL = decltype(slot_c)::value;
+    // the stage's key rows; past the last key (or past the last stage) the loads return zeros
+    const int64_t r0 = st * (P * kKT);
+    const __amdgpu_buffer_rsrc_t rh = rsrc_of(xh + r0 * dp, n - r0, P * kKT, 2 * dp);
+    const __amdgpu_buffer_rsrc_t rl = rsrc_of(xl + r0 * dp, n - r0, P * kKT, 2 * dp);
 #pragma unroll
     for (int t = 0; t < P; ++t) {
-      const int64_t kr = st * (P * kKT) + kKT * t + skey;
-      ph[SL][t] = make_uint4(0, 0, 0, 0);
-      pl[SL][t] = ph[SL][t];
-      if (kr < n) {
-        ph[SL][t] = *reinterpret_cast<const uint4*>(xh + kr * dp + kDK * c + spiece);
-        if (SPLIT) pl[SL][t] = *reinterpret_cast<const uint4*>(xl + kr * dp + kDK * c + spiece);
-      }
+      const int soff = __builtin_amdgcn_readfirstlane(2 * (kKT * t * dp + kDK * c));
+      ph[SL][t] = bload16(rh, svoff, soff);
+      pl[SL][t] = SPLIT ? bload16(rl, svoff, soff) : ph[SL][t];
     }
     if constexpr (RES == 0) {
 #pragma unroll
@@ -348,7 +381,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
       float lb[2];
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        lb[j] = qv[r] + nk[j0 + j] - 2.0f * tot[j0 + j][r];
+        lb[j] = qv[r] + __fmul_rn(c1, nk[j0 + j]) - 2.0f * tot[j0 + j][r];
         if (!clean) {
           const int64_t key = k0 + 32 * j + col;
           if (key >= n || (self && key == q) || q >= nq) lb[j] = INFINITY;
@@ -406,13 +439,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     constexpr int ai = decltype(ai_c)::value;
     constexpr int SL = decltype(slot_c)::value;
     if (c == 0) {
+      // the stage's key norms (zero past the last key); scaled by c1 where the bounds are formed
+      const int64_t r0 = st * (P * kKT);
+      const __amdgpu_buffer_rsrc_t rn = rsrc_of(nrm + r0, n - r0, P * kKT, 4);
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) {
-        const int64_t key = st * (P * kKT) + 32 * j + col;
-        nk[j] = key < n ? c1 * nrm[key] : 0.f;
-      }
+      for (int j = 0; j < NJ; ++j) nk[j] = bloadf(rn, 4 * col, 4 * 32 * j);
     }
-    if (i + 2 < steps) fetch(slot_c, st2, c2);
+    fetch(slot_c, st2, c2);
     const uint16_t* b = kst + ring * 2 * kStage;
     // d <= 128 (RES > 0): one accumulator over all coordinates; else a fresh one per chunk,
     // added to the total (the error constant of the bound follows the same structure)
@@ -447,28 +480,37 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
         if (st * P + 1 < nkt) epilogue(st * P + 1, std::integral_constant<int, 2>{});
       }
     }
-    if (i + 1 < steps) stash(std::integral_constant<int, 1 - SL>{}, ring + 1 == RING ? 0 : ring + 1);
+    // (past the last step this moves zeros into a ring slot nobody reads again)
+    stash(std::integral_constant<int, 1 - SL>{}, ring + 1 == RING ? 0 : ring + 1);
     __syncthreads();
   };
   using S0 = std::integral_constant<int, 0>;
   using S1 = std::integral_constant<int, 1>;
   fetch(S0{}, 0, 0);
   stash(S0{}, 0);
-  if (steps > 1) fetch(S1{}, nch > 1 ? 0 : 1, nch > 1 ? 1 : 0);
+  fetch(S1{}, nch > 1 ? 0 : 1, nch > 1 ? 1 : 0);
   __syncthreads();
   if constexpr (RES > 0) {
     // two stages per iteration, so every step's register slot, query chunk and the chunk two
-    // steps ahead are static
-    for (int64_t s0 = 0; s0 < nst; s0 += 2) {
-      static_for<0, 2 * RES>([&](auto tc) __attribute__((always_inline)) {
+    // steps ahead are static; an odd last stage leaves the loop between the two (no branch
+    // around a step, whose loads the compiler could then not count)
+    for (int64_t s0 = 0;; s0 += 2) {
+      static_for<0, RES>([&](auto tc) __attribute__((always_inline)) {
         constexpr int u = decltype(tc)::value;   // step within the pair of stages
-        constexpr int t = u / RES, c = u % RES;
-        constexpr int t2 = (u + 2) / RES, c2 = (u + 2) % RES;
-        const int64_t i = (s0 + t) * RES + c;
-        if (s0 + t < nst)
-          step(std::integral_constant<int, u & 1>{}, i, s0 + t, c, (int)(i % RING), s0 + t2, c2,
-               std::integral_constant<int, c>{});
+        constexpr int c = u, t2 = (u + 2) / RES, c2 = (u + 2) % RES;
+        const int64_t i = s0 * RES + c;
+        step(std::integral_constant<int, u & 1>{}, i, s0, c, (int)(i % RING), s0 + t2, c2,
+             std::integral_constant<int, c>{});
       });
+      if (s0 + 1 >= nst) break;
+      static_for<RES, 2 * RES>([&](auto tc) __attribute__((always_inline)) {
+        constexpr int u = decltype(tc)::value;
+        constexpr int c = u - RES, t2 = (u + 2) / RES, c2 = (u + 2) % RES;
+        const int64_t i = (s0 + 1) * RES + c;
+        step(std::integral_constant<int, u & 1>{}, i, s0 + 1, c, (int)(i % RING), s0 + t2, c2,
+             std::integral_constant<int, c>{});
+      });
+      if (s0 + 2 >= nst) break;
     }
   } else {
     int64_t st = 0, st2 = 0;
@@ -481,17 +523,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     };
     advance(st2, c2);
     advance(st2, c2);   // two steps ahead
-    for (int64_t i = 0; i < steps; i += 2) {
+    for (int64_t i = 0;; i += 2) {
       step(S0{}, i, st, c, ring, st2, c2, S0{});
       advance(st, c);
       advance(st2, c2);
       ring = ring + 1 == RING ? 0 : ring + 1;
-      if (i + 1 < steps) {
-        step(S1{}, i + 1, st, c, ring, st2, c2, S0{});
-        advance(st, c);
-        advance(st2, c2);
-        ring = ring + 1 == RING ? 0 : ring + 1;
-      }
+      if (i + 1 >= steps) break;
+      step(S1{}, i + 1, st, c, ring, st2, c2, S0{});
+      advance(st, c);
+      advance(st2, c2);
+      ring = ring + 1 == RING ? 0 : ring + 1;
+      if (i + 2 >= steps) break;
     }
   }
   for (int e = lane; e < 32 * C; e += 64) {
@@ -540,11 +582,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   }
   if (lane < 32) tshare[kh][32 * rh + lane] = INFINITY;
   float qv[16], tau[16];
+  {
+    const __amdgpu_buffer_rsrc_t rq = rsrc_of(qn + q0, nq - q0, 32, 4);   // zero past the last query
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int64_t q = q0 + 8 * (r >> 2) + 4 * half + (r & 3);
-    qv[r] = q < nq ? c1 * qn[q] : 0.f;
-    tau[r] = INFINITY;
+    for (int r = 0; r < 16; ++r) {
+      qv[r] = __fmul_rn(c1, bloadf(rq, 4 * (4 * half), 4 * (8 * (r >> 2) + (r & 3))));
+      tau[r] = INFINITY;
+    }
   }
   const int64_t arow = min<int64_t>(q0 + col, nq - 1);
   const uint16_t* aph = qh + arow * dp + 8 * half;
@@ -558,21 +602,21 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
       al[c][s2] = SPLIT ? gload8(apl + kDK * c + 16 * s2) : ah[c][s2];
     }
   const int skey = tid >> 2, spiece = (tid & 3) * 8;
+  const int svoff = 2 * (skey * dp + spiece);   // this thread's byte offset inside a key stage
   const int64_t nkt = (n + kKT - 1) / kKT;
   const int64_t nst = (nkt + P - 1) / P;
   const int64_t steps = nst * nch;
   uint4 ph[2][P], pl[2][P];
   auto fetch = [&](auto slot_c, int64_t st, int c) __attribute__((always_inline)) {
     constexpr int SL = decltype(slot_c)::value;
+    const int64_t r0 = st * (P * kKT);
+    const __amdgpu_buffer_rsrc_t rh = rsrc_of(xh + r0 * dp, n - r0, P * kKT, 2 * dp);
+    const __amdgpu_buffer_rsrc_t rl = rsrc_of(xl + r0 * dp, n - r0, P * kKT, 2 * dp);
 #pragma unroll
     for (int t = 0; t < P; ++t) {
-      const int64_t kr = st * (P * kKT) + kKT * t + skey;
-      ph[SL][t] = make_uint4(0, 0, 0, 0);
-      pl[SL][t] = ph[SL][t];
-      if (kr < n) {
-        ph[SL][t] = *reinterpret_cast<const uint4*>(xh + kr * dp + kDK * c + spiece);
-        if (SPLIT) pl[SL][t] = *reinterpret_cast<const uint4*>(xl + kr * dp + kDK * c + spiece);
-      }
+      const int soff = __builtin_amdgcn_readfirstlane(2 * (kKT * t * dp + kDK * c));
+      ph[SL][t] = bload16(rh, svoff, soff);
+      pl[SL][t] = SPLIT ? bload16(rl, svoff, soff) : ph[SL][t];
     }
   };
   auto stash = [&](auto slot_c, int ring) __attribute__((always_inline)) {
@@ -599,7 +643,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
       float lb[2];
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        lb[j] = qv[r] + nk[j] - 2.0f * tot[j][r];
+        lb[j] = qv[r] + __fmul_rn(c1, nk[j]) - 2.0f * tot[j][r];
         if (!clean) {
           const int64_t key = k0 + 32 * j + col;
           if (key >= n || (self && key == q) || q >= nq) lb[j] = INFINITY;
@@ -655,13 +699,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     constexpr int ai = decltype(ai_c)::value;
     constexpr int SL = decltype(slot_c)::value;
     if (c == 0) {
+      const int64_t r0 = st * (P * kKT);
+      const __amdgpu_buffer_rsrc_t rn = rsrc_of(nrm + r0, n - r0, P * kKT, 4);
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int64_t key = st * (P * kKT) + kKT * kh + 32 * j + col;
-        nk[j] = key < n ? c1 * nrm[key] : 0.f;
-      }
+      for (int j = 0; j < 2; ++j) nk[j] = bloadf(rn, 4 * col, __builtin_amdgcn_readfirstlane(4 * (kKT * kh + 32 * j)));
     }
-    if (i + 2 < steps) fetch(slot_c, st2, c2);
+    fetch(slot_c, st2, c2);
     const uint16_t* b = kst + ring * 2 * kStage + kKT * kh * kRow;
     if (c == 0) {
 #pragma unroll
@@ -682,25 +725,32 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
       }
     }
     if (c == nch - 1 && st * P + kh < nkt) epilogue(st * P + kh);
-    if (i + 1 < steps) stash(std::integral_constant<int, 1 - SL>{}, ring + 1 == RING ? 0 : ring + 1);
+    stash(std::integral_constant<int, 1 - SL>{}, ring + 1 == RING ? 0 : ring + 1);
     __syncthreads();
   };
   using S0 = std::integral_constant<int, 0>;
   using S1 = std::integral_constant<int, 1>;
   fetch(S0{}, 0, 0);
   stash(S0{}, 0);
-  if (steps > 1) fetch(S1{}, nch > 1 ? 0 : 1, nch > 1 ? 1 : 0);
+  fetch(S1{}, nch > 1 ? 0 : 1, nch > 1 ? 1 : 0);
   __syncthreads();
-  for (int64_t s0 = 0; s0 < nst; s0 += 2) {
-    static_for<0, 2 * RES>([&](auto tc) __attribute__((always_inline)) {
+  for (int64_t s0 = 0;; s0 += 2) {
+    static_for<0, RES>([&](auto tc) __attribute__((always_inline)) {
       constexpr int u = decltype(tc)::value;
-      constexpr int t = u / RES, c = u % RES;
-      constexpr int t2 = (u + 2) / RES, c2 = (u + 2) % RES;
-      const int64_t i = (s0 + t) * RES + c;
-      if (s0 + t < nst)
-        step(std::integral_constant<int, u & 1>{}, i, s0 + t, c, (int)(i % RING), s0 + t2, c2,
-             std::integral_constant<int, c>{});
+      constexpr int c = u, t2 = (u + 2) / RES, c2 = (u + 2) % RES;
+      const int64_t i = s0 * RES + c;
+      step(std::integral_constant<int, u & 1>{}, i, s0, c, (int)(i % RING), s0 + t2, c2,
+           std::integral_constant<int, c>{});
     });
+    if (s0 + 1 >= nst) break;
+    static_for<RES, 2 * RES>([&](auto tc) __attribute__((always_inline)) {
+      constexpr int u = decltype(tc)::value;
+      constexpr int c = u - RES, t2 = (u + 2) / RES, c2 = (u + 2) % RES;
+      const int64_t i = (s0 + 1) * RES + c;
+      step(std::integral_constant<int, u & 1>{}, i, s0 + 1, c, (int)(i % RING), s0 + t2, c2,
+           std::integral_constant<int, c>{});
+    });
+    if (s0 + 2 >= nst) break;
   }
   // merge the two waves' lists of each row: waves 0 and 1 take rows 0-15 of their row half,
   // waves 2 and 3 rows 16-31 (the last barrier of the scan made every list visible)
