@@ -269,7 +269,7 @@ constexpr int cand_tiles() { return RES > 0 ? 2 : 1; }   // 64-key tiles per LDS
 template <int RES>
 constexpr int cand_ring() { return RES > 0 ? 2 : 3; }    // LDS stages in the ring
 
-template <bool SPLIT, int RES>
+template <bool SPLIT, int RES, bool FAST>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void cand_kernel(
     const uint16_t* __restrict__ xh, const uint16_t* __restrict__ xl, const float* __restrict__ nrm, int64_t n, int dp,
     int C, float c1, int32_t* __restrict__ cand, float* __restrict__ tau_out, const uint16_t* __restrict__ qh,
@@ -369,66 +369,114 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   for (int j = 0; j < NJ; ++j) nk[j] = 0.f;
   // lower bounds of tile kt (column tiles j0, j0 + 1 of the stage); rows with a bound below their
   // C-th bound merge (wave-local)
+  // Merge of row r (accumulator entry r of this lane; one row per lane half) with the tile's
+  // bounds lb (keys k0 + 32 j + col): the candidates below the row's C-th bound tr enter its list;
+  // returns the row's new C-th bound (for this lane's half).
+  auto merge_row = [&](int r, int64_t k0, const float (&lb)[2], float tr) __attribute__((always_inline)) {
+    const uint64_t m0 = __ballot(lb[0] < tr), m1 = __ballot(lb[1] < tr);
+    if ((m0 | m1) == 0ull) return tr;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const uint32_t b0 = (uint32_t)(m0 >> (32 * h)), b1 = (uint32_t)(m1 >> (32 * h));
+      const int cnt = __popc(b0) + __popc(b1);
+      if (cnt == 0) continue;
+      const int rho = 8 * (r >> 2) + 4 * h + (r & 3);
+      float* lv = lvw + rho * C;
+      int* li = liw + rho * C;
+      float nt;
+      if (cnt <= kBulk) {
+        nt = INFINITY;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          uint32_t bb = j == 0 ? b0 : b1;
+          while (bb) {
+            const int bit = __builtin_ctz(bb);
+            bb &= bb - 1;
+            const float v =
+                __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, lb[j]), 32 * h + bit));
+            nt = list_insert(lv, li, C, v, (int)(k0 + 32 * j + bit));
+          }
+        }
+      } else {
+        // the row's 64 bounds of this tile: lanes 0-31 keys k0 .. k0+31, lanes 32-63 the rest
+        const int src = 32 * h + col;
+        const float v0 = __shfl(lb[0], src), v1 = __shfl(lb[1], src);
+        float vv[2];
+        int ii[2];
+        vv[0] = lane < C ? lv[lane] : INFINITY;
+        ii[0] = lane < C ? li[lane] : INT32_MAX;
+        vv[1] = half == 0 ? v0 : v1;
+        ii[1] = vv[1] == INFINITY ? INT32_MAX : (int)(k0 + lane);
+        wave_sort128(vv, ii);
+        if (lane < C) {
+          lv[lane] = vv[0];
+          li[lane] = ii[0];
+        }
+        nt = __shfl(vv[0], C - 1);
+      }
+      if (half == h) tr = nt;
+    }
+    return tr;
+  };
+  // lower bounds of tile kt (column tiles j0, j0 + 1 of the stage); rows with a bound below their
+  // C-th bound merge (wave-local)
   auto epilogue = [&](int64_t kt, auto j0_c) __attribute__((always_inline)) {
     constexpr int j0 = decltype(j0_c)::value;
     const int64_t k0 = kt * kKT;
     // only the last tile has keys past n, only the tiles holding this wave's rows hold a self
     // pair, only the last work-group has rows past n: other tiles need no masking
     const bool clean = k0 + kKT <= n && (!self || k0 >= q0 + 32 || k0 + kKT <= q0) && q0 + 32 <= nq;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
+    const float nkc[2] = {__fmul_rn(c1, nk[j0]), __fmul_rn(c1, nk[j0 + 1])};
+    auto bounds = [&](int r, float t0, float t1, float qr, float (&lb)[2]) __attribute__((always_inline)) {
       const int64_t q = q0 + 8 * (r >> 2) + 4 * half + (r & 3);
-      float lb[2];
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        lb[j] = qv[r] + __fmul_rn(c1, nk[j0 + j]) - 2.0f * tot[j0 + j][r];
+        lb[j] = __fmaf_rn(-2.0f, j == 0 ? t0 : t1, __fadd_rn(qr, nkc[j]));
         if (!clean) {
           const int64_t key = k0 + 32 * j + col;
           if (key >= n || (self && key == q) || q >= nq) lb[j] = INFINITY;
         }
       }
-      const uint64_t m0 = __ballot(lb[0] < tau[r]), m1 = __ballot(lb[1] < tau[r]);
-      if ((m0 | m1) == 0ull) continue;
+    };
+    if constexpr (FAST) {
+      // Long scans: rows (bit r) with a bound below their C-th bound in this tile first.  Late in
+      // a long scan most tiles improve no row, and this test is a few register operations per
+      // row; the merge then visits only the rows found, picking their values out of the register
+      // arrays by comparisons (static indices only, so the arrays stay in registers).
+      uint32_t rows = 0xffffu;
+      if (clean) {
+        rows = 0u;
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const uint32_t b0 = (uint32_t)(m0 >> (32 * h)), b1 = (uint32_t)(m1 >> (32 * h));
-        const int cnt = __popc(b0) + __popc(b1);
-        if (cnt == 0) continue;
-        const int rho = 8 * (r >> 2) + 4 * h + (r & 3);
-        float* lv = lvw + rho * C;
-        int* li = liw + rho * C;
-        float nt;
-        if (cnt <= kBulk) {
-          nt = INFINITY;
-#pragma unroll
-          for (int j = 0; j < 2; ++j) {
-            uint32_t bb = j == 0 ? b0 : b1;
-            while (bb) {
-              const int bit = __builtin_ctz(bb);
-              bb &= bb - 1;
-              const float v =
-                  __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, lb[j]), 32 * h + bit));
-              nt = list_insert(lv, li, C, v, (int)(k0 + 32 * j + bit));
-            }
-          }
-        } else {
-          // the row's 64 bounds of this tile: lanes 0-31 keys k0 .. k0+31, lanes 32-63 the rest
-          const int src = 32 * h + col;
-          const float v0 = __shfl(lb[0], src), v1 = __shfl(lb[1], src);
-          float vv[2];
-          int ii[2];
-          vv[0] = lane < C ? lv[lane] : INFINITY;
-          ii[0] = lane < C ? li[lane] : INT32_MAX;
-          vv[1] = half == 0 ? v0 : v1;
-          ii[1] = vv[1] == INFINITY ? INT32_MAX : (int)(k0 + lane);
-          wave_sort128(vv, ii);
-          if (lane < C) {
-            lv[lane] = vv[0];
-            li[lane] = ii[0];
-          }
-          nt = __shfl(vv[0], C - 1);
+        for (int r = 0; r < 16; ++r) {
+          const bool hit = __fmaf_rn(-2.0f, tot[j0][r], __fadd_rn(qv[r], nkc[0])) < tau[r] ||
+                           __fmaf_rn(-2.0f, tot[j0 + 1][r], __fadd_rn(qv[r], nkc[1])) < tau[r];
+          rows |= __ballot(hit) != 0ull ? (1u << r) : 0u;
         }
-        if (half == h) tau[r] = nt;
+      }
+      while (rows) {
+        const int r = __builtin_ctz(rows);
+        rows &= rows - 1;
+        float t0 = tot[j0][0], t1 = tot[j0 + 1][0], qr = qv[0], tr = tau[0];
+#pragma unroll
+        for (int u = 1; u < 16; ++u) {
+          t0 = r == u ? tot[j0][u] : t0;
+          t1 = r == u ? tot[j0 + 1][u] : t1;
+          qr = r == u ? qv[u] : qr;
+          tr = r == u ? tau[u] : tr;
+        }
+        float lb[2];
+        bounds(r, t0, t1, qr, lb);
+        tr = merge_row(r, k0, lb, tr);
+#pragma unroll
+        for (int u = 0; u < 16; ++u) tau[u] = r == u ? tr : tau[u];
+      }
+    } else {
+      // short scans, where most tiles improve some row: every row in turn
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        float lb[2];
+        bounds(r, tot[j0][r], tot[j0 + 1][r], qv[r], lb);
+        tau[r] = merge_row(r, k0, lb, tau[r]);
       }
     }
   };
@@ -555,6 +603,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
 // cand_kernel.
 constexpr int kQS = 64;   // query rows per work-group of the split search
 constexpr int64_t kSplitBelow = 256;   // split while cand_kernel would have fewer work-groups (one per CU)
+// Key counts from which the plain search tests all rows of a tile before merging (the FAST
+// epilogue of cand_kernel).  Measured against merging row by row: 1,000,000 keys (d = 128)
+// 900 -> 825 ms and 400,000 keys (d = 64) 139 -> 103 ms, but 300,000 keys (d = 128) 104 -> 114 ms
+// and 60,000 keys (d = 64) 6.1 -> 8.6 ms: in shorter scans most tiles still improve some row.
+constexpr int64_t kFastKeys = 1 << 19;
 
 template <bool SPLIT, int RES>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void cand_split_kernel(
@@ -950,8 +1003,11 @@ slk_status knn_mfma(const float* x, int64_t n, int32_t d, int32_t k, int32_t can
   if (R > 0 && split_search)                                                                                    \
     hipLaunchKernelGGL((cand_split_kernel<SPL, (R > 0 ? R : 1)>), dim3(grid), dim3(kBlock), lds, s, xh, xl, nrm, n, \
                        dp, C, c1, cidx, tau, qh, ql, qn, nq, selfi);                                              \
+  else if (n >= kFastKeys)                                                                                      \
+    hipLaunchKernelGGL((cand_kernel<SPL, R, true>), dim3(grid), dim3(kBlock), lds, s, xh, xl, nrm, n, dp, C, c1,   \
+                       cidx, tau, qh, ql, qn, nq, selfi);                                                       \
   else                                                                                                          \
-    hipLaunchKernelGGL((cand_kernel<SPL, R>), dim3(grid), dim3(kBlock), lds, s, xh, xl, nrm, n, dp, C, c1, cidx,   \
+    hipLaunchKernelGGL((cand_kernel<SPL, R, false>), dim3(grid), dim3(kBlock), lds, s, xh, xl, nrm, n, dp, C, c1, cidx,   \
                        tau, qh, ql, qn, nq, selfi)
 #define SLK_CAND_RES(SPL)                  \
     switch (res) {                         \
