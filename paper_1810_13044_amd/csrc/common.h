@@ -22,6 +22,39 @@ __host__ __device__ __forceinline__ float bf16_round(float v) {
   return r;
 }
 
+// Buffer loads for kernels that stream rows: a load at or past the end of the resource returns
+// zeros without a memory access, so loads near the end of an array need no per-lane branch (a
+// branch around a load makes the compiler wait for every load in flight where the paths join).
+typedef unsigned int slk_vu4 __attribute__((ext_vector_type(4)));
+
+// Resource over the first `rows` (clamped to [0, cap]) rows of `row_bytes` bytes at p.  Both are
+// the same in every lane; the first lane's values are taken so that the descriptor sits in scalar
+// registers (a descriptor the compiler cannot prove uniform is applied lane group by lane group in
+// a loop).  Plain comparisons: the min/max templates lower 64-bit integers through FP64.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_of(const void* p, int64_t rows, int cap, int row_bytes) {
+  const int r = rows <= 0 ? 0 : (rows >= cap ? cap : (int)rows);
+  const int nb = __builtin_amdgcn_readfirstlane(r * row_bytes);
+  const uint64_t a = (uint64_t)(uintptr_t)p;
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)a);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(a >> 32));
+  void* base = (void*)(uintptr_t)(((uint64_t)hi << 32) | lo);
+  return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, nb, 0x00020000);
+}
+
+// voff: the lane's byte offset; soff: a byte offset common to the wave (kept in a scalar register)
+__device__ __forceinline__ uint4 bload16(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  const slk_vu4 v = __builtin_bit_cast(slk_vu4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+
+__device__ __forceinline__ float bloadf(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
+__device__ __forceinline__ int bloadi(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+}
+
 // ------------------------------------------------------------------------------------
 // errors
 // ------------------------------------------------------------------------------------

@@ -102,16 +102,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
 
   // staging of the point chunks: thread tid moves point tid / 4, 8 coordinates at (tid % 4) * 8
   const int spt = tid >> 2, spiece = (tid & 3) * 8;
+  const int svoff = 2 * (spt * dp + spiece);   // this thread's byte offset inside a tile of points
   uint4 ph = make_uint4(0, 0, 0, 0), pl = ph;
-  // step positions (tile, chunk) and ring slots advance by counters: no divisions in the loop
+  // step positions (tile, chunk) and ring slots advance by counters: no divisions in the loop.
+  // Every global load of the loop is a buffer load with no branch around it (zeros past the last
+  // point), so the compiler waits only for the loads a step needs.
   auto fetch = [&](int64_t t, int c) __attribute__((always_inline)) {
-    const int64_t pr = t * kPT + spt;
-    ph = make_uint4(0, 0, 0, 0);
-    pl = ph;
-    if (pr < n) {
-      ph = *reinterpret_cast<const uint4*>(xh + pr * dp + kDK * c + spiece);
-      if (SPLIT) pl = *reinterpret_cast<const uint4*>(xl + pr * dp + kDK * c + spiece);
-    }
+    const int64_t p0 = t * kPT;
+    const __amdgpu_buffer_rsrc_t rh = rsrc_of(xh + p0 * dp, n - p0, kPT, 2 * dp);
+    const __amdgpu_buffer_rsrc_t rl = rsrc_of(xl + p0 * dp, n - p0, kPT, 2 * dp);
+    const int soff = __builtin_amdgcn_readfirstlane(2 * kDK * c);
+    ph = bload16(rh, svoff, soff);
+    pl = SPLIT ? bload16(rl, svoff, soff) : ph;
   };
   // RES == 0: the candidate operands of the next chunk are loaded one step ahead
   bf16x8 nbh[2], nbl[2];
@@ -135,13 +137,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   // stores it in `labs` at the tile's second chunk (after a barrier), and the slots read it from
   // there when the tile's Z is stashed (after the next barrier).
   constexpr int SPT = LB * 4 * 64 / kBlock;   // slots per thread
+  // the next tile's raw values (labels, Z, norms), turned into operands where they are stashed;
+  // every wave loads the tile's labels and norms (point tid % 64), wave 0 stashes them
   float zv[SPT][8];
-  int lreg = -1;
-  float nv = -INFINITY;
+  int lraw = 0;
+  float nraw = 0.f;
+  bool pok = false;   // point tid % 64 of the fetched tile exists
   auto zfetch = [&](int64_t t) __attribute__((always_inline)) {
+    const int64_t p0 = t * kPT;
     if constexpr (HARD) {
-      if (tid < kPT) lreg = t * kPT + tid < n ? lab[t * kPT + tid] : -1;
+      lraw = bloadi(rsrc_of(lab + p0, n - p0, kPT, 4), 4 * (tid & 63), 0);
     } else {
+      const __amdgpu_buffer_rsrc_t rz = rsrc_of(z + p0 * L, n - p0, kPT, 4 * L);
 #pragma unroll
       for (int i = 0; i < SPT; ++i) {
         const int sl = tid + kBlock * i;
@@ -149,15 +156,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
         const int l = 32 * lb2 + (sln & 31), gg = sln >> 5;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          const int64_t p = t * kPT + 16 * kc + 8 * (e >> 2) + 4 * gg + (e & 3);
-          zv[i][e] = (p < n && l < L) ? z[p * L + l] : 0.f;
+          const int pl = 16 * kc + 8 * (e >> 2) + 4 * gg + (e & 3);
+          // clusters past L read cluster L - 1 here and are zeroed where stashed
+          zv[i][e] = bloadf(rz, 4 * (pl * L + min(l, L - 1)), 0);
         }
       }
     }
-    if (tid < kPT) nv = t * kPT + tid < n ? kscale * nrm[t * kPT + tid] : -INFINITY;
+    nraw = bloadf(rsrc_of(nrm + p0, n - p0, kPT, 4), 4 * (tid & 63), 0);
+    pok = p0 + (tid & 63) < n;
   };
   auto lstash = [&]() __attribute__((always_inline)) {
-    if (HARD && tid < kPT) labs[tid] = lreg;
+    if (HARD && tid < kPT) labs[tid] = pok ? lraw : -1;
   };
   auto zstash = [&]() __attribute__((always_inline)) {
 #pragma unroll
@@ -178,14 +187,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
         if constexpr (HARD) {
           hi[e] = lv[e] == l ? (__bf16)1.0f : (__bf16)0.0f;
         } else {
-          hi[e] = (__bf16)zv[i][e];
-          lo[e] = (__bf16)(zv[i][e] - (float)hi[e]);
+          const float zz = l < L ? zv[i][e] : 0.f;
+          hi[e] = (__bf16)zz;
+          lo[e] = (__bf16)(zz - (float)hi[e]);
         }
       }
       *reinterpret_cast<bf16x8*>(zst + sl * 8) = hi;
       if constexpr (!HARD) *reinterpret_cast<bf16x8*>(zst + kZ + sl * 8) = lo;
     }
-    if (tid < kPT) nst[tid] = nv;
+    if (tid < kPT) nst[tid] = pok ? kscale * nraw : -INFINITY;
   };
 
   f32x16 acc[2];
@@ -266,7 +276,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   lstash();
   stash(0);
   advance(tf, cf);
-  if (steps > 1) fetch(tf, cf);
+  fetch(tf, cf);   // zeros past the last step
   int64_t t = 0;    // position of this step
   int c = 0;
   int slot = 0;     // ring slot of this step
@@ -274,22 +284,25 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     __syncthreads();
     if (c == 0) {
       zstash();
-      if (t + 1 < ntile) zfetch(t + 1);
     } else if (c == 1) {
       lstash();
     }
+    // (past the last step: zeros into a ring slot nobody reads again)
     const int nslot = slot == 2 ? 0 : slot + 1;
-    if (i + 1 < steps) stash(nslot);
+    stash(nslot);
     bf16x8 cbh[2], cbl[2];
     if constexpr (RES == 0) {
       cbh[0] = nbh[0];
       cbh[1] = nbh[1];
       cbl[0] = nbl[0];
       cbl[1] = nbl[1];
-      if (i + 1 < steps) yfetch(c + 1 == nch ? 0 : c + 1);
+      yfetch(c + 1 == nch ? 0 : c + 1);
     }
     advance(tf, cf);
-    if (i + 2 < steps) fetch(tf, cf);
+    fetch(tf, cf);
+    // the next tile's Z after this step's other loads, so that waiting for those (at the next
+    // stash) is not a wait for these as well (past the last tile: zeros, never stashed)
+    if (c == 0) zfetch(t + 1);
     if (c == 0) {
       acc[0] = f32x16{};
       acc[1] = f32x16{};
