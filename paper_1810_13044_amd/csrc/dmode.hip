@@ -101,7 +101,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   }
 
   // staging of the point chunks: thread tid moves point tid / 4, 8 coordinates at (tid % 4) * 8
-  const int spt = tid >> 2, spiece = (tid & 3) * 8;
+  // point rows of a wave's lanes: 4 (l / 4 % 4) + l / 16, so that the lanes an LDS write serves at
+  // once cover rows 4 apart, whose 80-byte rows fall on distinct banks (as in the kNN staging)
+  const int spt = 16 * (tid >> 6) + 4 * ((tid >> 2) & 3) + ((tid >> 4) & 3), spiece = (tid & 3) * 8;
   const int svoff = 2 * (spt * dp + spiece);   // this thread's byte offset inside a tile of points
   uint4 ph = make_uint4(0, 0, 0, 0), pl = ph;
   // step positions (tile, chunk) and ring slots advance by counters: no divisions in the loop.

@@ -294,7 +294,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   }
   // staging: thread tid moves keys tid / 4 + 64 t (t < P), 8 coordinates at (tid % 4) * 8, hi
   // and lo, through two register slots (loads in flight two chunks ahead) into the LDS ring
-  const int skey = tid >> 2, spiece = (tid & 3) * 8;
+  // key rows of a wave's lanes: 4 (l / 4 % 4) + l / 16 (the four pieces of a row in four adjacent
+  // lanes), so that the 8 (or 16) lanes an LDS write serves at once cover rows 4 (or 12) apart,
+  // whose 80-byte rows fall on distinct banks; rows in order had every write two-way conflicted
+  const int skey = 16 * (tid >> 6) + 4 * ((tid >> 2) & 3) + ((tid >> 4) & 3), spiece = (tid & 3) * 8;
   const int svoff = 2 * (skey * dp + spiece);   // this thread's byte offset inside a key stage
   const int64_t nkt = (n + kKT - 1) / kKT;
   const int64_t nst = (nkt + P - 1) / P;   // stages of keys
@@ -629,7 +632,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
       ah[c][s2] = gload8(aph + kDK * c + 16 * s2);
       al[c][s2] = SPLIT ? gload8(apl + kDK * c + 16 * s2) : ah[c][s2];
     }
-  const int skey = tid >> 2, spiece = (tid & 3) * 8;
+  // key rows of a wave's lanes: 4 (l / 4 % 4) + l / 16 (the four pieces of a row in four adjacent
+  // lanes), so that the 8 (or 16) lanes an LDS write serves at once cover rows 4 (or 12) apart,
+  // whose 80-byte rows fall on distinct banks; rows in order had every write two-way conflicted
+  const int skey = 16 * (tid >> 6) + 4 * ((tid >> 2) & 3) + ((tid >> 4) & 3), spiece = (tid & 3) * 8;
   const int svoff = 2 * (skey * dp + spiece);   // this thread's byte offset inside a key stage
   const int64_t nkt = (n + kKT - 1) / kKT;
   const int64_t nst = (nkt + P - 1) / P;
