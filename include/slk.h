@@ -519,13 +519,15 @@ slk_status slk_pool_trim(void);
  * They come from a table the project's autotuner (tune.py) measured on the GPU, keyed by the row
  * count and the lane-group class of L, and every call - single fits, assignments, the served form
  * - takes them from there, so a job's results are the same wherever it runs.  Tile shapes change
- * no result except the order of the relaxed bound's FP64 partial sums.
+ * no result except the order of the relaxed bound's FP64 partial sums.  knn_long_scan reports the
+ * form of the MFMA candidate search over n keys (the candidate lists are the same either way).
  */
 typedef struct {
   int32_t wave_steps;       /* row batches per wave in a z-update tile (L <= 64; 4 above)       */
   int32_t knn_exact_width;  /* queries per work-group of the exact kNN over n rows              */
   int32_t knn_exact;        /* 1 if the AUTO kNN method takes the exact search for (n, d)        */
-  int32_t reserved;
+  int32_t knn_long_scan;    /* 1 if the MFMA candidate search over n keys tests each key tile
+                               against all of a wave's rows before merging (n >= 2^19)            */
 } slk_tune_params;
 
 /* The tile shapes a problem of n points in d dimensions with L clusters gets (host output). */

@@ -282,7 +282,7 @@ def tune_lookup(n, d, L):
     """Tile shapes the library takes for a problem of n points, d dimensions and L clusters."""
     t = _lib.TuneParams()
     _lib.check(_lib.load().slk_tune_lookup(int(n), int(d), int(L), C.byref(t)))
-    return {f: getattr(t, f) for f, _ in t._fields_ if f != "reserved"}
+    return {f: getattr(t, f) for f, _ in t._fields_}
 
 
 def tune_override(wave_steps):

@@ -71,7 +71,7 @@ class ServerOpts(C.Structure):
 
 class TuneParams(C.Structure):
     _fields_ = [("wave_steps", C.c_int32), ("knn_exact_width", C.c_int32), ("knn_exact", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("knn_long_scan", C.c_int32)]
 
 
 class ServerStats(C.Structure):

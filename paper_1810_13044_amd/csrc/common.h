@@ -400,6 +400,8 @@ slk_status knn_exact_group(const KnnExactJob* jobs_host, int njobs, hipStream_t 
 
 // The kNN method AUTO resolves to: the exact search when n^2 d <= 4e9 (api.hip).
 bool knn_takes_exact(int64_t n, int32_t d, const slk_knn_opts& o);
+// 1 if the MFMA candidate search over n_keys keys tests whole key tiles before merging (long scans)
+bool knn_long_scan(int64_t n_keys);
 
 // argument checks and per-graph settings shared by the C ABI and the served form (api.hip)
 slk_status check_points(const float* x, int64_t n, int32_t d);

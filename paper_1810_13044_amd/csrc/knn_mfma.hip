@@ -888,6 +888,8 @@ __global__ __launch_bounds__(kBlock) void rerank_kernel(const float* __restrict_
 
 }  // namespace
 
+bool knn_long_scan(int64_t n_keys) { return n_keys >= kFastKeys; }
+
 slk_status split_points(const float* x, int64_t n, int32_t d, int32_t dp, int32_t bf16, double* mean, uint16_t* xh,
                         uint16_t* xl, float* nrm, hipStream_t s) {
   if (!bf16) {
@@ -984,7 +986,7 @@ slk_status knn_mfma(const float* x, int64_t n, int32_t d, int32_t k, int32_t can
   if (R > 0 && split_search)                                                                                    \
     hipLaunchKernelGGL((cand_split_kernel<SPL, (R > 0 ? R : 1)>), dim3(grid), dim3(kBlock), lds, s, xh, xl, nrm, n, \
                        dp, C, c1, cidx, tau, qh, ql, qn, nq, selfi);                                              \
-  else if (n >= kFastKeys)                                                                                      \
+  else if (knn_long_scan(n))                                                                                    \
     hipLaunchKernelGGL((cand_kernel<SPL, R, true>), dim3(grid), dim3(kBlock), lds, s, xh, xl, nrm, n, dp, C, c1,   \
                        cidx, tau, qh, ql, qn, nq, selfi);                                                       \
   else                                                                                                          \

@@ -47,7 +47,7 @@ slk_status slk_tune_lookup(int64_t n, int32_t d, int32_t L, slk_tune_params* out
   slk_knn_opts o;
   slk_knn_opts_default(&o);
   out->knn_exact = knn_takes_exact(n, d, o) ? 1 : 0;
-  out->reserved = 0;
+  out->knn_long_scan = knn_long_scan(n) ? 1 : 0;
   return SLK_OK;
 }
 

@@ -123,6 +123,30 @@ def test_knn_mfma_split_and_plain_search(n, d, slk, torch):
     assert info["rows_fallback"] == 0
 
 
+@pytest.mark.parametrize("d", [24, 72, 200])
+def test_knn_mfma_long_scan(d, slk, torch):
+    """Scans of 2^19 keys or more test each key tile against all of a wave's rows before merging
+    (the library reports the form; 2^19 + 1001 rows, a ragged last tile) at the query-operand
+    widths other than the large-1m workload's: d = 24 (one 32-coordinate chunk), 72 (three) and
+    200 (operands loaded with each chunk).  The certified lists equal the oracle's bit for bit on
+    sampled rows (the first and last 6 and 12 at random), and every row certifies."""
+    n = (1 << 19) + 1001
+    assert slk.tune_lookup(n, d, 20)["knn_long_scan"] == 1
+    inst = gen.gaussian_mixture(n=n, d=d, L=20, K=10, seed=d)
+    g = slk.Graph.build_knn(to_dev(torch, inst.X, torch.float32), k=inst.K, method="mfma")
+    info = g.info()
+    ex = g.export()
+    idx, d2 = ex["knn_idx"].cpu().numpy(), ex["knn_d2"].cpu().numpy()
+    g.close()
+    rng = np.random.default_rng(d)
+    rows = np.unique(np.concatenate([np.arange(6), np.arange(n - 6, n), rng.integers(0, n, 12)]))
+    _say(f"[mfma long scan] n={n} d={d}: certified={info['rows_certified']} fallback={info['rows_fallback']}")
+    oi, od = orc.knn(inst.X, inst.K, rows=rows, block=8)
+    assert np.array_equal(idx[rows], oi)
+    assert np.array_equal(d2[rows], od)
+    assert info["rows_fallback"] == 0
+
+
 def test_graph_from_knn_and_reorder(case, slk, torch):
     inst = case["inst"]
     for reorder in (False, True):
