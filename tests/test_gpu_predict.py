@@ -68,6 +68,27 @@ def test_predict_exact_widths(slk, torch, m):
     check(z[r], lab[r], nn[r], ref, 0.8, 10)
 
 
+def test_predict_long_scan(slk, torch):
+    """40,001 queries (the plain MFMA search, not the split one) into 2^19 + 777 points of 48
+    coordinates: the candidate search tests whole key tiles before merging (long scans), with no
+    point excluded and fewer queries than keys.  Z is a seeded row-stochastic matrix; the oracle
+    checks the first and last 20 queries and 60 drawn at random."""
+    n, m = (1 << 19) + 777, 40001
+    assert slk.tune_lookup(n, 48, 6)["knn_long_scan"] == 1
+    inst = gen.gaussian_mixture(n=n, d=48, L=6, K=10, seed=83)
+    rng = np.random.default_rng(7)
+    Zh = rng.random((n, 6)) + 0.05
+    Zh = (Zh / Zh.sum(axis=1, keepdims=True)).astype(np.float32)
+    x = to_dev(torch, inst.X, torch.float32)
+    Y = queries(inst, m, seed=9)
+    z, lab, nn = slk.predict(x, to_dev(torch, Zh, torch.float32), inst.init_modes, to_dev(torch, Y, torch.float32),
+                             k=10, lam=0.8, sigma2=200.0, method="mfma")
+    rows = np.unique(np.concatenate([np.arange(20), np.arange(m - 20, m), rng.integers(0, m, 60)]))
+    ref = extend.predict(inst.X, Zh.astype(np.float64), inst.init_modes, Y[rows], 10, 200.0, 0.8)
+    r = torch.as_tensor(rows, device="cuda")
+    check(z[r], lab[r], nn[r], ref, 0.8, 10)
+
+
 def test_predict_bf16_points(slk, torch):
     inst = gen.gaussian_mixture(n=1200, d=20, L=6, K=10, seed=61)
     x = to_dev(torch, inst.X, torch.float32)
