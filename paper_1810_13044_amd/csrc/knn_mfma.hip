@@ -216,7 +216,7 @@ __device__ __forceinline__ void static_for(F&& f) {
 
 constexpr int kQT = 128;
 constexpr int kKT = 64;
-constexpr int kBulk = 4;   // more new candidates than this: bulk merge
+constexpr int kBulk = 16;  // more new candidates than this (in a row and tile): bulk merge
 
 // Insert (v, key) into the sorted list of one row (lanes < C hold it); returns the new C-th bound.
 __device__ __forceinline__ float list_insert(float* lv, int* li, int C, float v, int key) {
