@@ -218,24 +218,36 @@ constexpr int kQT = 128;
 constexpr int kKT = 64;
 constexpr int kBulk = 16;  // more new candidates than this (in a row and tile): bulk merge
 
-// Insert (v, key) into the sorted list of one row (lanes < C hold it); returns the new C-th bound.
-__device__ __forceinline__ float list_insert(float* lv, int* li, int C, float v, int key) {
+// Insert (v, key) into the sorted list of one row held in registers: lane i < C holds entry i
+// (cv, ci), lanes from C on hold (+inf, INT32_MAX).  A run of inserts reads the list from LDS once
+// and writes it back once (list_load, list_store): an LDS round trip per insert had made the
+// inserts the bulk of a short scan.
+__device__ __forceinline__ void list_insert(float& cv, int& ci, int C, float v, int key) {
   const int lane = threadIdx.x & 63;
-  const float cv = lane < C ? lv[lane] : INFINITY;
-  const int ci = lane < C ? li[lane] : INT32_MAX;
   const bool before = lane < C && lex_less(cv, ci, v, key);
   const int pos = __popcll(__ballot(before));
   const float pv = __shfl_up(cv, 1);
   const int pi = __shfl_up(ci, 1);
   if (pos < C && lane < C && lane >= pos) {
-    lv[lane] = lane == pos ? v : pv;
-    li[lane] = lane == pos ? key : pi;
+    cv = lane == pos ? v : pv;
+    ci = lane == pos ? key : pi;
   }
-  // the C-th entry after the insert (unchanged when the candidate did not enter)
-  const float last = __shfl(cv, C - 1), prev = __shfl(cv, C - 2 < 0 ? 0 : C - 2);
-  if (pos >= C) return last;
-  if (C == 1) return v;
-  return pos == C - 1 ? v : prev;
+}
+
+__device__ __forceinline__ void list_load(const float* lv, const int* li, int C, float& cv, int& ci) {
+  const int lane = threadIdx.x & 63;
+  cv = lane < C ? lv[lane] : INFINITY;
+  ci = lane < C ? li[lane] : INT32_MAX;
+}
+
+// writes the list back and returns its C-th bound
+__device__ __forceinline__ float list_store(float* lv, int* li, int C, float cv, int ci) {
+  const int lane = threadIdx.x & 63;
+  if (lane < C) {
+    lv[lane] = cv;
+    li[lane] = ci;
+  }
+  return __shfl(cv, C - 1);
 }
 
 // Two waves per SIMD (at most 256 registers per lane): the scan is latency-bound below that.
@@ -363,7 +375,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
       int* li = liw + rho * C;
       float nt;
       if (cnt <= kBulk) {
-        nt = INFINITY;
+        float cv;
+        int ci;
+        list_load(lv, li, C, cv, ci);
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
           uint32_t bb = j == 0 ? b0 : b1;
@@ -372,9 +386,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
             bb &= bb - 1;
             const float v =
                 __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, lb[j]), 32 * h + bit));
-            nt = list_insert(lv, li, C, v, (int)(k0 + 32 * j + bit));
+            list_insert(cv, ci, C, v, (int)(k0 + 32 * j + bit));
           }
         }
+        nt = list_store(lv, li, C, cv, ci);
       } else {
         // the row's 64 bounds of this tile: lanes 0-31 keys k0 .. k0+31, lanes 32-63 the rest
         const int src = 32 * h + col;
@@ -695,7 +710,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
         int* li = liw + rho * C;
         float nt;
         if (cnt <= kBulk) {
-          nt = INFINITY;
+          float cv;
+          int ci;
+          list_load(lv, li, C, cv, ci);
 #pragma unroll
           for (int j = 0; j < 2; ++j) {
             uint32_t bb = j == 0 ? b0 : b1;
@@ -704,9 +721,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
               bb &= bb - 1;
               const float v =
                   __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, lb[j]), 32 * h + bit));
-              nt = list_insert(lv, li, C, v, (int)(k0 + 32 * j + bit));
+              list_insert(cv, ci, C, v, (int)(k0 + 32 * j + bit));
             }
           }
+          nt = list_store(lv, li, C, cv, ci);
         } else {
           const int src = 32 * h + col;
           const float v0 = __shfl(lb[0], src), v1 = __shfl(lb[1], src);
