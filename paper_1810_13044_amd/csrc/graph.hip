@@ -8,6 +8,8 @@
 //   sum_f64           fixed-order FP64 sum (sigma^2 from the kNN squared distances)
 #include "common.h"
 
+#include <type_traits>
+
 #include <float.h>
 #include <math.h>
 
@@ -119,31 +121,43 @@ __device__ __forceinline__ void knn_exact_block(const float* __restrict__ x, int
       if (q < n) {
         const float* xq = x + q * d + c0;
         // the key's coordinates in order; 16 bytes per load where rows allow it (each thread
-        // walks its own row, so single floats re-fetch every cache line from L2 up to 16 times)
-        int j = 0;
-        if (vec4) {
-          for (; j + 4 <= dc; j += 4) {
-            const float4 f4 = *reinterpret_cast<const float4*>(xq + j);
-            const float fv[4] = {f4.x, f4.y, f4.z, f4.w};
+        // walks its own row, so single floats re-fetch every cache line from L2 up to 16 times),
+        // four such loads issued together before their coordinates are used (one at a time, each
+        // load's latency stood between two groups of FP64 updates)
+        auto scan = [&](auto bf_c) __attribute__((always_inline)) {
+          constexpr bool BF = decltype(bf_c)::value;
+          auto coord = [&](float f, int jj) __attribute__((always_inline)) {
+            if (BF) f = bf16_round(f);
+            const double xv = (double)f;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              float f = fv[u];
-              if (bf16) f = bf16_round(f);
-              const double xv = (double)f;
+            for (int i = 0; i < kQB; ++i) acc[i] = sqdist_step(acc[i], qs[i][jj], xv);
+          };
+          int j = 0;
+          if (vec4) {
+            for (; j + 16 <= dc; j += 16) {
+              float4 f4[4];
 #pragma unroll
-              for (int i = 0; i < kQB; ++i) acc[i] = sqdist_step(acc[i], qs[i][j + u], xv);
+              for (int w = 0; w < 4; ++w) f4[w] = *reinterpret_cast<const float4*>(xq + j + 4 * w);
+#pragma unroll
+              for (int w = 0; w < 4; ++w) {
+                coord(f4[w].x, j + 4 * w);
+                coord(f4[w].y, j + 4 * w + 1);
+                coord(f4[w].z, j + 4 * w + 2);
+                coord(f4[w].w, j + 4 * w + 3);
+              }
+            }
+            for (; j + 4 <= dc; j += 4) {
+              const float4 f4 = *reinterpret_cast<const float4*>(xq + j);
+              coord(f4.x, j);
+              coord(f4.y, j + 1);
+              coord(f4.z, j + 2);
+              coord(f4.w, j + 3);
             }
           }
-        }
-        for (; j < dc; ++j) {
-          float f = xq[j];
-          if (bf16) f = bf16_round(f);
-          const double xv = (double)f;
-#pragma unroll
-          for (int i = 0; i < kQB; ++i) {
-            acc[i] = sqdist_step(acc[i], qs[i][j], xv);
-          }
-        }
+          for (; j < dc; ++j) coord(xq[j], j);
+        };
+        if (bf16) scan(std::true_type{});
+        else scan(std::false_type{});
       }
     }
     // filter against the current k-th best of each query
