@@ -100,7 +100,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
       }
   }
 
-  // staging of the point chunks: thread tid moves point tid / 4, 8 coordinates at (tid % 4) * 8
+  // staging of the point chunks: thread tid moves point spt (below), 8 coordinates at (tid % 4) * 8
   // point rows of a wave's lanes: 4 (l / 4 % 4) + l / 16, so that the lanes an LDS write serves at
   // once cover rows 4 apart, whose 80-byte rows fall on distinct banks (as in the kNN staging)
   const int spt = 16 * (tid >> 6) + 4 * ((tid >> 2) & 3) + ((tid >> 4) & 3), spiece = (tid & 3) * 8;

@@ -304,8 +304,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
         al[c][s2] = SPLIT ? gload8(apl + kDK * c + 16 * s2) : ah[c][s2];
       }
   }
-  // staging: thread tid moves keys tid / 4 + 64 t (t < P), 8 coordinates at (tid % 4) * 8, hi
-  // and lo, through two register slots (loads in flight two chunks ahead) into the LDS ring
+  // staging: thread tid moves keys skey + 64 t (t < P), 8 coordinates at (tid % 4) * 8, hi and
+  // lo, through two register slots (loads in flight two chunks ahead) into the LDS ring
   // key rows of a wave's lanes: 4 (l / 4 % 4) + l / 16 (the four pieces of a row in four adjacent
   // lanes), so that the 8 (or 16) lanes an LDS write serves at once cover rows 4 (or 12) apart,
   // whose 80-byte rows fall on distinct banks; rows in order had every write two-way conflicted
@@ -357,8 +357,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   float nk[NJ];
 #pragma unroll
   for (int j = 0; j < NJ; ++j) nk[j] = 0.f;
-  // lower bounds of tile kt (column tiles j0, j0 + 1 of the stage); rows with a bound below their
-  // C-th bound merge (wave-local)
   // Merge of row r (accumulator entry r of this lane; one row per lane half) with the tile's
   // bounds lb (keys k0 + 32 j + col): the candidates below the row's C-th bound tr enter its list;
   // returns the row's new C-th bound (for this lane's half).
