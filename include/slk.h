@@ -527,7 +527,7 @@ typedef struct {
   int32_t knn_exact_width;  /* queries per work-group of the exact kNN over n rows              */
   int32_t knn_exact;        /* 1 if the AUTO kNN method takes the exact search for (n, d)        */
   int32_t knn_long_scan;    /* 1 if the MFMA candidate search over n keys tests each key tile
-                               against all of a wave's rows before merging (n >= 2^19)            */
+                               against all of a wave's rows before merging (n >= 393,216)         */
 } slk_tune_params;
 
 /* The tile shapes a problem of n points in d dimensions with L clusters gets (host output). */

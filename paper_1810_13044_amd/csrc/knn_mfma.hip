@@ -595,10 +595,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
 constexpr int kQS = 64;   // query rows per work-group of the split search
 constexpr int64_t kSplitBelow = 256;   // split while cand_kernel would have fewer work-groups (one per CU)
 // Key counts from which the plain search tests all rows of a tile before merging (the FAST
-// epilogue of cand_kernel).  Measured against merging row by row: 1,000,000 keys (d = 128)
-// 900 -> 825 ms and 400,000 keys (d = 64) 139 -> 103 ms, but 300,000 keys (d = 128) 104 -> 114 ms
-// and 60,000 keys (d = 64) 6.1 -> 8.6 ms: in shorter scans most tiles still improve some row.
-constexpr int64_t kFastKeys = 1 << 19;
+// epilogue of cand_kernel).  Measured against merging row by row (ms, row by row -> tile test):
+// 1,000,000 keys (d = 128) 900 -> 825, 400,000 keys 116 -> 97 (d = 64), 134 -> 119 (d = 96),
+// 510 -> 509 (d = 200); but 300,000 keys 95 -> 108 (d = 128), 68 -> 73 (d = 32), 270,000 keys
+// (d = 64) 66 -> 75: in shorter scans most tiles still improve some row.
+constexpr int64_t kFastKeys = 3 << 17;   // 393,216
 
 template <bool SPLIT, int RES>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void cand_split_kernel(

@@ -156,9 +156,9 @@ def test_exact_knn_width_rule(n, d, width):
     assert t["wave_steps"] in (1, 2, 4, 8)
 
 
-@pytest.mark.parametrize("n,long_scan", [(524287, 0), (524288, 1), (2000, 0), (1000000, 1)])
+@pytest.mark.parametrize("n,long_scan", [(393215, 0), (393216, 1), (2000, 0), (1000000, 1)])
 def test_knn_long_scan_rule(n, long_scan):
     """The MFMA candidate search tests each key tile against all of a wave's rows before merging
-    from 2^19 keys on (host lookup, no GPU); the GPU tests build graphs on both sides."""
+    from 393,216 keys on (host lookup, no GPU); the GPU tests build graphs on both sides."""
     import paper_1810_13044_amd as slk
     assert slk.tune_lookup(n, 64, 10)["knn_long_scan"] == long_scan

@@ -125,7 +125,7 @@ def test_knn_mfma_split_and_plain_search(n, d, slk, torch):
 
 @pytest.mark.parametrize("d", [24, 72, 200])
 def test_knn_mfma_long_scan(d, slk, torch):
-    """Scans of 2^19 keys or more test each key tile against all of a wave's rows before merging
+    """Scans of 393,216 keys or more test each key tile against all of a wave's rows before merging
     (the library reports the form; 2^19 + 1001 rows, a ragged last tile) at the query-operand
     widths other than the large-1m workload's: d = 24 (one 32-coordinate chunk), 72 (three) and
     200 (operands loaded with each chunk).  The certified lists equal the oracle's bit for bit on
