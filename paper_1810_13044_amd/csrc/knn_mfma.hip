@@ -222,16 +222,20 @@ constexpr int kBulk = 16;  // more new candidates than this (in a row and tile):
 // (cv, ci), lanes from C on hold (+inf, INT32_MAX).  A run of inserts reads the list from LDS once
 // and writes it back once (list_load, list_store): an LDS round trip per insert had made the
 // inserts the bulk of a short scan.
+// Lane i gets lane i - 1's value (lane 0 its own): the DPP whole-wave shift (wave_shr:1), one
+// VALU operation; __shfl_up went through the LDS crossbar (ds_bpermute) and its latency.
+__device__ __forceinline__ int wave_shr1(int x) { return __builtin_amdgcn_update_dpp(x, x, 0x138, 0xf, 0xf, false); }
+
 __device__ __forceinline__ void list_insert(float& cv, int& ci, int C, float v, int key) {
   const int lane = threadIdx.x & 63;
-  const bool before = lane < C && lex_less(cv, ci, v, key);
+  // (cv, ci) < (v, key), without branches
+  const bool before = (lane < C) & ((cv < v) | ((cv == v) & (ci < key)));
   const int pos = __popcll(__ballot(before));
-  const float pv = __shfl_up(cv, 1);
-  const int pi = __shfl_up(ci, 1);
-  if (pos < C && lane < C && lane >= pos) {
-    cv = lane == pos ? v : pv;
-    ci = lane == pos ? key : pi;
-  }
+  const float pv = __builtin_bit_cast(float, wave_shr1(__builtin_bit_cast(int, cv)));
+  const int pi = wave_shr1(ci);
+  const bool move = (pos < C) & (lane < C) & (lane >= pos);
+  cv = move ? (lane == pos ? v : pv) : cv;
+  ci = move ? (lane == pos ? key : pi) : ci;
 }
 
 __device__ __forceinline__ void list_load(const float* lv, const int* li, int C, float& cv, int& ci) {
