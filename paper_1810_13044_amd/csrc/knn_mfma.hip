@@ -216,7 +216,13 @@ __device__ __forceinline__ void static_for(F&& f) {
 
 constexpr int kQT = 128;
 constexpr int kKT = 64;
-constexpr int kBulk = 16;  // more new candidates than this (in a row and tile): bulk merge
+// More new candidates than this (of a row in a tile) go through the 128-wide bitonic merge; fewer
+// are inserted one by one.  Measured with the inserts on DPP shifts (64 = always insert, a tile
+// holding 64 keys): always inserting is fastest for d <= 96 and for the long-scan form; for the
+// row-by-row form at 97 <= d <= 128 it was slower (300,000 x 128: 93 -> 108 ms), 16 stays there;
+// above d = 128, 32.
+template <int RES, bool FAST>
+constexpr int bulk_above() { return RES == 0 ? 32 : (RES == 4 && !FAST) ? 16 : 64; }
 
 // Insert (v, key) into the sorted list of one row held in registers: lane i < C holds entry i
 // (cv, ci), lanes from C on hold (+inf, INT32_MAX).  A run of inserts reads the list from LDS once
@@ -376,7 +382,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
       float* lv = lvw + rho * C;
       int* li = liw + rho * C;
       float nt;
-      if (cnt <= kBulk) {
+      if (cnt <= bulk_above<RES, FAST>()) {
         float cv;
         int ci;
         list_load(lv, li, C, cv, ci);
@@ -712,7 +718,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
         float* lv = lvw + rho * C;
         int* li = liw + rho * C;
         float nt;
-        if (cnt <= kBulk) {
+        if (cnt <= bulk_above<RES, false>()) {
           float cv;
           int ci;
           list_load(lv, li, C, cv, ci);
