@@ -99,6 +99,26 @@ __device__ __forceinline__ void knn_exact_block(const float* __restrict__ x, int
   if (tid < kQB) bcnt[tid] = 0;
   __syncthreads();
 
+  // the queries' coordinates c0 .. c0 + kQDc - 1 into qs (zeros past d and past the last query)
+  auto stage_queries = [&](int c0, int dc) __attribute__((always_inline)) {
+    for (int e = tid; e < kQB * kQDc; e += kBlock) {
+      const int i = e / kQDc, j = e % kQDc;
+      double v = 0.0;
+      if (i < nq && j < dc) {
+        float f = qsrc[qrow[i] * d + c0 + j];
+        if (bf16) f = bf16_round(f);
+        v = (double)f;
+      }
+      qs[i][j] = v;
+    }
+  };
+  // with one chunk (d <= kQDc: every served job's width) the queries are staged once for all key
+  // blocks; re-staging them for each block had cost two barriers and a round of loads per block
+  const bool one_chunk = d <= kQDc;
+  if (one_chunk) {
+    stage_queries(0, d);
+    __syncthreads();
+  }
   for (int64_t k0 = 0; k0 < n; k0 += kBlock) {
     const int64_t q = k0 + tid;
     double acc[kQB];
@@ -106,18 +126,11 @@ __device__ __forceinline__ void knn_exact_block(const float* __restrict__ x, int
     for (int i = 0; i < kQB; ++i) acc[i] = 0.0;
     for (int c0 = 0; c0 < d; c0 += kQDc) {
       const int dc = min(kQDc, d - c0);
-      __syncthreads();
-      for (int e = tid; e < kQB * kQDc; e += kBlock) {
-        const int i = e / kQDc, j = e % kQDc;
-        double v = 0.0;
-        if (i < nq && j < dc) {
-          float f = qsrc[qrow[i] * d + c0 + j];
-          if (bf16) f = bf16_round(f);
-          v = (double)f;
-        }
-        qs[i][j] = v;
+      if (!one_chunk) {
+        __syncthreads();
+        stage_queries(c0, dc);
+        __syncthreads();
       }
-      __syncthreads();
       if (q < n) {
         const float* xq = x + q * d + c0;
         // the key's coordinates in order; 16 bytes per load where rows allow it (each thread
@@ -196,6 +209,9 @@ __device__ __forceinline__ void knn_exact_block(const float* __restrict__ x, int
       if (tid == 0) bcnt[i] = 0;
       __syncthreads();
     }
+    // the next block's filter writes bcnt, bd and bq: every thread must be past this block's
+    // merges first (with several chunks the staging barrier at the top of the block does this)
+    if (one_chunk) __syncthreads();
   }
   for (int e = tid; e < nq * k; e += kBlock) {
     const int i = e / k, j = e % k;
