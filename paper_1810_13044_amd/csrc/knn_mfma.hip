@@ -142,6 +142,25 @@ __global__ __launch_bounds__(kBlock) void split_kernel(const float* __restrict__
 // ------------------------------------------------------------------------------------------
 // 2. candidate search on MFMA
 // ------------------------------------------------------------------------------------------
+// The value of lane (lane ^ stride): DPP within a row for strides 1 and 2 (quad permutations) and
+// 4 and 8 (the row shifted up or down, chosen per lane); the LDS crossbar (__shfl_xor) beyond.
+// stride is a constant wherever this is inlined into an unrolled loop.
+__device__ __forceinline__ int xor_lane(int x, int stride) {
+  if (stride == 1) return __builtin_amdgcn_update_dpp(x, x, 0xB1, 0xf, 0xf, false);   // quad_perm [1,0,3,2]
+  if (stride == 2) return __builtin_amdgcn_update_dpp(x, x, 0x4E, 0xf, 0xf, false);   // quad_perm [2,3,0,1]
+  if (stride == 4) {
+    const int up = __builtin_amdgcn_update_dpp(x, x, 0x104, 0xf, 0xf, false);  // row_shl:4, lane + 4
+    const int dn = __builtin_amdgcn_update_dpp(x, x, 0x114, 0xf, 0xf, false);  // row_shr:4, lane - 4
+    return (threadIdx.x & 4) ? dn : up;
+  }
+  if (stride == 8) {
+    const int up = __builtin_amdgcn_update_dpp(x, x, 0x108, 0xf, 0xf, false);  // row_shl:8, lane + 8
+    const int dn = __builtin_amdgcn_update_dpp(x, x, 0x118, 0xf, 0xf, false);  // row_shr:8, lane - 8
+    return (threadIdx.x & 8) ? dn : up;
+  }
+  return __shfl_xor(x, stride);
+}
+
 // 128-element bitonic sort across a wave, two (value, index) pairs per lane at positions
 // lane and lane + 64; ascending.
 __device__ __forceinline__ void wave_sort128(float (&v)[2], int (&ix)[2]) {
@@ -164,8 +183,8 @@ __device__ __forceinline__ void wave_sort128(float (&v)[2], int (&ix)[2]) {
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
           const int e = lane + 64 * s;
-          const float ov = __shfl_xor(v[s], stride);
-          const int oi = __shfl_xor(ix[s], stride);
+          const float ov = __builtin_bit_cast(float, xor_lane(__builtin_bit_cast(int, v[s]), stride));
+          const int oi = xor_lane(ix[s], stride);
           const bool lower = (e & stride) == 0;
           const bool asc = (e & size) == 0;
           const bool other_smaller = lex_less(ov, oi, v[s], ix[s]);
