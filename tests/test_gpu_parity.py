@@ -147,6 +147,28 @@ def test_knn_mfma_long_scan(d, slk, torch):
     assert info["rows_fallback"] == 0
 
 
+def _bfs_order(rp, ci):
+    """Breadth-first order of a CSR graph: roots in increasing index order, each row's neighbours
+    in CSR order (the locality order the library documents for reordered graphs)."""
+    n = len(rp) - 1
+    seen = np.zeros(n, bool)
+    order = []
+    for root in range(n):
+        if seen[root]:
+            continue
+        seen[root] = True
+        head = len(order)
+        order.append(root)
+        while head < len(order):
+            v = order[head]
+            head += 1
+            for u in ci[rp[v]:rp[v + 1]]:
+                if not seen[u]:
+                    seen[u] = True
+                    order.append(int(u))
+    return np.asarray(order, np.int64)
+
+
 def test_graph_from_knn_and_reorder(case, slk, torch):
     inst = case["inst"]
     for reorder in (False, True):
@@ -156,7 +178,8 @@ def test_graph_from_knn_and_reorder(case, slk, torch):
         assert np.array_equal(ex["row_ptr"].cpu().numpy(), case["rp"])
         assert np.array_equal(ex["col_idx"].cpu().numpy(), case["ci"])
         perm = ex["perm"].cpu().numpy()
-        assert np.array_equal(np.sort(perm), np.arange(inst.N))
+        want = _bfs_order(case["rp"], case["ci"]) if reorder else np.arange(inst.N)
+        assert np.array_equal(perm, want)
         assert g.info()["reordered"] == int(reorder)
 
 
