@@ -181,6 +181,14 @@ def test_graph_from_knn_and_reorder(case, slk, torch):
         want = _bfs_order(case["rp"], case["ci"]) if reorder else np.arange(inst.N)
         assert np.array_equal(perm, want)
         assert g.info()["reordered"] == int(reorder)
+        # the caller's CSR, imported as it is: the same order
+        gc = slk.Graph.from_csr(to_dev(torch, case["rp"], torch.int32), to_dev(torch, case["ci"], torch.int32),
+                                sigma2=case["s2"], reorder=reorder)
+        ec = gc.export()
+        assert np.array_equal(ec["row_ptr"].cpu().numpy(), case["rp"])
+        assert np.array_equal(ec["col_idx"].cpu().numpy(), case["ci"])
+        assert np.array_equal(ec["perm"].cpu().numpy(), want)
+        assert gc.info()["reordered"] == int(reorder)
 
 
 # ------------------------------------------------------------------- a4: unary
@@ -483,9 +491,12 @@ def test_lambda_zero_and_empty_graph(slk, torch):
     assert np.array_equal(r0["labels"].cpu().numpy(), nearest)
     assert r0["result"]["inner_iters_last"] == 2
     rp0 = torch.zeros(inst.N + 1, dtype=torch.int32, device="cuda")
-    ge = slk.Graph.from_csr(rp0, torch.zeros(0, dtype=torch.int32, device="cuda"), sigma2=s2)
-    r1 = slk.assign(x, ge, inst.init_modes, lam=3.0)
-    assert torch.equal(r0["z"], r1["z"])
+    for reorder in (False, True):
+        ge = slk.Graph.from_csr(rp0, torch.zeros(0, dtype=torch.int32, device="cuda"), sigma2=s2, reorder=reorder)
+        # without edges every row is its own component: the breadth-first order is the identity
+        assert np.array_equal(ge.export()["perm"].cpu().numpy(), np.arange(inst.N))
+        r1 = slk.assign(x, ge, inst.init_modes, lam=3.0)
+        assert torch.equal(r0["z"], r1["z"])
 
 
 def test_deterministic(slk, torch):
